@@ -1,0 +1,55 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of nh_oracle.c (a dropped term, a wrong
+sign, a wrong power, a transposed operand, a wrong tableau entry), builds it
+into a temporary library on the CPU, and runs the pin suite against it through
+NH_ORACLE_LIB.  The suite must fail for every mutant.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "nh_oracle.c")
+
+MUTANTS = {
+    "force_sign": ("dY[2] = -g * x;", "dY[2] = g * x;"),
+    "force_transposed": ("dY[3] = -g * y;", "dY[3] = -g * x;"),
+    "drift_power": ("A = opz * opz / H;", "A = opz / H;"),
+    "kick_factor": ("B = nho_kappa(m, z) * nho_G() * opz / H;", "B = nho_kappa(m, z) * nho_G() / H;"),
+    "no_compensation": ("if (r < rv) return Mz * (nho_nfw_I(r / s) / nho_nfw_I(c) - comp);",
+                        "if (r < rv) return Mz * (nho_nfw_I(r / s) / nho_nfw_I(c));"),
+    "shell_sign": ("return Mz * (1.0 - comp);", "return Mz * (1.0 + comp);"),
+    "nfw_I_term": ("return log1p(q) - q / (1.0 + q);", "return log1p(q) - q;"),
+    "series_sign": ("sum += (k % 2 == 0) ? term : -term;", "sum += term;"),
+    "hubble_power": ("sqrt(m->Omega_m * opz * opz * opz + m->Omega_L)", "sqrt(m->Omega_m * opz * opz + m->Omega_L)"),
+    "lagrangian_radius": ("double fac = 2.0 * nho_G() / (m->Omega_m * H0k * H0k);",
+                          "double fac = 3.0 * nho_G() / (m->Omega_m * H0k * H0k);"),
+    "truncation_image": ("*rv = (*R / c200) * (1.0 + z);", "*rv = (*R / c200);"),
+    "rk4_weight": ("(k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i])", "(k1[i] + 2.0 * k2[i] + k3[i] + 2.0 * k4[i])"),
+    "rk4_stage_time": ("nho_rhs(m, u1, T, k3);", "nho_rhs(m, u0, T, k3);"),
+    "dp_tableau": ("{44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0},", "{44.0 / 45.0, -56.0 / 15.0, 32.0 / 8.0, 0, 0, 0},"),
+    "dp_weight": ("static const double DP_B[7] = {35.0 / 384.0,", "static const double DP_B[7] = {36.0 / 384.0,"),
+    "dp_error_weight": ("-92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};", "-92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 30.0};"),
+    "mass_xi": ("double xi = (m->z_form - z) / m->z_form;", "double xi = (m->z_form - z) / (m->z_form + 1.0);"),
+    "conc_power": ("return m->c0 * pow(1.0 + z, -m->conc_gamma);", "return m->c0 * pow(1.0 + z, m->conc_gamma);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "mut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-o", str(so), str(mut), "-lm"], check=True)
+    env = dict(os.environ, NH_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
