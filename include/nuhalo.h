@@ -1,0 +1,278 @@
+/*
+ * nuhalo.h -- C ABI of libnuhalo.so: relic overdensity profiles n(r)/nbar
+ * around a spherically symmetric, time-evolving NFW halo by backward N-1-body
+ * integration and a Liouville momentum-space quadrature, on one MI355X (gfx950).
+ *
+ * Method: Worku, Sabti & Kamionkowski, arXiv:2410.08267.
+ *   - background and equations of motion: Sec. II.A, Eq. (eoms)
+ *   - halo model: Sec. II.B, Eqs. (rhototal), (nfw); enclosed mass App. A
+ *   - backward integration and Liouville map: Sec. II.C
+ *   - momentum-space quadrature: Eqs. (density_integral), (localdensity) and
+ *     the background density that follows them
+ *   - grids and mass-independence of the orbits: Sec. II.D
+ *   - halo-growth variants and G(z): Sec. IV.A, IV.B
+ *
+ * Conventions for every entry point:
+ *   - Return value: NH_OK (0) or a negative NH_E* code.  No exception or
+ *     longjmp crosses this boundary.  nh_last_error(ctx) holds a message for
+ *     the last failing call on that context (thread-local per context use).
+ *   - Host input arrays are read (copied) before the call returns; the caller
+ *     may free or reuse them afterwards.
+ *   - Output buffers belong to the caller.  "host" buffers are ordinary host
+ *     memory; "device" buffers are HIP device allocations on the context's
+ *     device (for example a torch tensor's data_ptr()).
+ *   - Streams are hipStream_t values passed as void*; NULL is the null stream.
+ *   - Units: radii in comoving kpc, velocities in km/s, masses in Msun,
+ *     H0 in km/s/Mpc, temperatures in K, relic mass in eV.
+ *   - All floating-point inputs must be finite.
+ */
+#ifndef NUHALO_H
+#define NUHALO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define NH_OK          0
+#define NH_EINVAL     (-1)  /* invalid request or argument; nothing was launched */
+#define NH_ENOMEM     (-2)  /* host or device allocation failed */
+#define NH_EDEVICE    (-3)  /* a HIP call failed; nh_last_error has HIP's text */
+#define NH_ESTEPS     (-4)  /* some trajectories hit max_steps or a step underflow;
+                               the profile is still written, see nh_stats */
+#define NH_ENONFINITE (-5)  /* a trajectory state became non-finite; profile written */
+#define NH_EBUSY      (-6)  /* serving: the request does not fit the free budget now */
+#define NH_ENOTREADY  (-7)  /* serving: the ticket has not completed yet */
+#define NH_ENOTFOUND  (-8)  /* serving: unknown or already collected ticket */
+#define NH_ECANCELED  (-9)  /* serving: the ticket was cancelled */
+
+/* ---- request ---------------------------------------------------------- */
+
+/* Flat FRW background, H(z) = H0 [Om (1+z)^3 + OL]^(1/2) (Sec. II.A).
+ * |Omega_m + Omega_L - 1| must be <= 1e-12 and Omega_m > 0. */
+typedef struct {
+    double H0_km_s_Mpc;
+    double Omega_m;
+    double Omega_L;
+} nh_cosmology;
+
+/* Halo mass history M(z) (Sec. II.B, IV.A). */
+enum {
+    NH_MASS_ZERO        = 0,  /* no halo: free streaming, n/nbar = 1 */
+    NH_MASS_PAPER       = 1,  /* M0 * xi(z)^alpha, xi = clamp((z_form - z)/z_form, 0, 1) */
+    NH_MASS_EXPONENTIAL = 2   /* M0 * exp(-beta z) */
+};
+/* Concentration history c(z). */
+enum {
+    NH_CONC_CONSTANT = 0,     /* c0 */
+    NH_CONC_POWER    = 1      /* c0 * (1+z)^(-gamma) */
+};
+/* Modulation of Newton's constant, G -> kappa(z) G (Sec. IV.B). */
+enum {
+    NH_KAPPA_NONE     = 0,    /* kappa = 1 */
+    NH_KAPPA_LOG      = 1,    /* 1 + a ln(1+z) */
+    NH_KAPPA_PAPER    = 2,    /* 1 + a [z/(1+z)]^b */
+    NH_KAPPA_CONSTANT = 3     /* a */
+};
+/* Halo geometry. */
+enum {
+    NH_GEOM_PAPER    = 0,     /* Sec. II.B: R from M(0) via M = (4 pi/3) R^3 rhobar_m0;
+                                 fixed physical r200 = R / 200^(1/3); comoving truncation
+                                 radius r200 (1+z); scale radius r200 (1+z) / c(z) */
+    NH_GEOM_DELTA200 = 1      /* R(z) from M(z); truncation radius R(z)/200^(1/3) comoving */
+};
+
+/* The halo.  With compensated = 1 (Sec. II.B) the enclosed mass perturbation is
+ *   M(z) [I(r/s)/I(c) - (r/R)^3]  inside the truncation radius,
+ *   M(z) [1 - (r/R)^3]            out to R,  0 beyond,
+ * with I(q) = ln(1+q) - q/(1+q); compensated = 0 drops the (r/R)^3 terms and
+ * the cutoff (plain NFW inside, point mass outside). */
+typedef struct {
+    int    mass_kind;    /* NH_MASS_* */
+    double M0_Msun;      /* > 0 unless NH_MASS_ZERO */
+    double mass_alpha;   /* NH_MASS_PAPER: exponent of xi (1 in the base model) */
+    double z_form;       /* NH_MASS_PAPER: z_i, 200^(1/3) - 1 in the base model; > 0 */
+    double mass_beta;    /* NH_MASS_EXPONENTIAL: rate */
+    int    conc_kind;    /* NH_CONC_* */
+    double c0;           /* > 0 */
+    double conc_gamma;
+    int    kappa_kind;   /* NH_KAPPA_* */
+    double kappa_a;
+    double kappa_b;
+    int    geometry;     /* NH_GEOM_*; NH_GEOM_PAPER needs z_end <= 200^(1/3) - 1 */
+    int    compensated;  /* 1 (paper) or 0 */
+} nh_halo;
+
+/* Initial (pre-halo) phase-space distribution of the relic, y = P / (k_B T). */
+enum {
+    NH_F0_FERMI_DIRAC = 0,    /* 1 / (1 + e^y)  (Sec. II.C) */
+    NH_F0_FREEZE_IN   = 1     /* y^(-1/2) e^(-y) (Sec. IV.B; normalisation cancels) */
+};
+typedef struct {
+    int    kind;             /* NH_F0_* */
+    double T_K;              /* > 0; 1.95 K for the neutrino background */
+} nh_f0;
+
+/* Grid.  Trajectory t = (k * n_y + j) * n_mu + l starts at x0 = (r_k, 0) with
+ * v0 = V_j (mu_l, sqrt(1 - mu_l^2)), V_j = y_j k_B T c / m (Sec. II.C, II.D).
+ * r_kpc > 0; y > 0 strictly ascending (n_y >= 2); |mu| < 1.
+ * mu == NULL: n_mu Gauss-Legendre nodes and weights on [-1, 1] (w_mu ignored).
+ * The |p| weights are y_j^3 dlny_j, trapezoid in ln y with half weights at the ends. */
+typedef struct {
+    int           n_r;
+    const double *r_kpc;     /* host, n_r */
+    int           n_y;
+    const double *y;         /* host, n_y */
+    int           n_mu;
+    const double *mu;        /* host, n_mu, or NULL */
+    const double *w_mu;      /* host, n_mu, required when mu != NULL */
+} nh_grid;
+
+/* Integrator, in u = ln a from 0 (z = 0) down to -ln(1 + z_end). */
+enum {
+    NH_RK4    = 0,           /* classical RK4, n_steps equal steps */
+    NH_DOPRI5 = 1            /* Dormand-Prince 5(4), adaptive */
+};
+enum {
+    NH_FP64  = 0,            /* FP64 state and arithmetic */
+    NH_FP32C = 1             /* FP32 state with compensated position / time sums;
+                                FP64 tables, promoted steps and quadrature */
+};
+/* Dormand-Prince step control: err = RMS over (x, y, vx, vy) of E_i / sc_i with
+ * sc = atol + rtol * max(|.|_n, |.|_{n+1}) (Euclidean norm of the position pair
+ * for x, y and of the velocity pair for vx, vy); accept err <= 1; next step
+ * h * min(5, max(0.2, 0.9 err^(-1/5))), capped at 1x right after a rejection;
+ * the last step lands on u_end. */
+typedef struct {
+    int       method;        /* NH_RK4 | NH_DOPRI5 */
+    int       n_steps;       /* NH_RK4: >= 1 */
+    double    rtol;          /* NH_DOPRI5: > 0 */
+    double    atol_x;        /* kpc; <= 0 means rtol * 1 kpc */
+    double    atol_v;        /* km/s; <= 0 means rtol * 1 km/s */
+    double    h0;            /* first trial step in u; 0 means -1e-3 */
+    long long max_steps;     /* attempted-step budget per trajectory; <= 0 means 1e6 */
+    double    z_end;         /* > 0 */
+    int       precision;     /* NH_FP64 | NH_FP32C (NH_FP32C needs NH_DOPRI5) */
+} nh_integrator;
+
+typedef struct {
+    nh_cosmology  cosmo;
+    nh_halo       halo;
+    double        m_eV;      /* relic mass, > 0 */
+    nh_f0         f0;
+    nh_grid       grid;
+    nh_integrator integ;
+} nh_request;
+
+/* Per-solve statistics. */
+typedef struct {
+    long long n_traj;              /* trajectories in the request */
+    long long accepted_steps;      /* sum over trajectories */
+    long long rejected_steps;      /* sum over trajectories */
+    long long max_steps_one_traj;  /* largest accepted+rejected count of one trajectory */
+    long long n_failed;            /* trajectories with a non-OK status */
+    long long fp64_steps;          /* NH_FP32C: attempted steps run in FP64 */
+    long long free_exits;          /* trajectories finished by the exact free-streaming exit */
+    double    kernel_ms;           /* device time of the trajectory kernel(s) */
+} nh_stats;
+
+typedef struct nh_context nh_context;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  The context owns device tables,
+ * work buffers and the serving queue; it allocates lazily and grows as
+ * requests need.  One host thread at a time may use nh_solve / nh_solve_async
+ * on a context. */
+int nh_context_create(int device, nh_context **out);
+
+/* Wait for outstanding work, free everything the context owns.  NULL is a no-op. */
+int nh_context_destroy(nh_context *ctx);
+
+/* Device memory (bytes) a request needs in the context beyond what every
+ * request shares: tables, grids, per-trajectory results.  Validates the
+ * request (NH_EINVAL).  Needs no GPU. */
+int nh_footprint_bytes(const nh_request *req, size_t *bytes);
+
+/* ---- plain solve ------------------------------------------------------ */
+
+/* Compute n/nbar for one request and wait for it.
+ * n_over_nbar: host, req->grid.n_r doubles, written in radius order.
+ * stats: may be NULL.
+ * Returns NH_OK, NH_ESTEPS / NH_ENONFINITE (profile written, failures counted
+ * in stats), or an error with nothing written. */
+int nh_solve(nh_context *ctx, const nh_request *req, double *n_over_nbar, nh_stats *stats);
+
+/* Enqueue one request on `stream` without waiting.
+ * d_out:   device, req->grid.n_r doubles, receives n/nbar.
+ * d_ratio: device, n_traj doubles, or NULL; receives P_i/P0 = |v(z_end)|/|v0|
+ *          of every trajectory in index order t = (k*n_y + j)*n_mu + l.
+ * The context's work buffers are reused by the next call on the same context,
+ * which first waits for this one.  nh_last_stats() waits and reports it. */
+int nh_solve_async(nh_context *ctx, const nh_request *req, double *d_out, double *d_ratio,
+                   void *stream);
+
+/* Wait for the last nh_solve_async on this context and return its statistics
+ * and status (NH_OK, NH_ESTEPS or NH_ENONFINITE). */
+int nh_last_stats(nh_context *ctx, nh_stats *stats);
+
+/* ---- batched solve ---------------------------------------------------- */
+
+/* Solve n_req heterogeneous requests in one persistent launch.
+ * d_out: device, sum of the requests' n_r doubles, profiles concatenated in
+ * request order.  All requests must share method and precision.
+ * stats: host array of n_req entries, or NULL.  Waits for completion. */
+int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d_out,
+                   nh_stats *stats, void *stream);
+
+/* ---- serving (continuous batching) ------------------------------------ */
+
+/* Device-memory budget (bytes) for admitted serving requests; 0 = 80 % of
+ * free device memory at the first submit.  Needs no GPU when bytes > 0. */
+int nh_serve_set_budget(nh_context *ctx, size_t bytes);
+
+/* Admit a request into the running batch, or NH_EBUSY if its footprint does
+ * not fit the free budget right now (nothing is queued then).
+ * ticket: receives an id for nh_poll / nh_cancel. */
+int nh_submit(nh_context *ctx, const nh_request *req, uint64_t *ticket);
+
+/* Collect a finished ticket.  out: host, n_r doubles.  stats: may be NULL.
+ * NH_ENOTREADY while the ticket runs; after a successful poll the ticket is gone. */
+int nh_poll(nh_context *ctx, uint64_t ticket, double *out, nh_stats *stats);
+
+/* Cancel a ticket; its trajectories are dropped from the batch and its memory
+ * returns to the budget.  Polling it afterwards returns NH_ECANCELED once. */
+int nh_cancel(nh_context *ctx, uint64_t ticket);
+
+/* ---- host-side helpers (need no GPU) --------------------------------------- */
+
+/* The n-point Gauss-Legendre rule on [-1, 1] that a grid with mu == NULL uses
+ * (Eq. density_integral integrates mu = cos psi over [-1, 1]).
+ * x, w: host, n doubles each; nodes ascending.  1 <= n <= 4096. */
+int nh_gauss_legendre(int n, double *x, double *w);
+
+/* The u-dependent coefficients of the equations of motion as the library
+ * tabulates them on the host in FP64, at n points u (u = ln a, in
+ * [-ln(1+z_end), 0]).  out: host, 6*n doubles, row i = (A, K, Kc, 1/s, c, R):
+ *   dx/du = A v,   dv/du = -[K I(min(r/s, c)) / r^3 - Kc] x  for r < R, else 0,
+ * A = (1+z)^2/H, K = kappa G (1+z) M / (H I(c)), Kc = kappa G (1+z) M / (H R^3),
+ * s the comoving NFW scale radius, R the compensation radius (1e300 when
+ * uncompensated).  Sec. II.A Eq. (eoms), Sec. II.B, App. A.  Validates req. */
+int nh_coefficients(const nh_request *req, int n, const double *u, double *out);
+
+/* ---- diagnostics ------------------------------------------------------- */
+
+const char *nh_strerror(int code);
+const char *nh_last_error(const nh_context *ctx);
+
+/* Library version string. */
+const char *nh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUHALO_H */

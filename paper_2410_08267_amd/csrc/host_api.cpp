@@ -1,0 +1,411 @@
+// C ABI of libnuhalo: context, plain solve, statistics, diagnostics.
+//
+// Host work per request (all FP64): validation, the coefficient table of the
+// equations of motion, the quadrature weights and Gauss-Legendre nodes.  They
+// are packed into one pinned staging buffer and copied to the device in one
+// transfer; everything after that runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "nh_context.h"
+
+namespace nh {
+
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
+hipError_t launch_free_all(long long n, const TrajOut &o, hipStream_t s);
+hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, hipStream_t s);
+int dp5_f64_blocks_per_cu(size_t lds_bytes);
+hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                          unsigned long long *counter, int grid, hipStream_t s);
+int dp5_f32c_blocks_per_cu(size_t lds_bytes);
+hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                           unsigned long long *counter, int grid, hipStream_t s);
+hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,
+                                 int f0_kind, double *out, hipStream_t s);
+hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long *stats,
+                               hipStream_t s);
+
+thread_local char g_err[512] = "";
+
+int set_err(nh_context *ctx, int code, const char *fmt, ...)
+{
+    char *dst = ctx ? ctx->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(dst, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int ensure_dev(nh_context *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.cap) return NH_OK;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return set_err(ctx, NH_EDEVICE, "hipFree: %s", hipGetErrorString(e));
+    }
+    size_t cap = std::max(bytes, (size_t)4096);
+    hipError_t e = hipMalloc(&b.p, cap);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return set_err(ctx, NH_ENOMEM, "hipMalloc(%zu): %s", cap, hipGetErrorString(e));
+    }
+    b.cap = cap;
+    return NH_OK;
+}
+
+int ensure_pinned(nh_context *ctx, size_t bytes)
+{
+    if (bytes <= ctx->h_stage_cap) return NH_OK;
+    if (ctx->h_stage) {
+        (void)hipHostFree(ctx->h_stage);
+        ctx->h_stage = nullptr;
+        ctx->h_stage_cap = 0;
+    }
+    size_t cap = std::max(bytes, (size_t)65536);
+    hipError_t e = hipHostMalloc(&ctx->h_stage, cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        ctx->h_stage = nullptr;
+        return set_err(ctx, NH_ENOMEM, "hipHostMalloc(%zu): %s", cap, hipGetErrorString(e));
+    }
+    ctx->h_stage_cap = cap;
+    return NH_OK;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Staged inputs of one request: layout and host construction.
+Staged stage_layout(const nh_request *q)
+{
+    Staged s{};
+    const bool rk4 = q->integ.method == NH_RK4;
+    s.n_tab = rk4 ? 2 * q->integ.n_steps + 1 : default_table_nodes();
+    size_t off = 0;
+    s.off_tab = off;  off = align_up(off + (size_t)s.n_tab * NCOL * sizeof(double));
+    s.off_r = off;    off = align_up(off + (size_t)q->grid.n_r * sizeof(double));
+    s.off_y = off;    off = align_up(off + (size_t)q->grid.n_y * sizeof(double));
+    s.off_wy = off;   off = align_up(off + (size_t)q->grid.n_y * sizeof(double));
+    s.off_mu = off;   off = align_up(off + (size_t)q->grid.n_mu * sizeof(double));
+    s.off_smu = off;  off = align_up(off + (size_t)q->grid.n_mu * sizeof(double));
+    s.off_wmu = off;  off = align_up(off + (size_t)q->grid.n_mu * sizeof(double));
+    s.bytes = off;
+    return s;
+}
+
+void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P)
+{
+    Physics ph(*q);
+    const double u_end = -std::log1p(q->integ.z_end);
+    double *tab = (double *)(base + s.off_tab);
+    std::memset(&P, 0, sizeof(P));
+    P.n_r = q->grid.n_r;
+    P.n_y = q->grid.n_y;
+    P.n_mu = q->grid.n_mu;
+    P.n_traj = n_traj_of(q);
+    // km/s per unit y: v = P/m = y k_B T c / m (non-relativistic, Sec. II.D)
+    P.vfac = KB_EV_PER_K * q->f0.T_K * C_KM_S / q->m_eV;
+    P.u_end = u_end;
+    if (q->integ.method == NH_RK4) {
+        build_rk4_table(ph, u_end, q->integ.n_steps, tab);
+        P.n_steps = q->integ.n_steps;
+        P.rk_h = u_end / (double)q->integ.n_steps;
+    } else {
+        build_interp_table(ph, u_end, s.n_tab, tab);
+        P.n_tab = s.n_tab;
+        P.tab_u0 = u_end;
+        P.tab_inv_du = (double)(s.n_tab - 1) / (0.0 - u_end);
+    }
+    const double rt = q->integ.rtol;
+    P.rtol = rt;
+    P.atol_x = q->integ.atol_x > 0 ? q->integ.atol_x : rt * 1.0;
+    P.atol_v = q->integ.atol_v > 0 ? q->integ.atol_v : rt * 1.0;
+    P.h0 = q->integ.h0 != 0.0 ? q->integ.h0 : -1.0e-3;
+    P.max_steps = q->integ.max_steps > 0 ? q->integ.max_steps : 1000000;
+    if (P.max_steps > 2000000000LL) P.max_steps = 2000000000LL;
+    P.r_exit = ph.r_exit(u_end);
+    // paper geometry (or no compensation): R does not depend on u
+    if (q->halo.geometry == NH_GEOM_PAPER || !q->halo.compensated)
+        P.R_const = q->halo.compensated ? ph.R_fixed : 1.0e300;
+    P.order = ORDER_SLOW_FIRST;
+    P.h_fp64 = 0.0;
+
+    std::memcpy(base + s.off_r, q->grid.r_kpc, sizeof(double) * q->grid.n_r);
+    std::memcpy(base + s.off_y, q->grid.y, sizeof(double) * q->grid.n_y);
+    y_weights(q->grid.n_y, q->grid.y, (double *)(base + s.off_wy));
+    double *mu = (double *)(base + s.off_mu);
+    double *smu = (double *)(base + s.off_smu);
+    double *wmu = (double *)(base + s.off_wmu);
+    if (q->grid.mu) {
+        std::memcpy(mu, q->grid.mu, sizeof(double) * q->grid.n_mu);
+        std::memcpy(wmu, q->grid.w_mu, sizeof(double) * q->grid.n_mu);
+    } else {
+        gauss_legendre(q->grid.n_mu, mu, wmu);
+    }
+    for (int l = 0; l < q->grid.n_mu; ++l) smu[l] = std::sqrt(1.0 - mu[l] * mu[l]);
+}
+
+GridPtrs grid_ptrs(const Staged &s, const char *dev)
+{
+    GridPtrs g;
+    g.tab = (const double *)(dev + s.off_tab);
+    g.r = (const double *)(dev + s.off_r);
+    g.y = (const double *)(dev + s.off_y);
+    g.wy = (const double *)(dev + s.off_wy);
+    g.mu = (const double *)(dev + s.off_mu);
+    g.smu = (const double *)(dev + s.off_smu);
+    g.wmu = (const double *)(dev + s.off_wmu);
+    return g;
+}
+
+size_t per_traj_bytes(const nh_request *q)
+{
+    (void)q;
+    return sizeof(double) + 4 * sizeof(int);
+}
+
+#define HIPCHK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return set_err(ctx, NH_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+int wait_pending(nh_context *ctx)
+{
+    if (!ctx->pending) return NH_OK;
+    HIPCHK(hipEventSynchronize(ctx->ev_done));
+    return NH_OK;
+}
+
+int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d_ratio,
+                  hipStream_t stream)
+{
+    int rc = validate(q, ctx->err, sizeof(ctx->err));
+    if (rc != NH_OK) return rc;
+    HIPCHK(hipSetDevice(ctx->device));
+    if ((rc = wait_pending(ctx)) != NH_OK) return rc;
+    ctx->pending = false;
+
+    const Staged s = stage_layout(q);
+    if ((rc = ensure_pinned(ctx, s.bytes)) != NH_OK) return rc;
+    TrajParams P;
+    stage_fill(q, s, (char *)ctx->h_stage, P);
+    if ((rc = ensure_dev(ctx, ctx->blob, s.bytes)) != NH_OK) return rc;
+    HIPCHK(hipMemcpyAsync(ctx->blob.p, ctx->h_stage, s.bytes, hipMemcpyHostToDevice, stream));
+    const GridPtrs g = grid_ptrs(s, (const char *)ctx->blob.p);
+
+    const long long n = P.n_traj;
+    if (!d_ratio) {
+        if ((rc = ensure_dev(ctx, ctx->ratio, (size_t)n * sizeof(double))) != NH_OK) return rc;
+        d_ratio = (double *)ctx->ratio.p;
+    }
+    if ((rc = ensure_dev(ctx, ctx->acc, (size_t)n * sizeof(int))) != NH_OK) return rc;
+    if ((rc = ensure_dev(ctx, ctx->rej, (size_t)n * sizeof(int))) != NH_OK) return rc;
+    if ((rc = ensure_dev(ctx, ctx->status, (size_t)n * sizeof(int))) != NH_OK) return rc;
+    if ((rc = ensure_dev(ctx, ctx->fp64, (size_t)n * sizeof(int))) != NH_OK) return rc;
+    if ((rc = ensure_dev(ctx, ctx->small, 64 * sizeof(unsigned long long))) != NH_OK) return rc;
+    unsigned long long *counter = (unsigned long long *)ctx->small.p;
+    unsigned long long *stats = counter + 8;
+    HIPCHK(launch_fill_u64(counter, 16, 0ull, stream));
+
+    TrajOut o;
+    o.ratio = d_ratio;
+    o.acc = (int *)ctx->acc.p;
+    o.rej = (int *)ctx->rej.p;
+    o.status = (int *)ctx->status.p;
+    o.fp64 = (int *)ctx->fp64.p;
+
+    HIPCHK(hipEventRecord(ctx->ev_t0, stream));
+    if (q->halo.mass_kind == NH_MASS_ZERO) {
+        HIPCHK(launch_free_all(n, o, stream));
+    } else if (q->integ.method == NH_RK4) {
+        HIPCHK(launch_rk4_f64(P, g, o, stream));
+    } else {
+        const size_t lds = (size_t)P.n_tab * NCOL * sizeof(double);
+        const bool f32 = q->integ.precision == NH_FP32C;
+        if (f32) P.h_fp64 = ctx->h_fp64;
+        const int per_cu = f32 ? dp5_f32c_blocks_per_cu(lds) : dp5_f64_blocks_per_cu(lds);
+        long long grid = (long long)ctx->n_cu * per_cu;
+        const long long need = (n + 255) / 256;
+        if (grid > need) grid = need;
+        if (grid < 1) grid = 1;
+        P.order = ctx->queue_order;
+        if (f32) HIPCHK(launch_dp5_f32c(P, g, o, counter, (int)grid, stream));
+        else HIPCHK(launch_dp5_f64(P, g, o, counter, (int)grid, stream));
+    }
+    HIPCHK(hipEventRecord(ctx->ev_t1, stream));
+    HIPCHK(launch_reduce_profile(P, g, d_ratio, q->f0.kind, d_out, stream));
+    HIPCHK(launch_reduce_stats(n, o, stats, stream));
+    HIPCHK(hipEventRecord(ctx->ev_done, stream));
+    ctx->pending = true;
+    ctx->last_n_traj = n;
+    return NH_OK;
+}
+
+int collect_stats(nh_context *ctx, nh_stats *out)
+{
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!ctx->pending && ctx->last_n_traj < 0) return set_err(ctx, NH_EINVAL, "no solve to report");
+    HIPCHK(hipEventSynchronize(ctx->ev_done));
+    unsigned long long h[8] = {0};
+    HIPCHK(hipMemcpy(h, (unsigned long long *)ctx->small.p + 8, sizeof(h), hipMemcpyDeviceToHost));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+    nh_stats st{};
+    st.n_traj = ctx->last_n_traj;
+    st.accepted_steps = (long long)h[0];
+    st.rejected_steps = (long long)h[1];
+    st.max_steps_one_traj = (long long)h[2];
+    st.n_failed = (long long)h[3];
+    st.fp64_steps = (long long)h[4];
+    st.free_exits = (long long)h[5];
+    st.kernel_ms = ms;
+    if (out) *out = st;
+    ctx->pending = false;
+    if (st.n_failed > 0) {
+        set_err(ctx, NH_ESTEPS, "%lld trajectories did not finish cleanly", st.n_failed);
+        return NH_ESTEPS;
+    }
+    return NH_OK;
+}
+
+}  // namespace nh
+
+using namespace nh;
+
+extern "C" {
+
+const char *nh_version(void) { return "nuhalo 0.1 (gfx950)"; }
+
+const char *nh_strerror(int code)
+{
+    switch (code) {
+    case NH_OK: return "ok";
+    case NH_EINVAL: return "invalid argument";
+    case NH_ENOMEM: return "out of memory";
+    case NH_EDEVICE: return "device error";
+    case NH_ESTEPS: return "some trajectories did not finish (max_steps or step underflow)";
+    case NH_ENONFINITE: return "non-finite trajectory state";
+    case NH_EBUSY: return "request does not fit the free budget";
+    case NH_ENOTREADY: return "ticket not finished";
+    case NH_ENOTFOUND: return "unknown ticket";
+    case NH_ECANCELED: return "ticket cancelled";
+    default: return "unknown error";
+    }
+}
+
+const char *nh_last_error(const nh_context *ctx) { return ctx ? ctx->err : g_err; }
+
+int nh_footprint_bytes(const nh_request *req, size_t *bytes)
+{
+    if (!bytes) return set_err(nullptr, NH_EINVAL, "bytes is NULL");
+    int rc = validate(req, g_err, sizeof(g_err));
+    if (rc != NH_OK) return rc;
+    const Staged s = stage_layout(req);
+    *bytes = s.bytes + (size_t)n_traj_of(req) * per_traj_bytes(req) + (size_t)req->grid.n_r * sizeof(double);
+    return NH_OK;
+}
+
+int nh_gauss_legendre(int n, double *x, double *w)
+{
+    if (n < 1 || n > 4096 || !x || !w) return set_err(nullptr, NH_EINVAL, "need 1 <= n <= 4096 and x, w");
+    gauss_legendre(n, x, w);
+    return NH_OK;
+}
+
+int nh_coefficients(const nh_request *req, int n, const double *u, double *out)
+{
+    int rc = validate(req, g_err, sizeof(g_err));
+    if (rc != NH_OK) return rc;
+    if (n < 0 || (n > 0 && (!u || !out))) return set_err(nullptr, NH_EINVAL, "bad n/u/out");
+    Physics ph(*req);
+    for (int i = 0; i < n; ++i) ph.coef(u[i], out + (size_t)i * NCOL);
+    return NH_OK;
+}
+
+int nh_context_create(int device, nh_context **out)
+{
+    if (!out) return set_err(nullptr, NH_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0)
+        return set_err(nullptr, NH_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
+    if (device < 0 || device >= ndev) return set_err(nullptr, NH_EINVAL, "device %d out of range", device);
+    nh_context *ctx = new (std::nothrow) nh_context();
+    if (!ctx) return set_err(nullptr, NH_ENOMEM, "context allocation");
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&ctx->ev_done) != hipSuccess || hipEventCreate(&ctx->ev_t0) != hipSuccess ||
+        hipEventCreate(&ctx->ev_t1) != hipSuccess) {
+        set_err(nullptr, NH_EDEVICE, "stream/event creation failed");
+        nh_context_destroy(ctx);
+        return NH_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
+    if (ctx->n_cu <= 0) ctx->n_cu = 256;
+    *out = ctx;
+    return NH_OK;
+}
+
+int nh_context_destroy(nh_context *ctx)
+{
+    if (!ctx) return NH_OK;
+    (void)hipSetDevice(ctx->device);
+    serve_shutdown(ctx);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    (void)hipDeviceSynchronize();
+    for (DevBuf *b : {&ctx->blob, &ctx->ratio, &ctx->acc, &ctx->rej, &ctx->status, &ctx->fp64,
+                      &ctx->small, &ctx->out})
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
+    if (ctx->ev_t0) (void)hipEventDestroy(ctx->ev_t0);
+    if (ctx->ev_t1) (void)hipEventDestroy(ctx->ev_t1);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return NH_OK;
+}
+
+int nh_solve_async(nh_context *ctx, const nh_request *req, double *d_out, double *d_ratio,
+                   void *stream)
+{
+    if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
+    if (!d_out) return set_err(ctx, NH_EINVAL, "d_out is NULL");
+    return solve_enqueue(ctx, req, d_out, d_ratio, (hipStream_t)stream);
+}
+
+int nh_last_stats(nh_context *ctx, nh_stats *stats)
+{
+    if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
+    return collect_stats(ctx, stats);
+}
+
+int nh_solve(nh_context *ctx, const nh_request *req, double *n_over_nbar, nh_stats *stats)
+{
+    if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
+    if (!n_over_nbar) return set_err(ctx, NH_EINVAL, "output is NULL");
+    int rc = validate(req, ctx->err, sizeof(ctx->err));
+    if (rc != NH_OK) return rc;
+    if ((rc = ensure_dev(ctx, ctx->out, (size_t)req->grid.n_r * sizeof(double))) != NH_OK) return rc;
+    rc = solve_enqueue(ctx, req, (double *)ctx->out.p, nullptr, ctx->stream);
+    if (rc != NH_OK) return rc;
+    rc = collect_stats(ctx, stats);
+    if (rc != NH_OK && rc != NH_ESTEPS) return rc;
+    hipError_t e = hipMemcpy(n_over_nbar, ctx->out.p, (size_t)req->grid.n_r * sizeof(double),
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_err(ctx, NH_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+// Host-side FP64 physics of a request: validation, the coefficient tables the
+// kernels interpolate, and the quadrature rules.
+//
+// Halo model: Sec. II.B (Eqs. rhototal, nfw) with the enclosed mass of App. A
+// (attractive sign); background and EOM: Sec. II.A, Eq. (eoms), written in
+// u = ln a; growth variants and G(z): Sec. IV.A, IV.B.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "nh_internal.h"
+
+namespace nh {
+
+namespace {
+constexpr double kCbrt200 = 5.8480354764257312;   // 200^(1/3)
+}
+
+double nfw_I_host(double q)
+{
+    // I(q) = ln(1+q) - q/(1+q); below q = 0.01 the Taylor series
+    // sum_{k=2..13} (-1)^k (k-1)/k q^k avoids the cancellation.
+    if (q < 1.0e-2) {
+        double acc = 0.0;
+        for (int k = 13; k >= 2; --k) {
+            double ck = (double)(k - 1) / (double)k;
+            acc = acc * q + ((k & 1) ? -ck : ck);
+        }
+        return acc * q * q;
+    }
+    return std::log1p(q) - q / (1.0 + q);
+}
+
+Physics::Physics(const nh_request &q)
+{
+    G = GM_SUN_SI / (KPC_IN_M * 1.0e6);
+    H0k = q.cosmo.H0_km_s_Mpc / 1000.0;
+    Om = q.cosmo.Omega_m;
+    OL = q.cosmo.Omega_L;
+    mass_kind = q.halo.mass_kind;
+    M0 = q.halo.M0_Msun;
+    alpha = q.halo.mass_alpha;
+    z_form = q.halo.z_form;
+    beta = q.halo.mass_beta;
+    conc_kind = q.halo.conc_kind;
+    c0 = q.halo.c0;
+    gamma = q.halo.conc_gamma;
+    kappa_kind = q.halo.kappa_kind;
+    ka = q.halo.kappa_a;
+    kb = q.halo.kappa_b;
+    geometry = q.halo.geometry;
+    compensated = q.halo.compensated;
+    // M(0) = (4 pi/3) R^3 rhobar_m0, rhobar_m0 = 3 Om H0^2 / (8 pi G)  =>  R^3 = 2 G M / (Om H0^2)
+    R_fixed = std::cbrt(2.0 * G * mass(0.0) / (Om * H0k * H0k));
+}
+
+double Physics::mass(double z) const
+{
+    switch (mass_kind) {
+    case NH_MASS_PAPER: {
+        double xi = (z_form - z) / z_form;
+        xi = xi < 0.0 ? 0.0 : (xi > 1.0 ? 1.0 : xi);
+        return M0 * std::pow(xi, alpha);
+    }
+    case NH_MASS_EXPONENTIAL:
+        return M0 * std::exp(-beta * z);
+    default:
+        return 0.0;
+    }
+}
+
+double Physics::conc(double z) const
+{
+    return conc_kind == NH_CONC_POWER ? c0 * std::pow(1.0 + z, -gamma) : c0;
+}
+
+double Physics::kappa(double z) const
+{
+    switch (kappa_kind) {
+    case NH_KAPPA_LOG: return 1.0 + ka * std::log1p(z);
+    case NH_KAPPA_PAPER: return 1.0 + ka * std::pow(z / (1.0 + z), kb);
+    case NH_KAPPA_CONSTANT: return ka;
+    default: return 1.0;
+    }
+}
+
+double Physics::hubble(double z) const
+{
+    double opz = 1.0 + z;
+    return H0k * std::sqrt(Om * opz * opz * opz + OL);
+}
+
+void Physics::coef(double u, double out[NCOL]) const
+{
+    const double opz = std::exp(-u);
+    const double z = std::expm1(-u);
+    const double H = H0k * std::sqrt(Om * opz * opz * opz + OL);
+    out[COL_A] = opz * opz / H;
+    const double M = mass(z);
+    const double c = conc(z);
+    out[COL_C] = c;
+    if (M == 0.0) {
+        out[COL_K] = 0.0;
+        out[COL_KC] = 0.0;
+        out[COL_INVS] = 0.0;
+        out[COL_R] = 0.0;
+        return;
+    }
+    double R, rv;
+    if (geometry == NH_GEOM_DELTA200) {
+        R = std::cbrt(2.0 * G * M / (Om * H0k * H0k));
+        rv = R / kCbrt200;
+    } else {
+        R = R_fixed;
+        rv = (R_fixed / kCbrt200) * opz;   // fixed physical r200, comoving image
+    }
+    const double B = kappa(z) * G * opz / H;
+    out[COL_K] = B * M / nfw_I_host(c);
+    out[COL_KC] = compensated ? B * M / (R * R * R) : 0.0;
+    out[COL_INVS] = c / rv;
+    out[COL_R] = compensated ? R : 1.0e300;
+}
+
+double Physics::r_exit(double u_end) const
+{
+    // Beyond the largest compensation radius over [u_end, 0] the force is
+    // exactly zero; an outward-moving relic there never returns (backward
+    // motion is along -v, and x.v <= 0 makes |x - s v| grow with s).
+    if (!compensated || mass_kind == NH_MASS_ZERO) return compensated ? 0.0 : -1.0;
+    if (geometry == NH_GEOM_PAPER) return R_fixed;
+    double Rmax = 0.0;
+    const int n = 4097;
+    for (int i = 0; i < n; ++i) {
+        double u = u_end * (double)i / (double)(n - 1);
+        double M = mass(std::expm1(-u));
+        double R = std::cbrt(2.0 * G * M / (Om * H0k * H0k));
+        Rmax = R > Rmax ? R : Rmax;
+    }
+    return Rmax;
+}
+
+int default_table_nodes() { return 1025; }
+
+void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out)
+{
+    const double du = (0.0 - u_end) / (double)(n_tab - 1);
+    for (int i = 0; i < n_tab; ++i) {
+        double u = (i == n_tab - 1) ? 0.0 : u_end + (double)i * du;
+        ph.coef(u, out + (size_t)i * NCOL);
+    }
+}
+
+void build_rk4_table(const Physics &ph, double u_end, int n_steps, double *out)
+{
+    // Stage abscissae u_m = m * (u_end / (2N)), m = 0..2N.
+    const double hh = u_end / (double)(2 * n_steps);
+    for (int m = 0; m <= 2 * n_steps; ++m) ph.coef((double)m * hh, out + (size_t)m * NCOL);
+}
+
+void gauss_legendre(int n, double *x, double *w)
+{
+    // Newton iteration on P_n from Tricomi's initial guesses; nodes ascending.
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double t = std::cos(pi * ((double)i + 0.75) / ((double)n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / (double)k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = t; p0 = 1.0; }
+            dp = (double)n * (t * p1 - p0) / (t * t - 1.0);
+            double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-17) break;
+        }
+        // final derivative at the converged node
+        double p0 = 1.0, p1 = t;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / (double)k;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) { p1 = t; p0 = 1.0; }
+        dp = (double)n * (t * p1 - p0) / (t * t - 1.0);
+        double wi = 2.0 / ((1.0 - t * t) * dp * dp);
+        x[i] = -t;
+        x[n - 1 - i] = t;
+        w[i] = wi;
+        w[n - 1 - i] = wi;
+    }
+    if (n & 1) x[n / 2] = 0.0;
+}
+
+void y_weights(int n, const double *y, double *w)
+{
+    // trapezoid in ln y of int dy y^2 f(y) = int dlny y^3 f(y); half weights at the ends
+    for (int j = 0; j < n; ++j) {
+        double d;
+        if (j == 0) d = 0.5 * (std::log(y[1]) - std::log(y[0]));
+        else if (j == n - 1) d = 0.5 * (std::log(y[n - 1]) - std::log(y[n - 2]));
+        else d = 0.5 * (std::log(y[j + 1]) - std::log(y[j - 1]));
+        w[j] = y[j] * y[j] * y[j] * d;
+    }
+}
+
+long long n_traj_of(const nh_request *q)
+{
+    return (long long)q->grid.n_r * (long long)q->grid.n_y * (long long)q->grid.n_mu;
+}
+
+#define NH_BAD(...)                                   \
+    do {                                              \
+        if (msg) std::snprintf(msg, msg_len, __VA_ARGS__); \
+        return NH_EINVAL;                             \
+    } while (0)
+
+int validate(const nh_request *q, char *msg, size_t msg_len)
+{
+    if (!q) NH_BAD("request is NULL");
+    const nh_cosmology &c = q->cosmo;
+    if (!std::isfinite(c.H0_km_s_Mpc) || c.H0_km_s_Mpc <= 0) NH_BAD("H0 must be finite and > 0");
+    if (!std::isfinite(c.Omega_m) || c.Omega_m <= 0) NH_BAD("Omega_m must be finite and > 0");
+    if (!std::isfinite(c.Omega_L) || c.Omega_L < 0) NH_BAD("Omega_L must be finite and >= 0");
+    if (std::fabs(c.Omega_m + c.Omega_L - 1.0) > 1e-12) NH_BAD("background must be flat: |Om + OL - 1| <= 1e-12");
+    const nh_halo &h = q->halo;
+    if (h.mass_kind < NH_MASS_ZERO || h.mass_kind > NH_MASS_EXPONENTIAL) NH_BAD("unknown mass_kind %d", h.mass_kind);
+    if (h.mass_kind != NH_MASS_ZERO && (!std::isfinite(h.M0_Msun) || h.M0_Msun <= 0)) NH_BAD("M0 must be finite and > 0");
+    if (h.mass_kind == NH_MASS_PAPER) {
+        if (!std::isfinite(h.z_form) || h.z_form <= 0) NH_BAD("z_form must be finite and > 0");
+        if (!std::isfinite(h.mass_alpha) || h.mass_alpha < 0) NH_BAD("mass_alpha must be finite and >= 0");
+    }
+    if (h.mass_kind == NH_MASS_EXPONENTIAL && !std::isfinite(h.mass_beta)) NH_BAD("mass_beta must be finite");
+    if (h.conc_kind < NH_CONC_CONSTANT || h.conc_kind > NH_CONC_POWER) NH_BAD("unknown conc_kind %d", h.conc_kind);
+    if (!std::isfinite(h.c0) || h.c0 <= 0) NH_BAD("c0 must be finite and > 0");
+    if (!std::isfinite(h.conc_gamma)) NH_BAD("conc_gamma must be finite");
+    if (h.kappa_kind < NH_KAPPA_NONE || h.kappa_kind > NH_KAPPA_CONSTANT) NH_BAD("unknown kappa_kind %d", h.kappa_kind);
+    if (!std::isfinite(h.kappa_a) || !std::isfinite(h.kappa_b)) NH_BAD("kappa parameters must be finite");
+    if (h.geometry != NH_GEOM_PAPER && h.geometry != NH_GEOM_DELTA200) NH_BAD("unknown geometry %d", h.geometry);
+    if (h.compensated != 0 && h.compensated != 1) NH_BAD("compensated must be 0 or 1");
+    if (!std::isfinite(q->m_eV) || q->m_eV <= 0) NH_BAD("m_eV must be finite and > 0");
+    if (q->f0.kind != NH_F0_FERMI_DIRAC && q->f0.kind != NH_F0_FREEZE_IN) NH_BAD("unknown f0 kind %d", q->f0.kind);
+    if (!std::isfinite(q->f0.T_K) || q->f0.T_K <= 0) NH_BAD("T_K must be finite and > 0");
+    const nh_grid &g = q->grid;
+    if (g.n_r < 1 || !g.r_kpc) NH_BAD("need n_r >= 1 radii");
+    for (int k = 0; k < g.n_r; ++k)
+        if (!std::isfinite(g.r_kpc[k]) || g.r_kpc[k] <= 0) NH_BAD("radius %d must be finite and > 0", k);
+    if (g.n_y < 2 || !g.y) NH_BAD("need n_y >= 2 momenta");
+    for (int j = 0; j < g.n_y; ++j) {
+        if (!std::isfinite(g.y[j]) || g.y[j] <= 0) NH_BAD("y[%d] must be finite and > 0", j);
+        if (j > 0 && !(g.y[j] > g.y[j - 1])) NH_BAD("y must be strictly ascending (index %d)", j);
+    }
+    if (g.n_mu < 1 || g.n_mu > 4096) NH_BAD("n_mu must be in [1, 4096]");
+    if (g.mu) {
+        if (!g.w_mu) NH_BAD("w_mu is required when mu is given");
+        for (int l = 0; l < g.n_mu; ++l) {
+            if (!std::isfinite(g.mu[l]) || std::fabs(g.mu[l]) >= 1.0) NH_BAD("mu[%d] must satisfy |mu| < 1", l);
+            if (!std::isfinite(g.w_mu[l])) NH_BAD("w_mu[%d] must be finite", l);
+        }
+    }
+    const nh_integrator &it = q->integ;
+    if (!std::isfinite(it.z_end) || it.z_end <= 0) NH_BAD("z_end must be finite and > 0");
+    if (h.geometry == NH_GEOM_PAPER && h.mass_kind != NH_MASS_ZERO && it.z_end > kCbrt200 - 1.0 + 1e-12)
+        NH_BAD("paper geometry is defined up to z_i = 200^(1/3) - 1");
+    if (it.method == NH_RK4) {
+        if (it.n_steps < 1 || it.n_steps > 1000000) NH_BAD("n_steps must be in [1, 1e6]");
+        if (it.precision != NH_FP64) NH_BAD("RK4 runs in FP64 only");
+    } else if (it.method == NH_DOPRI5) {
+        if (!std::isfinite(it.rtol) || it.rtol < 1e-15 || it.rtol >= 1.0) NH_BAD("rtol must be in [1e-15, 1)");
+        if (!std::isfinite(it.atol_x) || !std::isfinite(it.atol_v) || !std::isfinite(it.h0)) NH_BAD("atol/h0 must be finite");
+    } else {
+        NH_BAD("unknown method %d", it.method);
+    }
+    if (it.precision != NH_FP64 && it.precision != NH_FP32C) NH_BAD("unknown precision %d", it.precision);
+    long long nt = n_traj_of(q);
+    if (nt > (1LL << 40)) NH_BAD("too many trajectories");
+    return NH_OK;
+}
+
+}  // namespace nh

@@ -1,0 +1,290 @@
+// FP64 trajectory kernels and the profile reduction.
+//
+// One wavefront lane integrates one relic trajectory backward in u = ln a
+// (Sec. II.C) through the halo's force (Sec. II.B, App. A).  Nothing here is a
+// dense contraction, so there is no MFMA: the work is FP64 VALU arithmetic on
+// register-resident state, with the u-dependent coefficients either read as
+// wave-uniform scalars (RK4: every lane sits at the same u) or interpolated
+// from an LDS copy of the FP64 table (Dormand-Prince: every lane has its own u).
+#include <hip/hip_runtime.h>
+
+#include "nh_dp5.h"
+
+namespace nh {
+
+// (Dormand-Prince tableau and step: nh_dp5.h)
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// No halo: the force vanishes everywhere, so every velocity is unchanged.
+__global__ void k_free_all(long long n, TrajOut o)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    o.ratio[t] = 1.0;
+    o.acc[t] = 0;
+    o.rej[t] = 0;
+    o.status[t] = ST_OK | ST_FREE_EXIT;
+    if (o.fp64) o.fp64[t] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// classical RK4, n_steps equal steps; all lanes share u
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajOut o)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = t < P.n_traj;
+    double x = 0.0, y = 0.0, vx = 0.0, vy = 0.0, v0n = 1.0;
+    if (valid) {
+        const int l = (int)(t % P.n_mu);
+        const long long kj = t / P.n_mu;
+        const int j = (int)(kj % P.n_y);
+        const int k = (int)(kj / P.n_y);
+        const double V = g.y[j] * P.vfac;
+        x = g.r[k];
+        vx = V * g.mu[l];
+        vy = V * g.smu[l];
+        v0n = sqrt(vx * vx + vy * vy);
+    }
+    const double r_exit2 = P.r_exit * P.r_exit;
+    bool active = valid;
+    bool freed = false;
+    int steps = 0;
+    const double h = P.rk_h;
+    const double hh = 0.5 * h;
+    for (int n = 0; n < P.n_steps; ++n) {
+        if (__ballot(active) == 0ull) break;
+        const double *c0 = g.tab + (size_t)(2 * n) * NCOL;    // wave-uniform rows
+        double ca[NCOL], cb[NCOL], cc[NCOL];
+#pragma unroll
+        for (int q = 0; q < NCOL; ++q) {
+            ca[q] = c0[q];
+            cb[q] = c0[NCOL + q];
+            cc[q] = c0[2 * NCOL + q];
+        }
+        double k1x, k1y, k1u, k1v, k2x, k2y, k2u, k2v, k3x, k3y, k3u, k3v, k4x, k4y, k4u, k4v;
+        rhs(ca, ca[COL_R], x, y, vx, vy, k1x, k1y, k1u, k1v);
+        rhs(cb, cb[COL_R], x + hh * k1x, y + hh * k1y, vx + hh * k1u, vy + hh * k1v, k2x, k2y, k2u, k2v);
+        rhs(cb, cb[COL_R], x + hh * k2x, y + hh * k2y, vx + hh * k2u, vy + hh * k2v, k3x, k3y, k3u, k3v);
+        rhs(cc, cc[COL_R], x + h * k3x, y + h * k3y, vx + h * k3u, vy + h * k3v, k4x, k4y, k4u, k4v);
+        const double h6 = h / 6.0;
+        if (active) {
+            x = x + h6 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
+            y = y + h6 * (k1y + 2.0 * k2y + 2.0 * k3y + k4y);
+            vx = vx + h6 * (k1u + 2.0 * k2u + 2.0 * k3u + k4u);
+            vy = vy + h6 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+            ++steps;
+            if (P.r_exit > 0.0 && x * x + y * y >= r_exit2 && x * vx + y * vy <= 0.0) {
+                active = false;
+                freed = true;
+            }
+        }
+    }
+    if (valid) {
+        o.ratio[t] = sqrt(vx * vx + vy * vy) / v0n;
+        o.acc[t] = steps;
+        o.rej[t] = 0;
+        int st = ST_OK;
+        if (!(isfinite(x) && isfinite(y) && isfinite(vx) && isfinite(vy))) st = ST_NONFINITE;
+        o.status[t] = st | (freed ? ST_FREE_EXIT : 0);
+        if (o.fp64) o.fp64[t] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dormand-Prince 5(4), adaptive; persistent waves refill lanes from a queue
+// ---------------------------------------------------------------------------
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
+                                                 unsigned long long *counter)
+{
+    extern __shared__ double lds_tab[];
+    for (int i = threadIdx.x; i < P.n_tab * NCOL; i += blockDim.x) lds_tab[i] = g.tab[i];
+    __syncthreads();
+
+    const TabCoef<NC> cf{lds_tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
+    DpCtl ctl;
+    ctl.u_end = P.u_end;
+    ctl.rtol = P.rtol;
+    ctl.atol_x = P.atol_x;
+    ctl.atol_v = P.atol_v;
+    ctl.r_exit2 = P.r_exit > 0.0 ? P.r_exit * P.r_exit : -1.0;
+    ctl.max_steps = (int)P.max_steps;
+
+    long long t = -1;          // -1: wants work, -2: queue drained, >= 0: trajectory
+    double v0n = 1.0;
+    Lane64 L{};
+    for (;;) {
+        const bool need = (t == -1);
+        const long long p = wave_claim(need, counter);
+        if (need) {
+            if (p < P.n_traj) {
+                t = traj_of(p, P);
+                const int l = (int)(t % P.n_mu);
+                const long long kj = t / P.n_mu;
+                const int j = (int)(kj % P.n_y);
+                const int k = (int)(kj / P.n_y);
+                const double V = g.y[j] * P.vfac;
+                const double vx0 = V * g.mu[l], vy0 = V * g.smu[l];
+                v0n = sqrt(vx0 * vx0 + vy0 * vy0);
+                dp5_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_end);
+            } else {
+                t = -2;
+            }
+        }
+        if (__ballot(t >= 0) == 0ull) break;
+        if (t >= 0) {
+            const int st = dp5_attempt(L, cf, ctl);
+            if (st >= 0) {
+                o.ratio[t] = sqrt(L.vx * L.vx + L.vy * L.vy) / v0n;
+                o.acc[t] = L.nacc;
+                o.rej[t] = L.nrej;
+                o.status[t] = st;
+                t = -1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// momentum-space quadrature: n/nbar_k = sum W f(y_j ratio) / sum W f(y_j)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_reduce_profile(TrajParams P, GridPtrs g,
+                                                        const double *__restrict__ ratio,
+                                                        int f0_kind, double *__restrict__ out)
+{
+    const int k = blockIdx.x;
+    const int ne = P.n_y * P.n_mu;
+    double num = 0.0, den = 0.0;
+    const double *rk = ratio + (size_t)k * ne;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        const int j = e / P.n_mu;
+        const int l = e - j * P.n_mu;
+        const double W = g.wy[j] * g.wmu[l];
+        const double yj = g.y[j];
+        num += W * f0_eval(f0_kind, yj * rk[e]);
+        den += W * f0_eval(f0_kind, yj);
+    }
+    __shared__ double sn[256], sd[256];
+    sn[threadIdx.x] = num;
+    sd[threadIdx.x] = den;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sn[threadIdx.x] += sn[threadIdx.x + s];
+            sd[threadIdx.x] += sd[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sn[0] / sd[0];
+}
+
+// Integer statistics (exact under any summation order).
+// stats: [accepted, rejected, max(acc+rej), failed, fp64 steps, free exits]
+__global__ __launch_bounds__(256) void k_reduce_stats(long long n, TrajOut o,
+                                                      unsigned long long *stats)
+{
+    unsigned long long acc = 0, rej = 0, mx = 0, fail = 0, f64 = 0, fre = 0;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x) {
+        const unsigned long long a = (unsigned)o.acc[t], r = (unsigned)o.rej[t];
+        acc += a;
+        rej += r;
+        mx = a + r > mx ? a + r : mx;
+        const int st = o.status[t];
+        fail += (st & 0xff) != ST_OK;
+        fre += (st & ST_FREE_EXIT) != 0;
+        if (o.fp64) f64 += (unsigned)o.fp64[t];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_down(acc, off);
+        rej += __shfl_down(rej, off);
+        const unsigned long long m2 = __shfl_down(mx, off);
+        mx = m2 > mx ? m2 : mx;
+        fail += __shfl_down(fail, off);
+        f64 += __shfl_down(f64, off);
+        fre += __shfl_down(fre, off);
+    }
+    if (__lane_id() == 0) {
+        atomicAdd(stats + 0, acc);
+        atomicAdd(stats + 1, rej);
+        atomicMax(stats + 2, mx);
+        atomicAdd(stats + 3, fail);
+        atomicAdd(stats + 4, f64);
+        atomicAdd(stats + 5, fre);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_free_all(long long n, const TrajOut &o, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_free_all, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, hipStream_t s)
+{
+    const long long blocks = (P.n_traj + 255) / 256;
+    hipLaunchKernelGGL(k_rk4_f64, dim3((unsigned)blocks), dim3(256), 0, s, P, g, o);
+    return hipGetLastError();
+}
+
+int dp5_f64_blocks_per_cu(size_t lds_bytes)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dp5_f64<NCOL - 1>, 256, lds_bytes) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                          unsigned long long *counter, int grid, hipStream_t s)
+{
+    const size_t lds = (size_t)P.n_tab * NCOL * sizeof(double);
+    if (P.R_const > 0.0)
+        hipLaunchKernelGGL(k_dp5_f64<NCOL - 1>, dim3(grid), dim3(256), lds, s, P, g, o, counter);
+    else
+        hipLaunchKernelGGL(k_dp5_f64<NCOL>, dim3(grid), dim3(256), lds, s, P, g, o, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,
+                                 int f0_kind, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_profile, dim3(P.n_r), dim3(256), 0, s, P, g, ratio, f0_kind, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long *stats,
+                               hipStream_t s)
+{
+    long long blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_reduce_stats, dim3((unsigned)blocks), dim3(256), 0, s, n, o, stats);
+    return hipGetLastError();
+}
+
+}  // namespace nh

@@ -1,0 +1,57 @@
+// The opaque nh_context and host helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstddef>
+
+#include "nh_internal.h"
+
+namespace nh {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+// Byte offsets of one request's inputs inside the staged blob.
+struct Staged {
+    int n_tab;
+    size_t off_tab, off_r, off_y, off_wy, off_mu, off_smu, off_wmu;
+    size_t bytes;
+};
+
+struct ServeState;   // serving loop (host_serve.cpp)
+
+}  // namespace nh
+
+struct nh_context {
+    int device = 0;
+    int n_cu = 0;
+    char err[512] = "";
+    hipStream_t stream = nullptr;                    // used by nh_solve
+    nh::DevBuf blob, ratio, acc, rej, status, fp64, small, out;
+    void *h_stage = nullptr;                         // pinned staging for the inputs
+    size_t h_stage_cap = 0;
+    hipEvent_t ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+    bool pending = false;
+    long long last_n_traj = -1;
+    // tunables (set by the autotuner / tests through nh_context_tune in the binding)
+    int queue_order = nh::ORDER_SLOW_FIRST;
+    double h_fp64 = 0.0;                             // FP32C: |h| below this runs in FP64
+    nh::ServeState *serve = nullptr;
+};
+
+namespace nh {
+
+int set_err(nh_context *ctx, int code, const char *fmt, ...);
+int ensure_dev(nh_context *ctx, DevBuf &b, size_t bytes);
+int ensure_pinned(nh_context *ctx, size_t bytes);
+Staged stage_layout(const nh_request *q);
+void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P);
+GridPtrs grid_ptrs(const Staged &s, const char *dev);
+size_t per_traj_bytes(const nh_request *q);
+void serve_shutdown(nh_context *ctx);
+
+}  // namespace nh

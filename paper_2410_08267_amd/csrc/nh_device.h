@@ -1,0 +1,186 @@
+// Device helpers shared by the trajectory kernels: FP64 elementary functions
+// sized for this problem, coefficient interpolation, the right-hand side of the
+// equations of motion, the relic distributions and the wavefront work queue.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "nh_internal.h"
+
+namespace nh {
+
+// ---------------------------------------------------------------------------
+// FP64 elementary functions.  The hardware rcp/rsq give a ~26-bit first guess;
+// two Newton steps bring it to within an ulp or so.  No special-case handling:
+// callers only pass positive finite arguments (r = 0 is masked by the caller).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double rcp64(double a)
+{
+    double r = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-a, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq64(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    double e = fma(-a * y, y, 1.0);     // 1 - a y^2
+    y = fma(0.5 * y, e, y);
+    e = fma(-a * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// ln(w) for w >= 1: w = m 2^e with m in [sqrt(1/2), sqrt(2)), and
+// ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^21/21), s = (m-1)/(m+1), |s| <= 0.1716.
+__device__ __forceinline__ double log_ge1(double w)
+{
+    int e = __builtin_amdgcn_frexp_exp(w);
+    double m = __builtin_amdgcn_frexp_mant(w);        // [0.5, 1)
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) * rcp64(m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double ts = 2.0 * s;
+    const double lm = fma(ts * s2, p, ts);
+    const double de = (double)e;
+    return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, lm));
+}
+
+// NFW mass integral I(q) = ln(1+q) - q/(1+q) (Eq. nfw).  Below q = 0.1 the
+// difference cancels; there I = sum_{k>=2} w^k / k with w = q/(1+q) (all terms
+// positive), truncated after k = 17.
+__device__ __forceinline__ double nfw_I(double q)
+{
+    const double opq = 1.0 + q;
+    const double inv = rcp64(opq);
+    if (q < 0.1) {
+        const double w = q * inv;
+        double p = 1.0 / 17.0;
+        p = fma(p, w, 1.0 / 16.0);
+        p = fma(p, w, 1.0 / 15.0);
+        p = fma(p, w, 1.0 / 14.0);
+        p = fma(p, w, 1.0 / 13.0);
+        p = fma(p, w, 1.0 / 12.0);
+        p = fma(p, w, 1.0 / 11.0);
+        p = fma(p, w, 1.0 / 10.0);
+        p = fma(p, w, 1.0 / 9.0);
+        p = fma(p, w, 1.0 / 8.0);
+        p = fma(p, w, 1.0 / 7.0);
+        p = fma(p, w, 1.0 / 6.0);
+        p = fma(p, w, 1.0 / 5.0);
+        p = fma(p, w, 1.0 / 4.0);
+        p = fma(p, w, 1.0 / 3.0);
+        p = fma(p, w, 1.0 / 2.0);
+        return w * w * p;
+    }
+    return log_ge1(opq) - q * inv;
+}
+
+// ---------------------------------------------------------------------------
+// coefficients and right-hand side
+// ---------------------------------------------------------------------------
+
+// Coefficients at u from the uniform table (4-point Lagrange, cubic).  Nodes
+// u_i = u0 + i du, i = 0..n-1, rows of NCOL doubles; the stencil is shifted
+// inward at both ends.  NC columns are interpolated (NC = NCOL - 1 when the
+// compensation radius R is constant and passed separately).
+template <int NC>
+__device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int n_tab, double u0,
+                                            double inv_du, double u, double c[NCOL])
+{
+    const double s = (u - u0) * inv_du;
+    int i = (int)s;
+    i = i < 1 ? 1 : (i > n_tab - 3 ? n_tab - 3 : i);
+    const double p = s - (double)i;
+    const double pm = p + 1.0, p1 = p - 1.0, p2 = p - 2.0;
+    const double wa = -(p * p1 * p2) * (1.0 / 6.0);
+    const double wb = (pm * p1 * p2) * 0.5;
+    const double wc = -(pm * p * p2) * 0.5;
+    const double wd = (pm * p * p1) * (1.0 / 6.0);
+    const double *row = tab + (i - 1) * NCOL;
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+        c[k] = wa * row[k] + wb * row[NCOL + k] + wc * row[2 * NCOL + k] + wd * row[3 * NCOL + k];
+}
+
+// dY/du for Y = (x, y, vx, vy): dx/du = A v, dv/du = -g x with
+// g = K I(min(r/s, c)) / r^3 - Kc inside R and 0 outside (and at r = 0).
+__device__ __forceinline__ void rhs(const double c[NCOL], double R, double x, double y, double vx,
+                                    double vy, double &dx, double &dy, double &dvx, double &dvy)
+{
+    const double r2 = x * x + y * y;
+    const double ri = rsq64(r2);
+    const double r = r2 * ri;
+    const double q = fmin(r * c[COL_INVS], c[COL_C]);
+    const double I = nfw_I(q);
+    double g = fma(c[COL_K] * I, ri * ri * ri, -c[COL_KC]);
+    g = (r2 > 0.0 && r < R) ? g : 0.0;
+    dx = c[COL_A] * vx;
+    dy = c[COL_A] * vy;
+    dvx = -g * x;
+    dvy = -g * y;
+}
+
+// Relic distribution before the halo formed, y = P / (k_B T).
+__device__ __forceinline__ double f0_eval(int kind, double y)
+{
+    if (kind == NH_F0_FREEZE_IN) return exp(-y) / sqrt(y);
+    return 1.0 / (1.0 + exp(y));
+}
+
+// Queue position -> trajectory index.
+__device__ __forceinline__ long long traj_of(long long p, const TrajParams &P)
+{
+    if (P.order == ORDER_SLOW_FIRST) {
+        const long long l = p % P.n_mu;
+        const long long q = p / P.n_mu;
+        const long long k = q % P.n_r;
+        const long long j = q / P.n_r;
+        return (k * P.n_y + j) * P.n_mu + l;
+    }
+    return p;
+}
+
+// One atomic per wavefront hands consecutive queue positions to the lanes
+// that asked for work; returns this lane's position (meaningful if `need`).
+__device__ __forceinline__ long long wave_claim(bool need, unsigned long long *counter)
+{
+    const unsigned long long mask = __ballot(need);
+    if (mask == 0ull) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+    const unsigned long long below = mask & ((1ull << lane) - 1ull);
+    return (long long)(base + (unsigned long long)__popcll(below));
+}
+
+// Step-size factor of the controller, min(fmax, max(0.2, 0.9 err^(-1/5))) from
+// err^2.  Only the step length depends on it (acceptance compares err^2 <= 1 in
+// FP64), so it is evaluated in FP32 with the hardware log2/exp2.
+__device__ __forceinline__ double step_factor(double err2, double fmax)
+{
+    if (err2 == 0.0) return fmax;
+    const float l = __builtin_amdgcn_logf((float)err2);      // log2
+    float f = 0.9f * __builtin_amdgcn_exp2f(-0.1f * l);
+    f = fminf((float)fmax, fmaxf(0.2f, f));
+    return (double)f;
+}
+
+}  // namespace nh

@@ -1,0 +1,159 @@
+// The Dormand-Prince 5(4) step of one trajectory in FP64, shared by the plain
+// and batched kernels.  Tableau: Dormand & Prince (1980); step control: Hairer,
+// Norsett & Wanner, Solving ODEs I, Sec. II.4 (see nh_dopri5 in nuhalo.h).
+#pragma once
+
+#include "nh_device.h"
+
+namespace nh {
+
+namespace dp {
+constexpr double c2 = 1.0 / 5.0, c3 = 3.0 / 10.0, c4 = 4.0 / 5.0, c5 = 8.0 / 9.0;
+constexpr double a21 = 1.0 / 5.0;
+constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
+constexpr double a41 = 44.0 / 45.0, a42 = -56.0 / 15.0, a43 = 32.0 / 9.0;
+constexpr double a51 = 19372.0 / 6561.0, a52 = -25360.0 / 2187.0, a53 = 64448.0 / 6561.0,
+                 a54 = -212.0 / 729.0;
+constexpr double a61 = 9017.0 / 3168.0, a62 = -355.0 / 33.0, a63 = 46732.0 / 5247.0,
+                 a64 = 49.0 / 176.0, a65 = -5103.0 / 18656.0;
+// fifth-order weights (= seventh stage row, FSAL)
+constexpr double b1 = 35.0 / 384.0, b3 = 500.0 / 1113.0, b4 = 125.0 / 192.0,
+                 b5 = -2187.0 / 6784.0, b6 = 11.0 / 84.0;
+// e = b - b* (fourth-order embedded weights b*)
+constexpr double e1 = 35.0 / 384.0 - 5179.0 / 57600.0;
+constexpr double e3 = 500.0 / 1113.0 - 7571.0 / 16695.0;
+constexpr double e4 = 125.0 / 192.0 - 393.0 / 640.0;
+constexpr double e5 = -2187.0 / 6784.0 - (-92097.0 / 339200.0);
+constexpr double e6 = 11.0 / 84.0 - 187.0 / 2100.0;
+constexpr double e7 = 0.0 - 1.0 / 40.0;
+}  // namespace dp
+
+// Coefficient source: an FP64 table in LDS.  NC = 5 when R is constant.
+template <int NC>
+struct TabCoef {
+    const double *tab;
+    int n_tab;
+    double u0, inv_du, R_const;
+    __device__ __forceinline__ void at(double u, double c[NCOL], double &R) const
+    {
+        coef_interp<NC>(tab, n_tab, u0, inv_du, u, c);
+        R = (NC == NCOL) ? c[COL_R] : R_const;
+    }
+};
+
+struct DpCtl {
+    double u_end;      // integration ends here (< 0)
+    double rtol, atol_x, atol_v;
+    double r_exit2;    // squared free-streaming exit radius; < 0 disables
+    int max_steps;
+};
+
+struct Lane64 {
+    double x, y, vx, vy, u, h;
+    double k1x, k1y, k1u, k1v;   // FSAL stage
+    int nacc, nrej, natt;
+    bool rej_prev;
+};
+
+// Start a trajectory at u = 0 (first stage evaluated here).
+template <class CF>
+__device__ __forceinline__ void dp5_start(Lane64 &L, const CF &cf, double x0, double vx0, double vy0,
+                                          double h0, double u_end)
+{
+    L.x = x0;
+    L.y = 0.0;
+    L.vx = vx0;
+    L.vy = vy0;
+    L.u = 0.0;
+    L.h = -fabs(h0);
+    if (fabs(L.h) > fabs(u_end)) L.h = u_end;
+    L.nacc = L.nrej = L.natt = 0;
+    L.rej_prev = false;
+    double c[NCOL], R;
+    cf.at(0.0, c, R);
+    rhs(c, R, L.x, L.y, L.vx, L.vy, L.k1x, L.k1y, L.k1u, L.k1v);
+}
+
+// One attempted step.  Returns -1 while the trajectory continues, else its
+// final status word (ST_*).
+template <class CF>
+__device__ __forceinline__ int dp5_attempt(Lane64 &L, const CF &cf, const DpCtl &ctl)
+{
+    using namespace dp;
+    if (L.natt >= ctl.max_steps) return ST_MAXSTEPS;
+    ++L.natt;
+    bool last = false;
+    double h = L.h;
+    if (L.u + h - ctl.u_end <= 0.0) {
+        h = ctl.u_end - L.u;
+        last = true;
+    }
+    const double x = L.x, y = L.y, vx = L.vx, vy = L.vy, u = L.u;
+    const double k1x = L.k1x, k1y = L.k1y, k1u = L.k1u, k1v = L.k1v;
+    double c[NCOL], R;
+    double k2x, k2y, k2u, k2v, k3x, k3y, k3u, k3v, k4x, k4y, k4u, k4v;
+    double k5x, k5y, k5u, k5v, k6x, k6y, k6u, k6v, k7x, k7y, k7u, k7v;
+
+    cf.at(u + c2 * h, c, R);
+    rhs(c, R, x + h * (a21 * k1x), y + h * (a21 * k1y), vx + h * (a21 * k1u), vy + h * (a21 * k1v),
+        k2x, k2y, k2u, k2v);
+    cf.at(u + c3 * h, c, R);
+    rhs(c, R, x + h * (a31 * k1x + a32 * k2x), y + h * (a31 * k1y + a32 * k2y),
+        vx + h * (a31 * k1u + a32 * k2u), vy + h * (a31 * k1v + a32 * k2v), k3x, k3y, k3u, k3v);
+    cf.at(u + c4 * h, c, R);
+    rhs(c, R, x + h * (a41 * k1x + a42 * k2x + a43 * k3x), y + h * (a41 * k1y + a42 * k2y + a43 * k3y),
+        vx + h * (a41 * k1u + a42 * k2u + a43 * k3u), vy + h * (a41 * k1v + a42 * k2v + a43 * k3v),
+        k4x, k4y, k4u, k4v);
+    cf.at(u + c5 * h, c, R);
+    rhs(c, R, x + h * (a51 * k1x + a52 * k2x + a53 * k3x + a54 * k4x),
+        y + h * (a51 * k1y + a52 * k2y + a53 * k3y + a54 * k4y),
+        vx + h * (a51 * k1u + a52 * k2u + a53 * k3u + a54 * k4u),
+        vy + h * (a51 * k1v + a52 * k2v + a53 * k3v + a54 * k4v), k5x, k5y, k5u, k5v);
+    cf.at(u + h, c, R);
+    rhs(c, R, x + h * (a61 * k1x + a62 * k2x + a63 * k3x + a64 * k4x + a65 * k5x),
+        y + h * (a61 * k1y + a62 * k2y + a63 * k3y + a64 * k4y + a65 * k5y),
+        vx + h * (a61 * k1u + a62 * k2u + a63 * k3u + a64 * k4u + a65 * k5u),
+        vy + h * (a61 * k1v + a62 * k2v + a63 * k3v + a64 * k4v + a65 * k5v), k6x, k6y, k6u, k6v);
+    const double x5 = x + h * (b1 * k1x + b3 * k3x + b4 * k4x + b5 * k5x + b6 * k6x);
+    const double y5 = y + h * (b1 * k1y + b3 * k3y + b4 * k4y + b5 * k5y + b6 * k6y);
+    const double vx5 = vx + h * (b1 * k1u + b3 * k3u + b4 * k4u + b5 * k5u + b6 * k6u);
+    const double vy5 = vy + h * (b1 * k1v + b3 * k3v + b4 * k4v + b5 * k5v + b6 * k6v);
+    rhs(c, R, x5, y5, vx5, vy5, k7x, k7y, k7u, k7v);   // c7 = c6 = 1: same coefficients
+
+    const double ex = h * (e1 * k1x + e3 * k3x + e4 * k4x + e5 * k5x + e6 * k6x + e7 * k7x);
+    const double ey = h * (e1 * k1y + e3 * k3y + e4 * k4y + e5 * k5y + e6 * k6y + e7 * k7y);
+    const double eu = h * (e1 * k1u + e3 * k3u + e4 * k4u + e5 * k5u + e6 * k6u + e7 * k7u);
+    const double ev = h * (e1 * k1v + e3 * k3v + e4 * k4v + e5 * k5v + e6 * k6v + e7 * k7v);
+    // sc = atol + rtol max(|.|_n, |.|_{n+1}); max of the norms = sqrt of the max of the squares
+    const double sx = ctl.atol_x + ctl.rtol * sqrt(fmax(x * x + y * y, x5 * x5 + y5 * y5));
+    const double sv = ctl.atol_v + ctl.rtol * sqrt(fmax(vx * vx + vy * vy, vx5 * vx5 + vy5 * vy5));
+    const double isx = rcp64(sx), isv = rcp64(sv);
+    const double qx = ex * isx, qy = ey * isx, qu = eu * isv, qv = ev * isv;
+    const double err2 = 0.25 * (qx * qx + qy * qy + qu * qu + qv * qv);   // err^2
+    if (!(err2 <= 1.0e300)) return ST_NONFINITE;
+    if (err2 <= 1.0) {
+        ++L.nacc;
+        L.u = last ? ctl.u_end : u + h;
+        L.x = x5;
+        L.y = y5;
+        L.vx = vx5;
+        L.vy = vy5;
+        L.k1x = k7x;
+        L.k1y = k7y;
+        L.k1u = k7u;
+        L.k1v = k7v;
+        if (last) return ST_OK;
+        if (ctl.r_exit2 >= 0.0 && x5 * x5 + y5 * y5 >= ctl.r_exit2 && x5 * vx5 + y5 * vy5 <= 0.0)
+            return ST_OK | ST_FREE_EXIT;
+        L.h = h * step_factor(err2, L.rej_prev ? 1.0 : 5.0);
+        L.rej_prev = false;
+    } else {
+        ++L.nrej;
+        L.h = h * step_factor(err2, 5.0);
+        L.rej_prev = true;
+    }
+    if (fabs(L.h) <= 8.881784197001252e-16 * fmax(1.0, fabs(L.u))) return ST_UNDERFLOW;
+    return -1;
+}
+
+}  // namespace nh

@@ -1,0 +1,118 @@
+// Internal declarations shared by the host side of libnuhalo and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "nuhalo.h"
+
+namespace nh {
+
+// Coefficient columns of the equations of motion in u = ln a (Sec. II.A, Eq. eoms
+// with dz = -(1+z) du; enclosed mass from Sec. II.B / App. A):
+//   dx/du = A(u) v
+//   dv/du = -[ K(u) I(min(r s^-1(u), c(u))) / r^3 - Kc(u) ] x   for r < R(u), else 0
+// A = (1+z)^2/H, B = kappa G (1+z)/H, K = B M / I(c), Kc = B M / R^3.
+enum Col : int { COL_A = 0, COL_K = 1, COL_KC = 2, COL_INVS = 3, COL_C = 4, COL_R = 5, NCOL = 6 };
+
+// Trajectory status word: low byte is the outcome, bit 8 marks the exact free-streaming exit.
+enum : int {
+    ST_OK = 0,
+    ST_MAXSTEPS = 1,
+    ST_UNDERFLOW = 2,
+    ST_NONFINITE = 3,
+    ST_FREE_EXIT = 256,
+};
+
+// Queue position -> trajectory index orders for the persistent kernels.
+enum : int {
+    ORDER_NATURAL = 0,     // t = p
+    ORDER_SLOW_FIRST = 1,  // p runs over (j, k, l) with l fastest: low-momentum relics first
+};
+
+// Everything a trajectory kernel needs about one request, passed by value.
+struct TrajParams {
+    // grid
+    int n_r, n_y, n_mu;
+    long long n_traj;
+    double vfac;            // k_B T c / m: km/s per unit y
+    // integration interval (u = ln a, backward from 0)
+    double u_end;
+    // interpolation table: n_tab nodes u_i = u_end + i * du, i = 0..n_tab-1 (DP5)
+    int n_tab;
+    double tab_u0;
+    double tab_inv_du;
+    // RK4: n_steps equal steps, stage abscissae m * hh
+    int n_steps;
+    double rk_h;
+    // Dormand-Prince control
+    double rtol, atol_x, atol_v, h0;
+    long long max_steps;
+    // exact free-streaming exit: beyond r_exit moving outward the force is zero forever
+    double r_exit;          // <= 0 disables
+    double R_const;         // > 0: the compensation radius is this constant (no R column)
+    int order;              // ORDER_*
+    // FP32-compensated form: steps with |h| below this run in FP64
+    double h_fp64;
+};
+
+// Device pointers of one request's staged inputs (one contiguous blob).
+struct GridPtrs {
+    const double *tab;      // n_tab * NCOL (DP5) or (2 n_steps + 1) * NCOL (RK4)
+    const double *r;        // n_r
+    const double *y;        // n_y
+    const double *wy;       // n_y
+    const double *mu;       // n_mu
+    const double *smu;      // n_mu: sqrt(1 - mu^2)
+    const double *wmu;      // n_mu
+};
+
+struct TrajOut {
+    double *ratio;          // n_traj: |v_end| / |v0|
+    int *acc;               // n_traj accepted steps
+    int *rej;               // n_traj rejected steps
+    int *status;            // n_traj status words
+    int *fp64;              // n_traj steps run in FP64 (FP32C) or nullptr
+};
+
+// Host-side physics of one request, evaluated in FP64 (tables, validation).
+struct Physics {
+    double G, H0k, Om, OL;
+    int mass_kind;
+    double M0, alpha, z_form, beta;
+    int conc_kind;
+    double c0, gamma;
+    int kappa_kind;
+    double ka, kb;
+    int geometry, compensated;
+    double R_fixed;         // NH_GEOM_PAPER: comoving Lagrangian radius from M(z=0)
+
+    explicit Physics(const nh_request &q);
+    double mass(double z) const;
+    double conc(double z) const;
+    double kappa(double z) const;
+    double hubble(double z) const;
+    void coef(double u, double out[NCOL]) const;
+    double r_exit(double u_end) const;   // radius beyond which the force is zero at every u
+};
+
+// Physical constants (the paper states only T_nu0 = 1.95 K).
+constexpr double GM_SUN_SI = 1.32712440018e20;        // m^3 s^-2, IAU 2015 nominal
+constexpr double KPC_IN_M = 3.0856775814913673e19;    // m
+constexpr double KB_EV_PER_K = 8.617333262e-5;        // eV / K
+constexpr double C_KM_S = 299792.458;                 // km / s
+
+double nfw_I_host(double q);
+void gauss_legendre(int n, double *x, double *w);
+void y_weights(int n, const double *y, double *w);
+int validate(const nh_request *q, char *msg, size_t msg_len);
+long long n_traj_of(const nh_request *q);
+
+// Table builders (host, FP64).
+int default_table_nodes();
+void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out);
+void build_rk4_table(const Physics &ph, double u_end, int n_steps, double *out);
+
+}  // namespace nh

@@ -1,0 +1,166 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Every case names itself on stdout before it touches the GPU.  Tolerances:
+  * RK4 (fixed steps, identical step sequence): n/nbar within 1e-11 relative,
+    per-trajectory speed ratios within 1e-9 for 99.9 % of trajectories.
+  * Dormand-Prince FP64 at the same rtol as the oracle: n/nbar within 1e-8
+    relative (the bound set for the FP64 path).  Step sizes agree up to the
+    FP32 evaluation of the step-size factor; per-trajectory ratios are
+    compared statistically.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_08267_amd import workloads as W
+from paper_2410_08267_amd.request import Z_FORM_PAPER
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_08267_amd import nuhalo as N
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = N.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) / np.asarray(b) - 1.0)
+
+
+def gpu_ratios(ctx, req):
+    """Run through nh_solve_async with a device ratio buffer; return (profile, ratios, stats)."""
+    out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+    ratio = torch.empty(req.n_traj, dtype=torch.float64, device="cuda")
+    ctx.solve_async(req, out, ratio)
+    stats, _ = ctx.last_stats()
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ratio.cpu().numpy(), stats
+
+
+def test_rk4_plain_small_full(ctx, O):
+    req = W.plain_small()
+    say(f"rk4 plain_small full grid n_traj={req.n_traj}")
+    prof, ratio, stats = gpu_ratios(ctx, req)
+    ref = O.solve(req)
+    print("n/nbar gpu", prof, "\noracle", ref["n_over_nbar"], flush=True)
+    d = rel(ratio, ref["ratio"])
+    print(f"ratio rel diff: median {np.median(d):.2e} p99.9 {np.quantile(d, 0.999):.2e} max {d.max():.2e}")
+    assert rel(prof, ref["n_over_nbar"]).max() <= 1e-11
+    assert np.quantile(d, 0.999) <= 1e-9
+    assert stats["n_failed"] == 0
+
+
+@pytest.mark.parametrize("method", ["rk4", "dp5"])
+def test_zero_halo_is_exactly_one(ctx, method):
+    req = W.shrink(W.plain_small(), 7, 13, 5).with_(mass_kind="zero", method=method)
+    say(f"zero halo {method}")
+    prof, ratio, _ = gpu_ratios(ctx, req)
+    assert np.all(prof == 1.0)
+    assert np.all(ratio == 1.0)
+
+
+def test_rk4_without_exit_region_matches(ctx, O):
+    """Radii far outside R: everything free streams (bit-exact ratio 1 for outgoing relics)."""
+    req = W.plain_small().with_(r_kpc=np.array([5000.0, 20000.0]), y=np.geomspace(0.01, 100, 9), n_mu=7)
+    say("rk4 far radii")
+    prof, ratio, _ = gpu_ratios(ctx, req)
+    ref = O.solve(req)
+    assert rel(prof, ref["n_over_nbar"]).max() <= 1e-12
+    mu, _ = O.mu_grid(req)
+    out = np.tile(mu, req.n_r * req.n_y) <= 0
+    assert np.all(ratio[out] == 1.0)
+
+
+DP5_CASES = {
+    "seed0": lambda: W.shrink(W.plain_scale(0), 12, 24, 10),
+    "seed4_heavy": lambda: W.shrink(W.plain_scale(4), 12, 24, 10),
+    "seed5": lambda: W.shrink(W.plain_scale(5), 9, 20, 7),
+    "paper_model": lambda: W.shrink(W.plain_small(), 8, 16, 6).with_(
+        method="dp5", mass_kind="paper", M0=1e14, conc_kind="constant", c0=7.0, z_end=Z_FORM_PAPER, m_eV=0.3),
+    "delta200": lambda: W.shrink(W.plain_small(), 8, 16, 6).with_(method="dp5", geometry="delta200", M0=5e13),
+    "kappa_freezein": lambda: W.shrink(W.plain_small(), 8, 16, 6).with_(
+        method="dp5", kappa_kind="log", kappa_a=0.05, f0_kind="freeze_in", M0=2e14, m_eV=0.2),
+    "uncompensated": lambda: W.shrink(W.plain_small(), 6, 12, 6).with_(method="dp5", compensated=False, M0=1e13),
+    "ragged_1r_1mu": lambda: W.shrink(W.plain_scale(1), 1, 37, 1),
+    "user_mu": lambda: W.shrink(W.plain_scale(2), 5, 11, 3).with_(
+        mu=np.array([-0.9, -0.2, 0.1, 0.65]), w_mu=np.array([0.3, 0.6, 0.6, 0.5])),
+    "tight_rtol": lambda: W.shrink(W.plain_scale(3), 6, 16, 8).with_(rtol=1e-11),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DP5_CASES))
+def test_dp5_matches_oracle(ctx, O, name):
+    req = DP5_CASES[name]()
+    say(f"dp5 {name} n_traj={req.n_traj} M0={req.M0:.3g} m={req.m_eV}")
+    prof, ratio, stats = gpu_ratios(ctx, req)
+    ref = O.solve(req)
+    e = rel(prof, ref["n_over_nbar"])
+    d = rel(ratio, ref["ratio"])
+    acc_ref = int(ref["accepted"].sum())
+    print(f"n/nbar max rel {e.max():.2e}; ratio median {np.median(d):.2e} p99 {np.quantile(d, 0.99):.2e} "
+          f"max {d.max():.2e}; steps gpu {stats['accepted_steps']} oracle {acc_ref} "
+          f"free exits {stats['free_exits']}", flush=True)
+    assert e.max() <= 1e-8
+    assert np.median(d) <= 1e-10
+    assert stats["n_failed"] == 0
+    # the free-streaming exit only removes steps
+    assert stats["accepted_steps"] <= acc_ref * 1.01 + 10
+
+
+def test_dp5_full_size_sampled(ctx, O):
+    """Full 100 x 200 x 64 grid in the benchmark's launch; 400 sampled trajectories
+    integrated one by one on the oracle, plus the quadrature re-done on the CPU
+    from the GPU's own ratios."""
+    req = W.plain_scale(4)
+    say(f"dp5 full size seed 4 n_traj={req.n_traj}")
+    prof, ratio, stats = gpu_ratios(ctx, req)
+    assert stats["n_failed"] == 0
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(req.n_traj, 400, replace=False))
+    tr = O.trajectories(req, index=idx)
+    d = rel(ratio[idx], tr["ratio"])
+    print(f"sampled ratio rel diff median {np.median(d):.2e} p99 {np.quantile(d, 0.99):.2e} max {d.max():.2e}")
+    assert np.median(d) <= 1e-10
+    assert np.quantile(d, 0.95) <= 1e-7
+    # the reduction at full size: oracle quadrature over the GPU's ratios
+    cpu_prof = O.profile_from_ratio(req, ratio)
+    assert rel(prof, cpu_prof).max() <= 1e-13
+
+
+def test_max_steps_is_reported(ctx):
+    from paper_2410_08267_amd import nuhalo as N
+    req = W.shrink(W.plain_scale(4), 3, 8, 4).with_(max_steps=3)
+    say("dp5 max_steps=3")
+    out, stats, rc = ctx.solve(req, allow_failed=True)
+    assert rc == N.NH_ESTEPS
+    assert stats["n_failed"] > 0
+    assert np.all(np.isfinite(out))
+
+
+def test_async_on_torch_stream(ctx, O):
+    req = W.shrink(W.plain_scale(0), 6, 16, 8)
+    say("dp5 async on a side stream")
+    s = torch.cuda.Stream()
+    out = torch.zeros(req.n_r, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(s):
+        ctx.solve_async(req, out, stream=s)
+    s.synchronize()
+    ref = O.solve(req)["n_over_nbar"]
+    assert rel(out.cpu().numpy(), ref).max() <= 1e-8
