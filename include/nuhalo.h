@@ -219,6 +219,13 @@ int nh_solve_async(nh_context *ctx, const nh_request *req, double *d_out, double
  * and status (NH_OK, NH_ESTEPS or NH_ENONFINITE). */
 int nh_last_stats(nh_context *ctx, nh_stats *stats);
 
+/* Per-trajectory diagnostics of the last completed solve on this context
+ * (waits for it).  Host arrays of n_traj entries in trajectory order, each
+ * may be NULL: accepted and rejected step counts, and the status word
+ * (low byte 0 ok, 1 max_steps, 2 step underflow, 3 non-finite; bit 8 set
+ * when the trajectory left through the exact free-streaming exit). */
+int nh_last_trajectory_stats(nh_context *ctx, int *accepted, int *rejected, int *status);
+
 /* ---- batched solve ---------------------------------------------------- */
 
 /* Solve n_req heterogeneous requests in one persistent launch.

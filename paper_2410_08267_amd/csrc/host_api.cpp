@@ -20,12 +20,10 @@ namespace nh {
 hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
 hipError_t launch_free_all(long long n, const TrajOut &o, hipStream_t s);
 hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, hipStream_t s);
-int dp5_f64_blocks_per_cu(size_t lds_bytes);
 hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                          unsigned long long *counter, int grid, hipStream_t s);
-int dp5_f32c_blocks_per_cu(size_t lds_bytes);
+                          unsigned long long *counter, int n_cu, hipStream_t s);
 hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                           unsigned long long *counter, int grid, hipStream_t s);
+                           unsigned long long *counter, int n_cu, hipStream_t s);
 hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,
                                  int f0_kind, double *out, hipStream_t s);
 hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long *stats,
@@ -229,17 +227,11 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
     } else if (q->integ.method == NH_RK4) {
         HIPCHK(launch_rk4_f64(P, g, o, stream));
     } else {
-        const size_t lds = (size_t)P.n_tab * NCOL * sizeof(double);
         const bool f32 = q->integ.precision == NH_FP32C;
         if (f32) P.h_fp64 = ctx->h_fp64;
-        const int per_cu = f32 ? dp5_f32c_blocks_per_cu(lds) : dp5_f64_blocks_per_cu(lds);
-        long long grid = (long long)ctx->n_cu * per_cu;
-        const long long need = (n + 255) / 256;
-        if (grid > need) grid = need;
-        if (grid < 1) grid = 1;
         P.order = ctx->queue_order;
-        if (f32) HIPCHK(launch_dp5_f32c(P, g, o, counter, (int)grid, stream));
-        else HIPCHK(launch_dp5_f64(P, g, o, counter, (int)grid, stream));
+        if (f32) HIPCHK(launch_dp5_f32c(P, g, o, counter, ctx->n_cu, stream));
+        else HIPCHK(launch_dp5_f64(P, g, o, counter, ctx->n_cu, stream));
     }
     HIPCHK(hipEventRecord(ctx->ev_t1, stream));
     HIPCHK(launch_reduce_profile(P, g, d_ratio, q->f0.kind, d_out, stream));
@@ -389,6 +381,19 @@ int nh_last_stats(nh_context *ctx, nh_stats *stats)
 {
     if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
     return collect_stats(ctx, stats);
+}
+
+int nh_last_trajectory_stats(nh_context *ctx, int *accepted, int *rejected, int *status)
+{
+    if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
+    if (ctx->last_n_traj < 0) return set_err(ctx, NH_EINVAL, "no solve to report");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (ctx->pending) HIPCHK(hipEventSynchronize(ctx->ev_done));
+    const size_t n = (size_t)ctx->last_n_traj;
+    if (accepted) HIPCHK(hipMemcpy(accepted, ctx->acc.p, n * sizeof(int), hipMemcpyDeviceToHost));
+    if (rejected) HIPCHK(hipMemcpy(rejected, ctx->rej.p, n * sizeof(int), hipMemcpyDeviceToHost));
+    if (status) HIPCHK(hipMemcpy(status, ctx->status.p, n * sizeof(int), hipMemcpyDeviceToHost));
+    return NH_OK;
 }
 
 int nh_solve(nh_context *ctx, const nh_request *req, double *n_over_nbar, nh_stats *stats)

@@ -99,7 +99,9 @@ void Physics::coef(double u, double out[NCOL]) const
     const double M = mass(z);
     const double c = conc(z);
     out[COL_C] = c;
-    if (M == 0.0) {
+    if (M == 0.0 && geometry == NH_GEOM_DELTA200) {
+        // no halo and no radius at this epoch (validation keeps such epochs
+        // off the tabulated interval when they would be interpolated)
         out[COL_K] = 0.0;
         out[COL_KC] = 0.0;
         out[COL_INVS] = 0.0;
@@ -139,7 +141,9 @@ double Physics::r_exit(double u_end) const
     return Rmax;
 }
 
-int default_table_nodes() { return 1025; }
+// 3073 nodes over u in [-ln 5, 0]: cubic interpolation error below ~2e-13
+// relative for the columns of the benchmark halos (checked on the host).
+int default_table_nodes() { return 3073; }
 
 void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out)
 {
@@ -265,6 +269,8 @@ int validate(const nh_request *q, char *msg, size_t msg_len)
     if (!std::isfinite(it.z_end) || it.z_end <= 0) NH_BAD("z_end must be finite and > 0");
     if (h.geometry == NH_GEOM_PAPER && h.mass_kind != NH_MASS_ZERO && it.z_end > kCbrt200 - 1.0 + 1e-12)
         NH_BAD("paper geometry is defined up to z_i = 200^(1/3) - 1");
+    if (h.geometry == NH_GEOM_DELTA200 && h.mass_kind == NH_MASS_PAPER && !(it.z_end < h.z_form))
+        NH_BAD("delta200 geometry needs M(z_end) > 0: z_end < z_form");
     if (it.method == NH_RK4) {
         if (it.n_steps < 1 || it.n_steps > 1000000) NH_BAD("n_steps must be in [1, 1e6]");
         if (it.precision != NH_FP64) NH_BAD("RK4 runs in FP64 only");

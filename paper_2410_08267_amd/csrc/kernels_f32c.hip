@@ -5,16 +5,10 @@
 
 namespace nh {
 
-int dp5_f32c_blocks_per_cu(size_t lds_bytes)
-{
-    (void)lds_bytes;
-    return 1;
-}
-
 hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                           unsigned long long *counter, int grid, hipStream_t s)
+                           unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    (void)P; (void)g; (void)o; (void)counter; (void)grid; (void)s;
+    (void)P; (void)g; (void)o; (void)counter; (void)n_cu; (void)s;
     return hipErrorNotSupported;
 }
 

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
         x = g.r[k];
         vx = V * g.mu[l];
         vy = V * g.smu[l];
-        v0n = sqrt(vx * vx + vy * vy);
+        v0n = sqrt(norm2(vx, vy));
     }
     const double r_exit2 = P.r_exit * P.r_exit;
     bool active = valid;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
         }
     }
     if (valid) {
-        o.ratio[t] = sqrt(vx * vx + vy * vy) / v0n;
+        o.ratio[t] = sqrt(norm2(vx, vy)) / v0n;
         o.acc[t] = steps;
         o.rej[t] = 0;
         int st = ST_OK;
@@ -105,12 +105,21 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
 // Dormand-Prince 5(4), adaptive; persistent waves refill lanes from a queue
 // ---------------------------------------------------------------------------
 
+// One block per CU: the table takes most of the LDS, and the register budget
+// allows three waves per SIMD (five columns) or two (six columns).
 template <int NC>
-__global__ __launch_bounds__(256) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
-                                                 unsigned long long *counter)
+constexpr int dp5_block() { return NC == NCOL ? 512 : 768; }
+
+template <int NC>
+__global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
+                                                             unsigned long long *counter)
 {
     extern __shared__ double lds_tab[];
-    for (int i = threadIdx.x; i < P.n_tab * NCOL; i += blockDim.x) lds_tab[i] = g.tab[i];
+    // stage the first NC columns of every node, rows of NC doubles
+    for (int i = threadIdx.x; i < P.n_tab * NC; i += blockDim.x) {
+        const int node = i / NC, col = i - node * NC;
+        lds_tab[i] = g.tab[node * NCOL + col];
+    }
     __syncthreads();
 
     const TabCoef<NC> cf{lds_tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(256) void k_dp5_f64(TrajParams P, GridPtrs g, TrajO
                 const int k = (int)(kj / P.n_y);
                 const double V = g.y[j] * P.vfac;
                 const double vx0 = V * g.mu[l], vy0 = V * g.smu[l];
-                v0n = sqrt(vx0 * vx0 + vy0 * vy0);
+                v0n = sqrt(norm2(vx0, vy0));
                 dp5_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_end);
             } else {
                 t = -2;
@@ -147,7 +156,7 @@ __global__ __launch_bounds__(256) void k_dp5_f64(TrajParams P, GridPtrs g, TrajO
         if (t >= 0) {
             const int st = dp5_attempt(L, cf, ctl);
             if (st >= 0) {
-                o.ratio[t] = sqrt(L.vx * L.vx + L.vy * L.vy) / v0n;
+                o.ratio[t] = sqrt(norm2(L.vx, L.vy)) / v0n;
                 o.acc[t] = L.nacc;
                 o.rej[t] = L.nrej;
                 o.status[t] = st;
@@ -250,24 +259,32 @@ hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut 
     return hipGetLastError();
 }
 
-int dp5_f64_blocks_per_cu(size_t lds_bytes)
+template <int NC>
+static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                                unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dp5_f64<NCOL - 1>, 256, lds_bytes) !=
-        hipSuccess)
-        return 1;
-    return nb > 0 ? nb : 1;
+    constexpr int B = dp5_block<NC>();
+    const size_t lds = (size_t)P.n_tab * NC * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f64<NC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dp5_f64<NC>, B, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    long long grid = (long long)n_cu * per_cu;
+    const long long need = (P.n_traj + B - 1) / B;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_dp5_f64<NC>, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
+    return hipGetLastError();
 }
 
 hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                          unsigned long long *counter, int grid, hipStream_t s)
+                          unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    const size_t lds = (size_t)P.n_tab * NCOL * sizeof(double);
-    if (P.R_const > 0.0)
-        hipLaunchKernelGGL(k_dp5_f64<NCOL - 1>, dim3(grid), dim3(256), lds, s, P, g, o, counter);
-    else
-        hipLaunchKernelGGL(k_dp5_f64<NCOL>, dim3(grid), dim3(256), lds, s, P, g, o, counter);
-    return hipGetLastError();
+    if (P.R_const > 0.0) return launch_dp5_nc<NCOL - 1>(P, g, o, counter, n_cu, s);
+    return launch_dp5_nc<NCOL>(P, g, o, counter, n_cu, s);
 }
 
 hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,

@@ -33,9 +33,9 @@ __device__ __forceinline__ double rsq64(double a)
     return fma(0.5 * y, e, y);
 }
 
-// ln(w) for w >= 1: w = m 2^e with m in [sqrt(1/2), sqrt(2)), and
+// ln(w) for positive finite w: w = m 2^e with m in [sqrt(1/2), sqrt(2)), and
 // ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^21/21), s = (m-1)/(m+1), |s| <= 0.1716.
-__device__ __forceinline__ double log_ge1(double w)
+__device__ __forceinline__ double log_pos(double w)
 {
     int e = __builtin_amdgcn_frexp_exp(w);
     double m = __builtin_amdgcn_frexp_mant(w);        // [0.5, 1)
@@ -88,17 +88,45 @@ __device__ __forceinline__ double nfw_I(double q)
         p = fma(p, w, 1.0 / 2.0);
         return w * w * p;
     }
-    return log_ge1(opq) - q * inv;
+    return log_pos(opq) - q * inv;
 }
+
+// e^x for |x| < 700: x = k ln2 + r, |r| <= ln2/2, e^r by its Taylor series to r^13/13!
+// (next term < 4e-18), then scaled by 2^k.
+__device__ __forceinline__ double exp64(double x)
+{
+    const double k = rint(x * 1.4426950408889634);
+    double r = fma(-k, 6.93147180369123816490e-01, x);
+    r = fma(-k, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 6227020800.0;                 // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
+// |v|^2 with a fixed operation order (the final and initial speeds must round
+// identically so that an untouched velocity gives a ratio of exactly 1).
+__device__ __forceinline__ double norm2(double a, double b) { return fma(a, a, b * b); }
 
 // ---------------------------------------------------------------------------
 // coefficients and right-hand side
 // ---------------------------------------------------------------------------
 
 // Coefficients at u from the uniform table (4-point Lagrange, cubic).  Nodes
-// u_i = u0 + i du, i = 0..n-1, rows of NCOL doubles; the stencil is shifted
-// inward at both ends.  NC columns are interpolated (NC = NCOL - 1 when the
-// compensation radius R is constant and passed separately).
+// u_i = u0 + i du, i = 0..n-1, rows of NC doubles (the first NC columns; NC =
+// NCOL - 1 when the compensation radius R is constant and passed separately);
+// the stencil is shifted inward at both ends.
 template <int NC>
 __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int n_tab, double u0,
                                             double inv_du, double u, double c[NCOL])
@@ -112,10 +140,10 @@ __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int 
     const double wb = (pm * p1 * p2) * 0.5;
     const double wc = -(pm * p * p2) * 0.5;
     const double wd = (pm * p * p1) * (1.0 / 6.0);
-    const double *row = tab + (i - 1) * NCOL;
+    const double *row = tab + (i - 1) * NC;
 #pragma unroll
     for (int k = 0; k < NC; ++k)
-        c[k] = wa * row[k] + wb * row[NCOL + k] + wc * row[2 * NCOL + k] + wd * row[3 * NCOL + k];
+        c[k] = wa * row[k] + wb * row[NC + k] + wc * row[2 * NC + k] + wd * row[3 * NC + k];
 }
 
 // dY/du for Y = (x, y, vx, vy): dx/du = A v, dv/du = -g x with
@@ -171,16 +199,14 @@ __device__ __forceinline__ long long wave_claim(bool need, unsigned long long *c
     return (long long)(base + (unsigned long long)__popcll(below));
 }
 
-// Step-size factor of the controller, min(fmax, max(0.2, 0.9 err^(-1/5))) from
-// err^2.  Only the step length depends on it (acceptance compares err^2 <= 1 in
-// FP64), so it is evaluated in FP32 with the hardware log2/exp2.
-__device__ __forceinline__ double step_factor(double err2, double fmax)
+// Step-size factor of the controller, min(fmax, max(0.2, 0.9 err^(-1/5))),
+// from err^2 in FP64: adaptive step sequences are discontinuous in the
+// accept/reject decisions, so the factor is kept as exact as the rest.
+__device__ __forceinline__ double step_factor(double err2, double fcap)
 {
-    if (err2 == 0.0) return fmax;
-    const float l = __builtin_amdgcn_logf((float)err2);      // log2
-    float f = 0.9f * __builtin_amdgcn_exp2f(-0.1f * l);
-    f = fminf((float)fmax, fmaxf(0.2f, f));
-    return (double)f;
+    if (err2 == 0.0) return fcap;
+    const double f = 0.9 * exp64(-0.1 * log_pos(err2));
+    return fmin(fcap, fmax(0.2, f));
 }
 
 }  // namespace nh

@@ -95,6 +95,8 @@ _SIGNATURES = {
     "nh_solve_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_request), ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "nh_last_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_stats)]),
+    "nh_last_trajectory_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "nh_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(nh_request),
                                       ctypes.c_void_p, ctypes.POINTER(nh_stats), ctypes.c_void_p]),
     "nh_serve_set_budget": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t]),
@@ -299,6 +301,16 @@ class Context:
         rc = self._lib.nh_last_stats(self.h, ctypes.byref(st))
         self._check(rc, (NH_OK, NH_ESTEPS, NH_ENONFINITE) if allow_failed else (NH_OK,))
         return st.as_dict(), rc
+
+    def trajectory_stats(self, n_traj: int):
+        """(accepted, rejected, status) per trajectory of the last completed solve."""
+        acc = np.empty(n_traj, dtype=np.int32)
+        rej = np.empty(n_traj, dtype=np.int32)
+        st = np.empty(n_traj, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        self._check(self._lib.nh_last_trajectory_stats(self.h, acc.ctypes.data_as(ip),
+                                                       rej.ctypes.data_as(ip), st.ctypes.data_as(ip)))
+        return acc, rej, st
 
     def solve_batch(self, reqs, out: "torch.Tensor", stream=None):
         """Solve several requests in one persistent launch; out holds the concatenated profiles."""

@@ -131,3 +131,27 @@ def test_coefficients_reproduce_oracle_rhs(N, oracle_mod, name):
     scale = np.abs(want[:, 2:]).max(axis=1, keepdims=True) + 1e-300
     # force: the oracle evaluates deltaM by branches; the coefficient form clamps q at c
     assert np.all(np.abs(got[:, 2:] - want[:, 2:]) <= 1e-12 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("seed", [0, 4, 9])
+def test_table_resolution(N, seed):
+    """The Dormand-Prince kernels interpolate the coefficients cubically from
+    3073 nodes on [ln a_end, 0]; at that resolution every column is within
+    5e-13 (relative to its largest value) of the exact host coefficients."""
+    req = W.plain_scale(seed)
+    n_tab = 3073
+    u_end = -math.log1p(req.z_end)
+    du = -u_end / (n_tab - 1)
+    nodes = u_end + np.arange(n_tab) * du
+    nodes[-1] = 0.0
+    T = N.coefficients(req, nodes)
+    u = np.random.default_rng(seed).uniform(u_end, 0.0, 5000)
+    exact = N.coefficients(req, u)
+    s = (u - u_end) / du
+    i = np.clip(s.astype(int), 1, n_tab - 3)
+    p = s - i
+    w = [-(p * (p - 1) * (p - 2)) / 6, ((p + 1) * (p - 1) * (p - 2)) / 2,
+         -((p + 1) * p * (p - 2)) / 2, ((p + 1) * p * (p - 1)) / 6]
+    interp = sum(wk[:, None] * T[i + o] for wk, o in zip(w, (-1, 0, 1, 2)))
+    err = np.abs(interp - exact).max(axis=0) / np.abs(exact).max(axis=0)
+    assert np.all(err < 5e-13), err
