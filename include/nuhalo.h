@@ -197,6 +197,19 @@ int nh_context_destroy(nh_context *ctx);
  * request (NH_EINVAL).  Needs no GPU. */
 int nh_footprint_bytes(const nh_request *req, size_t *bytes);
 
+/* Context options (tuning; defaults in brackets).  Apply to later solves. */
+enum {
+    NH_OPT_QUEUE_ORDER   = 1,  /* persistent-kernel work order: [0] index order (a wave's
+                                  lanes share radius and momentum, so their u and table
+                                  reads stay close), 1 lowest momenta first */
+    NH_OPT_FREE_EXIT     = 2,  /* [1] stop a trajectory once it is beyond the compensation
+                                  radius and receding (exact: the force is zero from then on);
+                                  0 integrates every trajectory to z_end */
+    NH_OPT_FP64_BELOW_H  = 3,  /* NH_FP32C: attempted steps with |h| below this run in FP64 [1e-4] */
+    NH_OPT_TABLE_NODES   = 4   /* Dormand-Prince coefficient table nodes, 64..3073 [3073] */
+};
+int nh_set_option(nh_context *ctx, int option, double value);
+
 /* ---- plain solve ------------------------------------------------------ */
 
 /* Compute n/nbar for one request and wait for it.

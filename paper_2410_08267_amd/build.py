@@ -40,6 +40,9 @@ def common_flags():
     return [
         f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # three-operand v_fma_f64 instead of the two-address v_fmac_f64: the
+        # latter forces a v_mov pair for every FP64 constant addend (Horner steps)
+        "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
         "-Wall", "-Wno-unused-command-line-argument",
         # keep loop-invariant FP64 constants out of the register file: hoisting
         # them out of the trajectory loops costs more registers than it saves

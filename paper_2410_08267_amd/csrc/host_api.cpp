@@ -81,11 +81,11 @@ int ensure_pinned(nh_context *ctx, size_t bytes)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Staged inputs of one request: layout and host construction.
-Staged stage_layout(const nh_request *q)
+Staged stage_layout(const nh_request *q, int table_nodes)
 {
     Staged s{};
     const bool rk4 = q->integ.method == NH_RK4;
-    s.n_tab = rk4 ? 2 * q->integ.n_steps + 1 : default_table_nodes();
+    s.n_tab = rk4 ? 2 * q->integ.n_steps + 1 : (table_nodes > 0 ? table_nodes : default_table_nodes());
     size_t off = 0;
     s.off_tab = off;  off = align_up(off + (size_t)s.n_tab * NCOL * sizeof(double));
     s.off_r = off;    off = align_up(off + (size_t)q->grid.n_r * sizeof(double));
@@ -192,10 +192,11 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
     if ((rc = wait_pending(ctx)) != NH_OK) return rc;
     ctx->pending = false;
 
-    const Staged s = stage_layout(q);
+    const Staged s = stage_layout(q, ctx->table_nodes);
     if ((rc = ensure_pinned(ctx, s.bytes)) != NH_OK) return rc;
     TrajParams P;
     stage_fill(q, s, (char *)ctx->h_stage, P);
+    if (!ctx->free_exit && P.r_exit > 0.0) P.r_exit = -1.0;
     if ((rc = ensure_dev(ctx, ctx->blob, s.bytes)) != NH_OK) return rc;
     HIPCHK(hipMemcpyAsync(ctx->blob.p, ctx->h_stage, s.bytes, hipMemcpyHostToDevice, stream));
     const GridPtrs g = grid_ptrs(s, (const char *)ctx->blob.p);
@@ -301,9 +302,36 @@ int nh_footprint_bytes(const nh_request *req, size_t *bytes)
     if (!bytes) return set_err(nullptr, NH_EINVAL, "bytes is NULL");
     int rc = validate(req, g_err, sizeof(g_err));
     if (rc != NH_OK) return rc;
-    const Staged s = stage_layout(req);
+    const Staged s = stage_layout(req, 0);
     *bytes = s.bytes + (size_t)n_traj_of(req) * per_traj_bytes(req) + (size_t)req->grid.n_r * sizeof(double);
     return NH_OK;
+}
+
+int nh_set_option(nh_context *ctx, int option, double value)
+{
+    if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
+    if (!std::isfinite(value)) return set_err(ctx, NH_EINVAL, "option value must be finite");
+    switch (option) {
+    case NH_OPT_QUEUE_ORDER:
+        if (value != 0.0 && value != 1.0) return set_err(ctx, NH_EINVAL, "queue order is 0 or 1");
+        ctx->queue_order = (int)value;
+        return NH_OK;
+    case NH_OPT_FREE_EXIT:
+        if (value != 0.0 && value != 1.0) return set_err(ctx, NH_EINVAL, "free exit is 0 or 1");
+        ctx->free_exit = value != 0.0;
+        return NH_OK;
+    case NH_OPT_FP64_BELOW_H:
+        if (value < 0.0) return set_err(ctx, NH_EINVAL, "threshold must be >= 0");
+        ctx->h_fp64 = value;
+        return NH_OK;
+    case NH_OPT_TABLE_NODES:
+        if (value < 64 || value > 3073 || value != (double)(int)value)
+            return set_err(ctx, NH_EINVAL, "table nodes must be an integer in [64, 3073]");
+        ctx->table_nodes = (int)value;
+        return NH_OK;
+    default:
+        return set_err(ctx, NH_EINVAL, "unknown option %d", option);
+    }
 }
 
 int nh_gauss_legendre(int n, double *x, double *w)

@@ -37,9 +37,11 @@ struct nh_context {
     hipEvent_t ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
     bool pending = false;
     long long last_n_traj = -1;
-    // tunables (set by the autotuner / tests through nh_context_tune in the binding)
-    int queue_order = nh::ORDER_SLOW_FIRST;
-    double h_fp64 = 0.0;                             // FP32C: |h| below this runs in FP64
+    // tunables (nh_set_option)
+    int queue_order = nh::ORDER_NATURAL;
+    bool free_exit = true;
+    double h_fp64 = 1.0e-4;                          // FP32C: |h| below this runs in FP64
+    int table_nodes = 0;                             // 0: default_table_nodes()
     nh::ServeState *serve = nullptr;
 };
 
@@ -48,7 +50,7 @@ namespace nh {
 int set_err(nh_context *ctx, int code, const char *fmt, ...);
 int ensure_dev(nh_context *ctx, DevBuf &b, size_t bytes);
 int ensure_pinned(nh_context *ctx, size_t bytes);
-Staged stage_layout(const nh_request *q);
+Staged stage_layout(const nh_request *q, int table_nodes);
 void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P);
 GridPtrs grid_ptrs(const Staged &s, const char *dev);
 size_t per_traj_bytes(const nh_request *q);

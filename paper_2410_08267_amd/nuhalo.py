@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libnuhalo.so")
 
 NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ESTEPS = 0, -1, -2, -3, -4
 NH_ENONFINITE, NH_EBUSY, NH_ENOTREADY, NH_ENOTFOUND, NH_ECANCELED = -5, -6, -7, -8, -9
+OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4}
 
 _MASS = {"zero": 0, "paper": 1, "exponential": 2}
 _CONC = {"constant": 0, "power": 1}
@@ -108,6 +109,7 @@ _SIGNATURES = {
     "nh_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "nh_version": (ctypes.c_char_p, []),
     "nh_gauss_legendre": (ctypes.c_int, [ctypes.c_int, _dp, _dp]),
+    "nh_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
     "nh_coefficients": (ctypes.c_int, [ctypes.POINTER(nh_request), ctypes.c_int, _dp, _dp]),
 }
 
@@ -265,6 +267,9 @@ class Context:
         if rc not in allow:
             raise NhError(rc, self._lib.nh_last_error(self.h).decode())
         return rc
+
+    def set_option(self, name: str, value: float):
+        self._check(self._lib.nh_set_option(self.h, OPTIONS[name], float(value)))
 
     def last_error(self) -> str:
         return self._lib.nh_last_error(self.h).decode()

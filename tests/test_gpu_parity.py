@@ -229,3 +229,34 @@ def test_async_on_torch_stream(ctx, O):
     s.synchronize()
     ref = O.solve(req)["n_over_nbar"]
     assert rel(out.cpu().numpy(), ref).max() <= 1e-8
+
+
+def test_step_counts_match_oracle_without_exit(ctx, O):
+    """With the free-streaming exit off, the GPU takes the oracle's step sequence:
+    identical accepted/rejected counts for almost every trajectory."""
+    req = W.shrink(W.plain_scale(0), 10, 20, 8)
+    say("dp5 step counts, free exit off")
+    ctx.set_option("free_exit", 0)
+    try:
+        prof, ratio, stats = gpu_ratios(ctx, req)
+        acc, rej, st = ctx.trajectory_stats(req.n_traj)
+    finally:
+        ctx.set_option("free_exit", 1)
+    ref = O.solve(req)
+    same = (acc == ref["accepted"]) & (rej == ref["rejected"])
+    print(f"identical step counts: {same.mean():.4f}; free exits {int(((st & 256) != 0).sum())}")
+    assert np.all((st & 256) == 0)
+    assert same.mean() > 0.97
+    assert stats["accepted_steps"] == int(acc.sum())
+
+
+def test_queue_order_does_not_change_results(ctx):
+    req = W.shrink(W.plain_scale(4), 8, 16, 8)
+    say("dp5 queue order 0 vs 1")
+    a = gpu_ratios(ctx, req)[1]
+    ctx.set_option("queue_order", 1)
+    try:
+        b = gpu_ratios(ctx, req)[1]
+    finally:
+        ctx.set_option("queue_order", 0)
+    assert np.array_equal(a, b)
