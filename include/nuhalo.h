@@ -201,12 +201,15 @@ int nh_footprint_bytes(const nh_request *req, size_t *bytes);
 enum {
     NH_OPT_QUEUE_ORDER   = 1,  /* persistent-kernel work order: [0] index order (a wave's
                                   lanes share radius and momentum, so their u and table
-                                  reads stay close), 1 lowest momenta first */
+                                  reads stay close), 1 lowest momenta first, 2 momentum
+                                  index fastest (lanes share radius and direction) */
     NH_OPT_FREE_EXIT     = 2,  /* [1] stop a trajectory once it is beyond the compensation
                                   radius and receding (exact: the force is zero from then on);
                                   0 integrates every trajectory to z_end */
     NH_OPT_FP64_BELOW_H  = 3,  /* NH_FP32C: attempted steps with |h| below this run in FP64 [1e-4] */
-    NH_OPT_TABLE_NODES   = 4   /* Dormand-Prince coefficient table nodes, 64..3073 [3073] */
+    NH_OPT_TABLE_NODES   = 4,  /* Dormand-Prince coefficient table nodes, 64..3073 [3073] */
+    NH_OPT_BLOCK_THREADS = 5   /* Dormand-Prince threads per workgroup, multiple of 64 in
+                                  [64, 1024] [512]; one table copy in LDS per workgroup */
 };
 int nh_set_option(nh_context *ctx, int option, double value);
 

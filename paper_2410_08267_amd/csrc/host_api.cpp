@@ -231,6 +231,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
         const bool f32 = q->integ.precision == NH_FP32C;
         if (f32) P.h_fp64 = ctx->h_fp64;
         P.order = ctx->queue_order;
+        P.block = ctx->block_threads;
         if (f32) HIPCHK(launch_dp5_f32c(P, g, o, counter, ctx->n_cu, stream));
         else HIPCHK(launch_dp5_f64(P, g, o, counter, ctx->n_cu, stream));
     }
@@ -313,7 +314,8 @@ int nh_set_option(nh_context *ctx, int option, double value)
     if (!std::isfinite(value)) return set_err(ctx, NH_EINVAL, "option value must be finite");
     switch (option) {
     case NH_OPT_QUEUE_ORDER:
-        if (value != 0.0 && value != 1.0) return set_err(ctx, NH_EINVAL, "queue order is 0 or 1");
+        if (value != 0.0 && value != 1.0 && value != 2.0)
+            return set_err(ctx, NH_EINVAL, "queue order is 0, 1 or 2");
         ctx->queue_order = (int)value;
         return NH_OK;
     case NH_OPT_FREE_EXIT:
@@ -323,6 +325,11 @@ int nh_set_option(nh_context *ctx, int option, double value)
     case NH_OPT_FP64_BELOW_H:
         if (value < 0.0) return set_err(ctx, NH_EINVAL, "threshold must be >= 0");
         ctx->h_fp64 = value;
+        return NH_OK;
+    case NH_OPT_BLOCK_THREADS:
+        if (value < 64 || value > 1024 || value != (double)(64 * (int)(value / 64)))
+            return set_err(ctx, NH_EINVAL, "block threads must be a multiple of 64 in [64, 1024]");
+        ctx->block_threads = (int)value;
         return NH_OK;
     case NH_OPT_TABLE_NODES:
         if (value < 64 || value > 3073 || value != (double)(int)value)

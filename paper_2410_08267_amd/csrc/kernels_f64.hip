@@ -106,9 +106,9 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
 // ---------------------------------------------------------------------------
 
 // One block per CU: the table takes most of the LDS, and the register budget
-// allows three waves per SIMD (five columns) or two (six columns).
+// (<= 128 VGPRs) allows four waves per SIMD.
 template <int NC>
-constexpr int dp5_block() { return NC == NCOL ? 512 : 768; }
+constexpr int dp5_block() { return 1024; }
 
 template <int NC>
 __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
@@ -263,7 +263,7 @@ template <int NC>
 static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                 unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    constexpr int B = dp5_block<NC>();
+    const int B = P.block > 0 ? P.block : dp5_block<NC>();
     const size_t lds = (size_t)P.n_tab * NC * sizeof(double);
     hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f64<NC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

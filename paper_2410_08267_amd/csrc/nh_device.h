@@ -61,34 +61,43 @@ __device__ __forceinline__ double log_pos(double w)
     return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, lm));
 }
 
-// NFW mass integral I(q) = ln(1+q) - q/(1+q) (Eq. nfw).  Below q = 0.1 the
-// difference cancels; there I = sum_{k>=2} w^k / k with w = q/(1+q) (all terms
-// positive), truncated after k = 17.
+// NFW mass integral I(q) = ln(1+q) - q/(1+q) (Eq. nfw), branch-free for q >= 0.
+// ln(1+q) = e ln2 + 2 atanh(s) with 1+q = m 2^e, m in [sqrt(1/2), sqrt(2)),
+// s = (m-1)/(m+1).  When e = 0 (q < sqrt(2) - 1), s = q/(2+q) is formed from q
+// itself and q/(1+q) = 2s/(1+s), so
+//   I = 2 s^2/(1+s) + 2 (atanh(s) - s),                 (all terms positive)
+// otherwise
+//   I = e ln2 + 2s - q/(1+q) + 2 (atanh(s) - s),
+// with atanh(s) - s = s^3/3 + s^5/5 + ... + s^21/21 (|s| <= 0.1716).  Relative
+// error a few ulp for every q; the two forms differ only through selects, so a
+// wavefront whose lanes straddle the switch does not diverge.
 __device__ __forceinline__ double nfw_I(double q)
 {
-    const double opq = 1.0 + q;
-    const double inv = rcp64(opq);
-    if (q < 0.1) {
-        const double w = q * inv;
-        double p = 1.0 / 17.0;
-        p = fma(p, w, 1.0 / 16.0);
-        p = fma(p, w, 1.0 / 15.0);
-        p = fma(p, w, 1.0 / 14.0);
-        p = fma(p, w, 1.0 / 13.0);
-        p = fma(p, w, 1.0 / 12.0);
-        p = fma(p, w, 1.0 / 11.0);
-        p = fma(p, w, 1.0 / 10.0);
-        p = fma(p, w, 1.0 / 9.0);
-        p = fma(p, w, 1.0 / 8.0);
-        p = fma(p, w, 1.0 / 7.0);
-        p = fma(p, w, 1.0 / 6.0);
-        p = fma(p, w, 1.0 / 5.0);
-        p = fma(p, w, 1.0 / 4.0);
-        p = fma(p, w, 1.0 / 3.0);
-        p = fma(p, w, 1.0 / 2.0);
-        return w * w * p;
-    }
-    return log_pos(opq) - q * inv;
+    const double w0 = 1.0 + q;
+    int e = __builtin_amdgcn_frexp_exp(w0);
+    double m = __builtin_amdgcn_frexp_mant(w0);        // [0.5, 1)
+    const bool lowm = m < 0.70710678118654752;
+    m = lowm ? 2.0 * m : m;
+    e = lowm ? e - 1 : e;
+    const bool small = (e == 0);
+    const double s = (small ? q : m - 1.0) * rcp64(small ? 2.0 + q : m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double t3 = 2.0 * s * s2 * p;                  // 2 (atanh(s) - s)
+    const double inv = rcp64(small ? 1.0 + s : w0);
+    const double de = (double)e;
+    const double big = fma(de, 6.93147180369123816490e-01,
+                           fma(de, 1.90821492927058770002e-10, fma(-q, inv, 2.0 * s)));
+    return (small ? 2.0 * s2 * inv : big) + t3;
 }
 
 // e^x for |x| < 700: x = k ln2 + r, |r| <= ln2/2, e^r by its Taylor series to r^13/13!
@@ -179,6 +188,13 @@ __device__ __forceinline__ long long traj_of(long long p, const TrajParams &P)
         const long long q = p / P.n_mu;
         const long long k = q % P.n_r;
         const long long j = q / P.n_r;
+        return (k * P.n_y + j) * P.n_mu + l;
+    }
+    if (P.order == ORDER_Y_FASTEST) {
+        const long long j = p % P.n_y;
+        const long long q = p / P.n_y;
+        const long long l = q % P.n_mu;
+        const long long k = q / P.n_mu;
         return (k * P.n_y + j) * P.n_mu + l;
     }
     return p;

@@ -30,6 +30,7 @@ enum : int {
 enum : int {
     ORDER_NATURAL = 0,     // t = p
     ORDER_SLOW_FIRST = 1,  // p runs over (j, k, l) with l fastest: low-momentum relics first
+    ORDER_Y_FASTEST = 2,   // p runs over (k, l, j) with j fastest: a wave shares radius and direction
 };
 
 // Everything a trajectory kernel needs about one request, passed by value.
@@ -54,6 +55,7 @@ struct TrajParams {
     double r_exit;          // <= 0 disables
     double R_const;         // > 0: the compensation radius is this constant (no R column)
     int order;              // ORDER_*
+    int block;              // workgroup size of the persistent kernels
     // FP32-compensated form: steps with |h| below this run in FP64
     double h_fp64;
 };

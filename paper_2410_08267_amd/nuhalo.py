@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libnuhalo.so")
 
 NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ESTEPS = 0, -1, -2, -3, -4
 NH_ENONFINITE, NH_EBUSY, NH_ENOTREADY, NH_ENOTFOUND, NH_ECANCELED = -5, -6, -7, -8, -9
-OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4}
+OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4, "block_threads": 5}
 
 _MASS = {"zero": 0, "paper": 1, "exponential": 2}
 _CONC = {"constant": 0, "power": 1}
