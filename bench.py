@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32c", dest="fp32c", action="store_false",
+                    help="skip the FP32-compensated leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (counter calibration)")
     args = ap.parse_args()
@@ -83,6 +85,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2410_08267_amd import nuhalo as N
     from paper_2410_08267_amd import workloads as W
@@ -120,6 +123,38 @@ def main():
         kernel_ms.append(st["kernel_ms"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+
+    # FP32-compensated form on the same halos: profiles/s and deviation from FP64
+    prec = {}
+    if args.fp32c:
+        prof64 = []
+        for r in reqs:
+            ctx.solve_async(r, out, stream=stream)
+            ctx.last_stats()
+            prof64.append(out[:r.n_r].cpu().numpy().copy())
+        reqs32 = [r.with_(precision="fp32c") for r in reqs]
+        ctx.solve_async(W.plain_scale(1000).with_(precision="fp32c"), out, stream=stream)
+        ctx.last_stats()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        acc32 = f64 = 0
+        errs = []
+        for r, p64 in zip(reqs32, prof64):
+            ctx.solve_async(r, out, stream=stream)
+            st, _ = ctx.last_stats()
+            acc32 += st["accepted_steps"]
+            f64 += st["fp64_steps"]
+            errs.append(float(np.max(np.abs(out[:r.n_r].cpu().numpy() / p64 - 1.0))))
+        torch.cuda.synchronize()
+        dt32 = time.perf_counter() - t1
+        prec = {
+            "trajectory_steps_per_s": acc32 / dt32,
+            "profiles_per_s": len(reqs32) / dt32,
+            "ms_per_step": dt32 / len(reqs32) * 1e3,
+            "fp64_attempts": f64,
+            "max_rel_err_vs_fp64_path": max(errs),
+            "rtol": 1e-6,
+        }
 
     value = acc / dt
     kern_s = sum(kernel_ms) / 1e3
@@ -159,6 +194,8 @@ def main():
             "flop_per_attempt": FLOP_PER_DP5_ATTEMPT,
         },
     }
+    if prec:
+        line["fp32c"] = prec
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     ctx.close()

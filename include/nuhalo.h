@@ -206,7 +206,7 @@ enum {
     NH_OPT_FREE_EXIT     = 2,  /* [1] stop a trajectory once it is beyond the compensation
                                   radius and receding (exact: the force is zero from then on);
                                   0 integrates every trajectory to z_end */
-    NH_OPT_FP64_BELOW_H  = 3,  /* NH_FP32C: attempted steps with |h| below this run in FP64 [1e-4] */
+    NH_OPT_FP64_BELOW_H  = 3,  /* NH_FP32C: attempted steps with |h| below this run in FP64 [1e-5] */
     NH_OPT_TABLE_NODES   = 4,  /* Dormand-Prince coefficient table nodes, 64..3073 [3073] */
     NH_OPT_BLOCK_THREADS = 5   /* Dormand-Prince threads per workgroup, multiple of 64 in
                                   [64, 1024] [512]; one table copy in LDS per workgroup */

@@ -40,7 +40,7 @@ struct nh_context {
     // tunables (nh_set_option)
     int queue_order = nh::ORDER_NATURAL;
     bool free_exit = true;
-    double h_fp64 = 1.0e-4;                          // FP32C: |h| below this runs in FP64
+    double h_fp64 = 1.0e-5;                          // FP32C: |h| below this runs in FP64
     int table_nodes = 0;                             // 0: default_table_nodes()
     int block_threads = 512;                         // Dormand-Prince workgroup size
     nh::ServeState *serve = nullptr;

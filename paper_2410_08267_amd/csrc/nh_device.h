@@ -133,10 +133,10 @@ __device__ __forceinline__ double norm2(double a, double b) { return fma(a, a, b
 // ---------------------------------------------------------------------------
 
 // Coefficients at u from the uniform table (4-point Lagrange, cubic).  Nodes
-// u_i = u0 + i du, i = 0..n-1, rows of NC doubles (the first NC columns; NC =
-// NCOL - 1 when the compensation radius R is constant and passed separately);
-// the stencil is shifted inward at both ends.
-template <int NC>
+// u_i = u0 + i du, i = 0..n-1, rows of STRIDE doubles of which the first NC
+// columns are used (NC = NCOL - 1 when the compensation radius R is constant
+// and passed separately); the stencil is shifted inward at both ends.
+template <int NC, int STRIDE = NC>
 __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int n_tab, double u0,
                                             double inv_du, double u, double c[NCOL])
 {
@@ -149,10 +149,10 @@ __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int 
     const double wb = (pm * p1 * p2) * 0.5;
     const double wc = -(pm * p * p2) * 0.5;
     const double wd = (pm * p * p1) * (1.0 / 6.0);
-    const double *row = tab + (i - 1) * NC;
+    const double *row = tab + (i - 1) * STRIDE;
 #pragma unroll
     for (int k = 0; k < NC; ++k)
-        c[k] = wa * row[k] + wb * row[NC + k] + wc * row[2 * NC + k] + wd * row[3 * NC + k];
+        c[k] = wa * row[k] + wb * row[STRIDE + k] + wc * row[2 * STRIDE + k] + wd * row[3 * STRIDE + k];
 }
 
 // dY/du for Y = (x, y, vx, vy): dx/du = A v, dv/du = -g x with

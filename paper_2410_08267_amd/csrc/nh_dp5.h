@@ -28,15 +28,16 @@ constexpr double e6 = 11.0 / 84.0 - 187.0 / 2100.0;
 constexpr double e7 = 0.0 - 1.0 / 40.0;
 }  // namespace dp
 
-// Coefficient source: an FP64 table in LDS.  NC = 5 when R is constant.
-template <int NC>
+// Coefficient source: an FP64 table (LDS rows of NC doubles, or the staged
+// global copy with rows of NCOL).  NC = 5 when R is constant.
+template <int NC, int STRIDE = NC>
 struct TabCoef {
     const double *tab;
     int n_tab;
     double u0, inv_du, R_const;
     __device__ __forceinline__ void at(double u, double c[NCOL], double &R) const
     {
-        coef_interp<NC>(tab, n_tab, u0, inv_du, u, c);
+        coef_interp<NC, STRIDE>(tab, n_tab, u0, inv_du, u, c);
         R = (NC == NCOL) ? c[COL_R] : R_const;
     }
 };

@@ -1,0 +1,79 @@
+"""The FP32-compensated precision form against the FP64 oracle.
+
+Bound: max relative n/nbar error per radius <= 1e-4 against the oracle's
+reference integration (Dormand-Prince at rtol 1e-10).  The FP32 path
+integrates at max(rtol, 1e-6); attempts whose step falls below the promotion
+threshold run in FP64.  Also reported: the error on delta = n/nbar - 1, which
+is the harder measure where n/nbar is close to 1.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_08267_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_08267_amd import nuhalo as N
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = N.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+CASES = {
+    "seed0": lambda: W.shrink(W.precision(0), 12, 24, 10),
+    "seed4_heavy": lambda: W.shrink(W.precision(4), 12, 24, 10),
+    "seed5": lambda: W.shrink(W.precision(5), 10, 20, 8),
+    "seed9": lambda: W.shrink(W.precision(9), 10, 20, 8),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("h_fp64", [0.0, 1e-4])
+def test_fp32c_within_1e4_of_oracle(ctx, O, name, h_fp64):
+    req = CASES[name]()
+    say(f"fp32c {name} h_fp64={h_fp64} n_traj={req.n_traj} M0={req.M0:.3g} m={req.m_eV}")
+    ctx.set_option("fp64_below_h", h_fp64)
+    try:
+        got, stats, _ = ctx.solve(req)
+    finally:
+        ctx.set_option("fp64_below_h", 1e-5)
+    ref = O.solve(req.with_(precision="fp64", rtol=1e-10))["n_over_nbar"]
+    e = np.abs(got / ref - 1)
+    ed = np.abs((got - 1) - (ref - 1)) / np.maximum(np.abs(ref - 1), 1e-12)
+    frac64 = stats["fp64_steps"] / max(1, stats["accepted_steps"] + stats["rejected_steps"])
+    print(f"max rel err {e.max():.2e}; delta rel err max {ed.max():.2e}; fp64 attempts {frac64:.4f}; "
+          f"steps {stats['accepted_steps']}", flush=True)
+    assert stats["n_failed"] == 0
+    assert e.max() <= 1e-4
+    if h_fp64 == 0.0:
+        assert stats["fp64_steps"] == 0
+
+
+def test_fp32c_full_size(ctx, O):
+    """Full 1.28 M-trajectory profile; compared on radii re-computed by the oracle
+    on a subsample of (y, mu) through the GPU's FP64 profile at rtol 1e-10."""
+    req = W.precision(4)
+    say(f"fp32c full size seed 4 n_traj={req.n_traj}")
+    got, stats, _ = ctx.solve(req)
+    ref, _, _ = ctx.solve(req.with_(precision="fp64", rtol=1e-10))
+    e = np.abs(got / ref - 1)
+    print(f"fp32c vs fp64(rtol 1e-10) full profile: max rel err {e.max():.2e}; "
+          f"fp64 attempts {stats['fp64_steps']}", flush=True)
+    assert stats["n_failed"] == 0
+    assert e.max() <= 1e-4
