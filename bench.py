@@ -24,11 +24,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 FLOP of one attempted Dormand-Prince step as implemented
-# (FMA = 2, hardware rcp/rsq/sqrt = 1): six right-hand sides at 132 FLOP each
-# (interpolation of five coefficient columns 52, force and drift 80), stage
-# combinations 184, error norm and control 110.
-FLOP_PER_DP5_ATTEMPT = 6 * 132 + 184 + 110
+# Algorithmic FP64 FLOP of one attempted Dormand-Prince step as written (FMA =
+# 2; hardware rcp, rsq, sqrt, min, max = 1): six right-hand sides at 84 (of
+# which the NFW mass integral 56), five coefficient interpolations at 55,
+# stage combinations 184, error norm and step control 182 (the FP64 step
+# factor exp/log 77).  Hardware FP64 counters give 1272 per attempt at 88.5 %
+# lane utilisation, i.e. ~1126 per active lane.
+FLOP_PER_DP5_ATTEMPT = 6 * 84 + 5 * 55 + 184 + 182
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
 

@@ -166,7 +166,7 @@ GridPtrs grid_ptrs(const Staged &s, const char *dev)
 size_t per_traj_bytes(const nh_request *q)
 {
     (void)q;
-    return sizeof(double) + 4 * sizeof(int);
+    return sizeof(double) + sizeof(TrajStat);
 }
 
 #define HIPCHK(call)                                                                     \
@@ -206,10 +206,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
         if ((rc = ensure_dev(ctx, ctx->ratio, (size_t)n * sizeof(double))) != NH_OK) return rc;
         d_ratio = (double *)ctx->ratio.p;
     }
-    if ((rc = ensure_dev(ctx, ctx->acc, (size_t)n * sizeof(int))) != NH_OK) return rc;
-    if ((rc = ensure_dev(ctx, ctx->rej, (size_t)n * sizeof(int))) != NH_OK) return rc;
-    if ((rc = ensure_dev(ctx, ctx->status, (size_t)n * sizeof(int))) != NH_OK) return rc;
-    if ((rc = ensure_dev(ctx, ctx->fp64, (size_t)n * sizeof(int))) != NH_OK) return rc;
+    if ((rc = ensure_dev(ctx, ctx->stat, (size_t)n * sizeof(TrajStat))) != NH_OK) return rc;
     if ((rc = ensure_dev(ctx, ctx->small, 64 * sizeof(unsigned long long))) != NH_OK) return rc;
     unsigned long long *counter = (unsigned long long *)ctx->small.p;
     unsigned long long *stats = counter + 8;
@@ -217,10 +214,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
 
     TrajOut o;
     o.ratio = d_ratio;
-    o.acc = (int *)ctx->acc.p;
-    o.rej = (int *)ctx->rej.p;
-    o.status = (int *)ctx->status.p;
-    o.fp64 = (int *)ctx->fp64.p;
+    o.stat = (TrajStat *)ctx->stat.p;
 
     HIPCHK(hipEventRecord(ctx->ev_t0, stream));
     if (q->halo.mass_kind == NH_MASS_ZERO) {
@@ -392,8 +386,7 @@ int nh_context_destroy(nh_context *ctx)
     serve_shutdown(ctx);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&ctx->blob, &ctx->ratio, &ctx->acc, &ctx->rej, &ctx->status, &ctx->fp64,
-                      &ctx->small, &ctx->out})
+    for (DevBuf *b : {&ctx->blob, &ctx->ratio, &ctx->stat, &ctx->small, &ctx->out})
         if (b->p) (void)hipFree(b->p);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
@@ -425,9 +418,13 @@ int nh_last_trajectory_stats(nh_context *ctx, int *accepted, int *rejected, int 
     HIPCHK(hipSetDevice(ctx->device));
     if (ctx->pending) HIPCHK(hipEventSynchronize(ctx->ev_done));
     const size_t n = (size_t)ctx->last_n_traj;
-    if (accepted) HIPCHK(hipMemcpy(accepted, ctx->acc.p, n * sizeof(int), hipMemcpyDeviceToHost));
-    if (rejected) HIPCHK(hipMemcpy(rejected, ctx->rej.p, n * sizeof(int), hipMemcpyDeviceToHost));
-    if (status) HIPCHK(hipMemcpy(status, ctx->status.p, n * sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<TrajStat> h(n);
+    HIPCHK(hipMemcpy(h.data(), ctx->stat.p, n * sizeof(TrajStat), hipMemcpyDeviceToHost));
+    for (size_t t = 0; t < n; ++t) {
+        if (accepted) accepted[t] = h[t].acc;
+        if (rejected) rejected[t] = h[t].rej;
+        if (status) status[t] = h[t].status;
+    }
     return NH_OK;
 }
 

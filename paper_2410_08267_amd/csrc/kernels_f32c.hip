@@ -313,10 +313,7 @@ __global__ __launch_bounds__(512) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
             if (st >= 0) {
                 const double fx = L.vx, fy = L.vy;
                 o.ratio[t] = sqrt(norm2(fx, fy)) / v0n;
-                o.acc[t] = L.nacc;
-                o.rej[t] = L.nrej;
-                o.status[t] = st;
-                if (o.fp64) o.fp64[t] = L.n64;
+                o.stat[t] = TrajStat{L.nacc, L.nrej, st, L.n64};
                 t = -1;
             }
         }

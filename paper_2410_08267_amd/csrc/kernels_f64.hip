@@ -30,10 +30,7 @@ __global__ void k_free_all(long long n, TrajOut o)
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     o.ratio[t] = 1.0;
-    o.acc[t] = 0;
-    o.rej[t] = 0;
-    o.status[t] = ST_OK | ST_FREE_EXIT;
-    if (o.fp64) o.fp64[t] = 0;
+    o.stat[t] = TrajStat{0, 0, ST_OK | ST_FREE_EXIT, 0};
 }
 
 // ---------------------------------------------------------------------------
@@ -92,12 +89,9 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
     }
     if (valid) {
         o.ratio[t] = sqrt(norm2(vx, vy)) / v0n;
-        o.acc[t] = steps;
-        o.rej[t] = 0;
         int st = ST_OK;
         if (!(isfinite(x) && isfinite(y) && isfinite(vx) && isfinite(vy))) st = ST_NONFINITE;
-        o.status[t] = st | (freed ? ST_FREE_EXIT : 0);
-        if (o.fp64) o.fp64[t] = 0;
+        o.stat[t] = TrajStat{steps, 0, st | (freed ? ST_FREE_EXIT : 0), 0};
     }
 }
 
@@ -157,9 +151,7 @@ __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridP
             const int st = dp5_attempt(L, cf, ctl);
             if (st >= 0) {
                 o.ratio[t] = sqrt(norm2(L.vx, L.vy)) / v0n;
-                o.acc[t] = L.nacc;
-                o.rej[t] = L.nrej;
-                o.status[t] = st;
+                o.stat[t] = TrajStat{L.nacc, L.nrej, st, 0};
                 t = -1;
             }
         }
@@ -208,14 +200,14 @@ __global__ __launch_bounds__(256) void k_reduce_stats(long long n, TrajOut o,
     unsigned long long acc = 0, rej = 0, mx = 0, fail = 0, f64 = 0, fre = 0;
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (long long)gridDim.x * blockDim.x) {
-        const unsigned long long a = (unsigned)o.acc[t], r = (unsigned)o.rej[t];
+        const TrajStat ts = o.stat[t];
+        const unsigned long long a = (unsigned)ts.acc, r = (unsigned)ts.rej;
         acc += a;
         rej += r;
         mx = a + r > mx ? a + r : mx;
-        const int st = o.status[t];
-        fail += (st & 0xff) != ST_OK;
-        fre += (st & ST_FREE_EXIT) != 0;
-        if (o.fp64) f64 += (unsigned)o.fp64[t];
+        fail += (ts.status & 0xff) != ST_OK;
+        fre += (ts.status & ST_FREE_EXIT) != 0;
+        f64 += (unsigned)ts.fp64;
     }
     for (int off = 32; off > 0; off >>= 1) {
         acc += __shfl_down(acc, off);

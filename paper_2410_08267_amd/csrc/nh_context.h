@@ -31,7 +31,7 @@ struct nh_context {
     int n_cu = 0;
     char err[512] = "";
     hipStream_t stream = nullptr;                    // used by nh_solve
-    nh::DevBuf blob, ratio, acc, rej, status, fp64, small, out;
+    nh::DevBuf blob, ratio, stat, small, out;
     void *h_stage = nullptr;                         // pinned staging for the inputs
     size_t h_stage_cap = 0;
     hipEvent_t ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;

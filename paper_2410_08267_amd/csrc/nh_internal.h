@@ -71,12 +71,17 @@ struct GridPtrs {
     const double *wmu;      // n_mu
 };
 
+// Per-trajectory counters, written with one 16-byte store.
+struct alignas(16) TrajStat {
+    int acc;                // accepted steps
+    int rej;                // rejected steps
+    int status;             // ST_* word
+    int fp64;               // attempts run in FP64 (FP32C form)
+};
+
 struct TrajOut {
     double *ratio;          // n_traj: |v_end| / |v0|
-    int *acc;               // n_traj accepted steps
-    int *rej;               // n_traj rejected steps
-    int *status;            // n_traj status words
-    int *fp64;              // n_traj steps run in FP64 (FP32C) or nullptr
+    TrajStat *stat;         // n_traj
 };
 
 // Host-side physics of one request, evaluated in FP64 (tables, validation).
