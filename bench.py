@@ -32,7 +32,33 @@ sys.path.insert(0, ROOT)
 # lane utilisation, i.e. ~1126 per active lane.
 FLOP_PER_DP5_ATTEMPT = 6 * 84 + 5 * 55 + 184 + 182
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+# HBM bytes per k_dp5_f64 launch on this workload, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (seeds 0 and 1), each scaled by what the counter reads for a plain
+# 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the kernel
+# sources these hashes name; any change to them reports traffic as null.
+TRAFFIC_BYTES_PER_LAUNCH = 93211696
+TRAFFIC_SOURCES = {
+    "kernels_f64.hip": "81edee914d1b4482c38a623d1aeafbdafc095a74db2f73a2974ca9653b07f9bd",
+    "nh_dp5.h": "25c2778fd6db8cf6f248f33be254c5f009357bb3983e01db98bc5782eb40254a",
+    "nh_device.h": "01c6def04c76201070f07642643834edd324e64cfbf5e9f23444961c56df8aba",
+    "nh_internal.h": "46c1b4588344e70e0d1c4a9093e339b8f878ba5f1d0ce4415b60a3a5fec1b684",
+}
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
+
+
+def measured_traffic():
+    """Per-launch HBM bytes if the kernel sources are the ones profiled, else None."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2410_08267_amd", "csrc")
+    for name, digest in TRAFFIC_SOURCES.items():
+        try:
+            with open(os.path.join(csrc, name), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return TRAFFIC_BYTES_PER_LAUNCH
 
 
 def cpu_baseline(budget_s: float):
@@ -191,7 +217,8 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch",
             "kernel": "k_dp5_f64",
             "flop_per_attempt": FLOP_PER_DP5_ATTEMPT,
         },

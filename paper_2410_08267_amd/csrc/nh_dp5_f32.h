@@ -1,0 +1,204 @@
+// The FP32-compensated Dormand-Prince step of one trajectory, shared by the
+// plain and batched kernels.
+//
+// State: positions in FP32 with a Kahan compensation term each (the carried
+// rounding error of the accumulated position), velocities in FP32, time u and
+// step h in FP64 (u also indexes the coefficient table).  Right-hand sides,
+// stage sums, error norm and step control run in FP32 on an FP32 copy of the
+// FP64 coefficient table.
+#pragma once
+
+#include "nh_dp5.h"
+
+namespace nh {
+
+namespace dp32 {
+constexpr float c2 = 1.0f / 5.0f, c3 = 3.0f / 10.0f, c4 = 4.0f / 5.0f, c5 = 8.0f / 9.0f;
+constexpr float a21 = 1.0f / 5.0f;
+constexpr float a31 = 3.0f / 40.0f, a32 = 9.0f / 40.0f;
+constexpr float a41 = 44.0f / 45.0f, a42 = -56.0f / 15.0f, a43 = 32.0f / 9.0f;
+constexpr float a51 = 19372.0f / 6561.0f, a52 = -25360.0f / 2187.0f, a53 = 64448.0f / 6561.0f,
+                a54 = -212.0f / 729.0f;
+constexpr float a61 = 9017.0f / 3168.0f, a62 = -355.0f / 33.0f, a63 = 46732.0f / 5247.0f,
+                a64 = 49.0f / 176.0f, a65 = -5103.0f / 18656.0f;
+constexpr float b1 = 35.0f / 384.0f, b3 = 500.0f / 1113.0f, b4 = 125.0f / 192.0f,
+                b5 = -2187.0f / 6784.0f, b6 = 11.0f / 84.0f;
+constexpr float e1 = (float)(35.0 / 384.0 - 5179.0 / 57600.0);
+constexpr float e3 = (float)(500.0 / 1113.0 - 7571.0 / 16695.0);
+constexpr float e4 = (float)(125.0 / 192.0 - 393.0 / 640.0);
+constexpr float e5 = (float)(-2187.0 / 6784.0 + 92097.0 / 339200.0);
+constexpr float e6 = (float)(11.0 / 84.0 - 187.0 / 2100.0);
+constexpr float e7 = (float)(-1.0 / 40.0);
+}  // namespace dp32
+
+// I(q) in FP32, branch-free: for q < sqrt(2) - 1 the positive-term form
+// 2 s^2/(1+s) + 2 (s^3/3 + ... + s^9/9), s = q/(2+q); above it
+// ln(1+q) - q/(1+q) with the hardware log2 (mild cancellation there).
+__device__ __forceinline__ float nfw_I32(float q)
+{
+    const float s = q * __builtin_amdgcn_rcpf(2.0f + q);
+    const float s2 = s * s;
+    float p = fmaf(1.0f / 9.0f, s2, 1.0f / 7.0f);
+    p = fmaf(p, s2, 1.0f / 5.0f);
+    p = fmaf(p, s2, 1.0f / 3.0f);
+    const float small = 2.0f * s2 * __builtin_amdgcn_rcpf(1.0f + s) + 2.0f * s * s2 * p;
+    const float opq = 1.0f + q;
+    const float big = fmaf(__builtin_amdgcn_logf(opq), 0.69314718056f, -q * __builtin_amdgcn_rcpf(opq));
+    return q < 0.41421356f ? small : big;
+}
+
+__device__ __forceinline__ void rhs32(const float c[NCOL], float R, float x, float y, float vx,
+                                      float vy, float &dx, float &dy, float &dvx, float &dvy)
+{
+    const float r2 = fmaf(x, x, y * y);
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float q = fminf(r * c[COL_INVS], c[COL_C]);
+    const float I = nfw_I32(q);
+    float g = fmaf(c[COL_K] * I, ri * ri * ri, -c[COL_KC]);
+    g = (r2 > 0.0f && r < R) ? g : 0.0f;
+    dx = c[COL_A] * vx;
+    dy = c[COL_A] * vy;
+    dvx = -g * x;
+    dvy = -g * y;
+}
+
+// Cubic interpolation from the FP32 table (rows of NC floats); the node
+// index and fraction come from the FP64 time.
+template <int NC>
+struct TabCoef32 {
+    const float *tab;
+    int n_tab;
+    double u0, inv_du;
+    float R_const;
+    __device__ __forceinline__ void at(double u, float c[NCOL], float &R) const
+    {
+        const double sd = (u - u0) * inv_du;
+        int i = (int)sd;
+        i = i < 1 ? 1 : (i > n_tab - 3 ? n_tab - 3 : i);
+        const float p = (float)(sd - (double)i);
+        const float pm = p + 1.0f, p1 = p - 1.0f, p2 = p - 2.0f;
+        const float wa = -(p * p1 * p2) * (1.0f / 6.0f);
+        const float wb = (pm * p1 * p2) * 0.5f;
+        const float wc = -(pm * p * p2) * 0.5f;
+        const float wd = (pm * p * p1) * (1.0f / 6.0f);
+        const float *row = tab + (i - 1) * NC;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            c[k] = fmaf(wa, row[k], fmaf(wb, row[NC + k], fmaf(wc, row[2 * NC + k], wd * row[3 * NC + k])));
+        R = (NC == NCOL) ? c[COL_R] : R_const;
+    }
+};
+
+struct Lane32 {
+    float x, y, xc, yc, vx, vy;   // xc, yc: Kahan compensation of the positions
+    double u, h;
+    float k1x, k1y, k1u, k1v;
+    int nacc, nrej, natt, n64;
+    bool rej_prev;
+};
+
+// Compensated sum: s + c accumulates d with the rounding error carried in c.
+__device__ __forceinline__ void kahan_add(float &s, float &c, float d)
+{
+    const float y = __fadd_rn(d, c);
+    const float t = __fadd_rn(s, y);
+    c = __fsub_rn(y, __fsub_rn(t, s));
+    s = t;
+}
+
+struct DpCtl32 {
+    double u_end;
+    float rtol, atol_x, atol_v;
+    float r_exit2;
+    int max_steps;
+};
+
+// One FP32 attempt.  Returns -1 while the trajectory continues, else its status.
+template <class CF>
+__device__ __forceinline__ int dp5_attempt32(Lane32 &L, const CF &cf, const DpCtl32 &ctl)
+{
+    using namespace dp32;
+    if (L.natt >= ctl.max_steps) return ST_MAXSTEPS;
+    ++L.natt;
+    bool last = false;
+    double hd = L.h;
+    if (L.u + hd - ctl.u_end <= 0.0) {
+        hd = ctl.u_end - L.u;
+        last = true;
+    }
+    const float h = (float)hd;
+    const double u = L.u;
+    const float x = L.x + L.xc, y = L.y + L.yc, vx = L.vx, vy = L.vy;
+    const float k1x = L.k1x, k1y = L.k1y, k1u = L.k1u, k1v = L.k1v;
+    float c[NCOL], R;
+    float k2x, k2y, k2u, k2v, k3x, k3y, k3u, k3v, k4x, k4y, k4u, k4v;
+    float k5x, k5y, k5u, k5v, k6x, k6y, k6u, k6v, k7x, k7y, k7u, k7v;
+
+    cf.at(u + (double)c2 * hd, c, R);
+    rhs32(c, R, x + h * (a21 * k1x), y + h * (a21 * k1y), vx + h * (a21 * k1u), vy + h * (a21 * k1v),
+          k2x, k2y, k2u, k2v);
+    cf.at(u + (double)c3 * hd, c, R);
+    rhs32(c, R, x + h * (a31 * k1x + a32 * k2x), y + h * (a31 * k1y + a32 * k2y),
+          vx + h * (a31 * k1u + a32 * k2u), vy + h * (a31 * k1v + a32 * k2v), k3x, k3y, k3u, k3v);
+    cf.at(u + (double)c4 * hd, c, R);
+    rhs32(c, R, x + h * (a41 * k1x + a42 * k2x + a43 * k3x), y + h * (a41 * k1y + a42 * k2y + a43 * k3y),
+          vx + h * (a41 * k1u + a42 * k2u + a43 * k3u), vy + h * (a41 * k1v + a42 * k2v + a43 * k3v),
+          k4x, k4y, k4u, k4v);
+    cf.at(u + (double)c5 * hd, c, R);
+    rhs32(c, R, x + h * (a51 * k1x + a52 * k2x + a53 * k3x + a54 * k4x),
+          y + h * (a51 * k1y + a52 * k2y + a53 * k3y + a54 * k4y),
+          vx + h * (a51 * k1u + a52 * k2u + a53 * k3u + a54 * k4u),
+          vy + h * (a51 * k1v + a52 * k2v + a53 * k3v + a54 * k4v), k5x, k5y, k5u, k5v);
+    cf.at(u + hd, c, R);
+    rhs32(c, R, x + h * (a61 * k1x + a62 * k2x + a63 * k3x + a64 * k4x + a65 * k5x),
+          y + h * (a61 * k1y + a62 * k2y + a63 * k3y + a64 * k4y + a65 * k5y),
+          vx + h * (a61 * k1u + a62 * k2u + a63 * k3u + a64 * k4u + a65 * k5u),
+          vy + h * (a61 * k1v + a62 * k2v + a63 * k3v + a64 * k4v + a65 * k5v), k6x, k6y, k6u, k6v);
+    const float dxs = h * (b1 * k1x + b3 * k3x + b4 * k4x + b5 * k5x + b6 * k6x);
+    const float dys = h * (b1 * k1y + b3 * k3y + b4 * k4y + b5 * k5y + b6 * k6y);
+    const float x5 = x + dxs, y5 = y + dys;
+    const float vx5 = vx + h * (b1 * k1u + b3 * k3u + b4 * k4u + b5 * k5u + b6 * k6u);
+    const float vy5 = vy + h * (b1 * k1v + b3 * k3v + b4 * k4v + b5 * k5v + b6 * k6v);
+    rhs32(c, R, x5, y5, vx5, vy5, k7x, k7y, k7u, k7v);
+
+    const float ex = h * (e1 * k1x + e3 * k3x + e4 * k4x + e5 * k5x + e6 * k6x + e7 * k7x);
+    const float ey = h * (e1 * k1y + e3 * k3y + e4 * k4y + e5 * k5y + e6 * k6y + e7 * k7y);
+    const float eu = h * (e1 * k1u + e3 * k3u + e4 * k4u + e5 * k5u + e6 * k6u + e7 * k7u);
+    const float ev = h * (e1 * k1v + e3 * k3v + e4 * k4v + e5 * k5v + e6 * k6v + e7 * k7v);
+    const float sx = ctl.atol_x + ctl.rtol * sqrtf(fmaxf(fmaf(x, x, y * y), fmaf(x5, x5, y5 * y5)));
+    const float sv = ctl.atol_v + ctl.rtol * sqrtf(fmaxf(fmaf(vx, vx, vy * vy), fmaf(vx5, vx5, vy5 * vy5)));
+    const float isx = __builtin_amdgcn_rcpf(sx), isv = __builtin_amdgcn_rcpf(sv);
+    const float qx = ex * isx, qy = ey * isx, qu = eu * isv, qv = ev * isv;
+    const float err2 = 0.25f * (qx * qx + qy * qy + qu * qu + qv * qv);
+    if (!(err2 <= 1.0e30f)) return ST_NONFINITE;
+    if (err2 <= 1.0f) {
+        ++L.nacc;
+        L.u = last ? ctl.u_end : u + hd;
+        kahan_add(L.x, L.xc, dxs);
+        kahan_add(L.y, L.yc, dys);
+        L.vx = vx5;
+        L.vy = vy5;
+        L.k1x = k7x;
+        L.k1y = k7y;
+        L.k1u = k7u;
+        L.k1v = k7v;
+        if (last) return ST_OK;
+        if (ctl.r_exit2 >= 0.0f && fmaf(x5, x5, y5 * y5) >= ctl.r_exit2 && fmaf(x5, vx5, y5 * vy5) <= 0.0f)
+            return ST_OK | ST_FREE_EXIT;
+        float f = err2 == 0.0f ? 5.0f
+                               : 0.9f * __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf(err2));
+        f = fminf(L.rej_prev ? 1.0f : 5.0f, fmaxf(0.2f, f));
+        L.h = hd * (double)f;
+        L.rej_prev = false;
+    } else {
+        ++L.nrej;
+        const float f = 0.9f * __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf(err2));
+        L.h = hd * (double)fminf(5.0f, fmaxf(0.2f, f));
+        L.rej_prev = true;
+    }
+    if (fabs(L.h) <= 8.881784197001252e-16 * fmax(1.0, fabs(L.u))) return ST_UNDERFLOW;
+    return -1;
+}
+
+}  // namespace nh
