@@ -43,6 +43,7 @@ TRAFFIC_SOURCES = {
     "nh_dp5.h": "25c2778fd6db8cf6f248f33be254c5f009357bb3983e01db98bc5782eb40254a",
     "nh_device.h": "01c6def04c76201070f07642643834edd324e64cfbf5e9f23444961c56df8aba",
     "nh_internal.h": "46c1b4588344e70e0d1c4a9093e339b8f878ba5f1d0ce4415b60a3a5fec1b684",
+    "../build.py": None,
 }
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
 
@@ -52,6 +53,8 @@ def measured_traffic():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2410_08267_amd", "csrc")
     for name, digest in TRAFFIC_SOURCES.items():
+        if digest is None:
+            return None
         try:
             with open(os.path.join(csrc, name), "rb") as f:
                 if hashlib.sha256(f.read()).hexdigest() != digest:
@@ -94,6 +97,39 @@ def cpu_baseline(budget_s: float):
     }
 
 
+def batched_leg(ctx, n_req: int):
+    """The batched workload (n_req heterogeneous requests, one persistent launch
+    each) in FP64 and in the FP32-compensated form: profiles/s of whole batches."""
+    import torch
+    from paper_2410_08267_amd import workloads as W
+    res = {"requests": n_req,
+           "workload": ("batched: M0 log-uniform 1e11-1e15 Msun, c0 U[4,15], m U[0.02,0.3] eV, "
+                        "N_r U{16..128} x N_y U{32..256} x N_mu U{16..64}, Dormand-Prince rtol 1e-8, z 0->4")}
+    for prec in ("fp64", "fp32c"):
+        warm = W.batched(999, n_req=16, prec=prec)
+        reqs = W.batched(0, n_req=n_req, prec=prec)
+        n_traj = sum(r.n_traj for r in reqs)
+        out = torch.empty(sum(r.n_r for r in reqs), dtype=torch.float64, device="cuda")
+        ctx.solve_batch(warm, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, _ = ctx.solve_batch(reqs, out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        acc = sum(st["accepted_steps"] for st in stats)
+        res[prec] = {
+            "profiles_per_s": n_req / dt,
+            "seconds": dt,
+            "kernel_ms": stats[0]["kernel_ms"],
+            "trajectories": n_traj,
+            "trajectory_steps_per_s": acc / dt,
+            "failed": sum(st["n_failed"] for st in stats),
+        }
+        print(f"[bench] batched {prec}: {n_req} requests {n_traj} trajectories in {dt:.2f} s", file=sys.stderr,
+              flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +139,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32c", dest="fp32c", action="store_false",
                     help="skip the FP32-compensated leg")
+    ap.add_argument("--no-batched", dest="batched", action="store_false",
+                    help="skip the batched leg (heterogeneous requests in one launch)")
+    ap.add_argument("--batch-requests", type=int, default=512)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (counter calibration)")
     args = ap.parse_args()
@@ -184,6 +223,10 @@ def main():
             "rtol": 1e-6,
         }
 
+    batched = {}
+    if args.batched:
+        batched = batched_leg(ctx, args.batch_requests)
+
     value = acc / dt
     kern_s = sum(kernel_ms) / 1e3
     achieved = FLOP_PER_DP5_ATTEMPT * (acc + rej) / kern_s / 1e12
@@ -225,6 +268,8 @@ def main():
     }
     if prec:
         line["fp32c"] = prec
+    if batched:
+        line["batched"] = batched
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     ctx.close()

@@ -207,9 +207,18 @@ enum {
                                   radius and receding (exact: the force is zero from then on);
                                   0 integrates every trajectory to z_end */
     NH_OPT_FP64_BELOW_H  = 3,  /* NH_FP32C: attempted steps with |h| below this run in FP64 [1e-5] */
-    NH_OPT_TABLE_NODES   = 4,  /* Dormand-Prince coefficient table nodes, 64..3073 [3073] */
-    NH_OPT_BLOCK_THREADS = 5   /* Dormand-Prince threads per workgroup, multiple of 64 in
-                                  [64, 1024] [512]; one table copy in LDS per workgroup */
+    NH_OPT_TABLE_NODES   = 4,  /* Dormand-Prince coefficient table nodes, 64..3073, or 0 for the
+                                  default [0]: 3073, or for the batched and serving forms as many
+                                  as their LDS slots hold (a larger value is NH_EINVAL there) */
+    NH_OPT_BLOCK_THREADS = 5,  /* Dormand-Prince threads per workgroup, multiple of 64 in
+                                  [64, 1024] [512]; one table copy in LDS per workgroup
+                                  (the batched and serving forms use at most 512) */
+    NH_OPT_BATCH_SLOTS   = 6   /* batched and serving forms: request tables per workgroup in
+                                  LDS, 1 or 2, or 0 for the default [0]: 1 for FP64 (3073
+                                  nodes, the plain form's table; a workgroup drains before it
+                                  changes request), 2 for FP32C (3073 FP32 nodes each; lanes
+                                  keep integrating while the next table loads).  Two FP64
+                                  tables hold at most 2044 (constant R) or 1703 nodes. */
 };
 int nh_set_option(nh_context *ctx, int option, double value);
 

@@ -21,9 +21,11 @@ LIB = os.path.join(HERE, "libnuhalo.so")
 SOURCES = [
     "host_physics.cpp",
     "host_api.cpp",
+    "host_batch.cpp",
     "host_serve.cpp",
     "kernels_f64.hip",
     "kernels_f32c.hip",
+    "kernels_batch.hip",
 ]
 
 ARCH = "gfx950"
@@ -44,6 +46,9 @@ def common_flags():
         # latter forces a v_mov pair for every FP64 constant addend (Horner steps)
         "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
         "-Wall", "-Wno-unused-command-line-argument",
+        # fuse a*b+c only within one source expression: the same per-trajectory
+        # code then rounds identically in the plain and the batched kernels
+        "-ffp-contract=on",
         # keep loop-invariant FP64 constants out of the register file: hoisting
         # them out of the trajectory loops costs more registers than it saves
         "-mllvm", "-disable-machine-licm",

@@ -14,20 +14,9 @@
 #include <vector>
 
 #include "nh_context.h"
+#include "nh_launch.h"
 
 namespace nh {
-
-hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
-hipError_t launch_free_all(long long n, const TrajOut &o, hipStream_t s);
-hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, hipStream_t s);
-hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                          unsigned long long *counter, int n_cu, hipStream_t s);
-hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                           unsigned long long *counter, int n_cu, hipStream_t s);
-hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,
-                                 int f0_kind, double *out, hipStream_t s);
-hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long *stats,
-                               hipStream_t s);
 
 thread_local char g_err[512] = "";
 
@@ -168,13 +157,6 @@ size_t per_traj_bytes(const nh_request *q)
     (void)q;
     return sizeof(double) + sizeof(TrajStat);
 }
-
-#define HIPCHK(call)                                                                     \
-    do {                                                                                 \
-        hipError_t e_ = (call);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return set_err(ctx, NH_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));     \
-    } while (0)
 
 int wait_pending(nh_context *ctx)
 {
@@ -326,9 +308,14 @@ int nh_set_option(nh_context *ctx, int option, double value)
         ctx->block_threads = (int)value;
         return NH_OK;
     case NH_OPT_TABLE_NODES:
-        if (value < 64 || value > 3073 || value != (double)(int)value)
-            return set_err(ctx, NH_EINVAL, "table nodes must be an integer in [64, 3073]");
+        if (value != 0.0 && (value < 64 || value > 3073 || value != (double)(int)value))
+            return set_err(ctx, NH_EINVAL, "table nodes must be 0 (default) or an integer in [64, 3073]");
         ctx->table_nodes = (int)value;
+        return NH_OK;
+    case NH_OPT_BATCH_SLOTS:
+        if (value != 0.0 && value != 1.0 && value != 2.0)
+            return set_err(ctx, NH_EINVAL, "batch slots is 0 (default), 1 or 2");
+        ctx->batch_slots = (int)value;
         return NH_OK;
     default:
         return set_err(ctx, NH_EINVAL, "unknown option %d", option);
@@ -386,7 +373,7 @@ int nh_context_destroy(nh_context *ctx)
     serve_shutdown(ctx);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&ctx->blob, &ctx->ratio, &ctx->stat, &ctx->small, &ctx->out})
+    for (DevBuf *b : {&ctx->blob, &ctx->ratio, &ctx->stat, &ctx->small, &ctx->out, &ctx->bctr})
         if (b->p) (void)hipFree(b->p);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);

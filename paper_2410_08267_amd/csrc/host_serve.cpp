@@ -11,13 +11,6 @@ using namespace nh;
 
 extern "C" {
 
-int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d_out,
-                   nh_stats *stats, void *stream)
-{
-    (void)n_req; (void)reqs; (void)d_out; (void)stats; (void)stream;
-    return set_err(ctx, NH_EINVAL, "nh_solve_batch: not built yet");
-}
-
 int nh_serve_set_budget(nh_context *ctx, size_t bytes)
 {
     (void)bytes;

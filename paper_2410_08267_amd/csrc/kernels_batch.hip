@@ -1,0 +1,487 @@
+// Slice kernels of the batched and serving forms (FP64 and FP32-compensated)
+// and the reductions over many requests.
+//
+// Every lane runs the same per-trajectory code as the plain kernels (start,
+// Dormand-Prince attempt, outputs); only the source of its request parameters
+// differs: a descriptor in HBM and one of the workgroup's two LDS table slots
+// (see nh_batch.h for the scheduling).
+#include <hip/hip_runtime.h>
+
+#include "nh_batch.h"
+#include "nh_dp5_f32.h"
+#include "nh_reduce.h"
+
+namespace nh {
+
+// FP64 coefficients from rows of STRIDE doubles of which the first NC columns
+// are interpolated; R comes from its column for requests with a moving
+// compensation radius (nc == NCOL, possible only when NC == NCOL), else it is
+// the request's constant.
+template <int NC, int STRIDE = NC>
+struct TabCoefB {
+    const double *tab;
+    int nc, n_tab;
+    double u0, inv_du, R_const;
+    __device__ __forceinline__ void at(double u, double c[NCOL], double &R) const
+    {
+        coef_interp<NC, STRIDE>(tab, n_tab, u0, inv_du, u, c);
+        R = (NC == NCOL && nc == NCOL) ? c[COL_R] : R_const;
+    }
+};
+
+// The same from an FP32 table slot (rows of NC floats).
+template <int NC>
+struct TabCoef32B {
+    const float *tab;
+    int nc, n_tab;
+    double u0, inv_du;
+    float R_const;
+    __device__ __forceinline__ void at(double u, float c[NCOL], float &R) const
+    {
+        const Stencil4f w = stencil32_at(n_tab, u0, inv_du, u);
+        const float *row = tab + w.row * NC;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) c[k] = stencil32_col(w, row, NC, k);
+        R = (NC == NCOL && nc == NCOL) ? c[COL_R] : R_const;
+    }
+};
+
+// Copy the first NC columns of request q's table rows into a slot (rows of
+// NC), by the threads first, first + step, ...
+template <int NC, class T>
+__device__ __forceinline__ void copy_table(T *dst, const BatchReq &q, int first, int step)
+{
+    const int n = q.P.n_tab * NC;
+    const double *src = q.g.tab;
+    for (int i = first; i < n; i += step) {
+        const int node = i / NC, col = i - node * NC;
+        dst[i] = (T)src[node * NCOL + col];
+    }
+}
+
+// Initial position and velocity of trajectory t = (k n_y + j) n_mu + l.
+__device__ __forceinline__ void initial_state(const BatchReq &q, long long t, double &x0, double &vx0,
+                                              double &vy0)
+{
+    const TrajParams &P = q.P;
+    const int l = (int)(t % P.n_mu);
+    const long long kj = t / P.n_mu;
+    const int j = (int)(kj % P.n_y);
+    const int k = (int)(kj / P.n_y);
+    const double V = q.g.y[j] * P.vfac;
+    vx0 = V * q.g.mu[l];
+    vy0 = V * q.g.smu[l];
+    x0 = q.g.r[k];
+}
+
+__device__ __forceinline__ void finish_free(const BatchReq &q, long long t)
+{
+    q.o.ratio[t] = 1.0;
+    q.o.stat[t] = TrajStat{0, 0, ST_OK | ST_FREE_EXIT, 0};
+}
+
+__device__ __forceinline__ unsigned long long pack2f(float a, float b)
+{
+    return ((unsigned long long)__float_as_uint(a) << 32) | __float_as_uint(b);
+}
+__device__ __forceinline__ unsigned long long pack2i(int a, int b)
+{
+    return ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
+}
+__device__ __forceinline__ float hi_f(unsigned long long w) { return __uint_as_float((unsigned)(w >> 32)); }
+__device__ __forceinline__ float lo_f(unsigned long long w) { return __uint_as_float((unsigned)w); }
+__device__ __forceinline__ int hi_i(unsigned long long w) { return (int)(unsigned)(w >> 32); }
+__device__ __forceinline__ int lo_i(unsigned long long w) { return (int)(unsigned)w; }
+__device__ __forceinline__ unsigned long long bits(double d) { return (unsigned long long)__double_as_longlong(d); }
+__device__ __forceinline__ double dbl(unsigned long long w) { return __longlong_as_double((long long)w); }
+
+__device__ __forceinline__ void pack64(const Lane64 &L, double v0n, LaneSave &s)
+{
+    s.w[0] = bits(L.x);
+    s.w[1] = bits(L.y);
+    s.w[2] = bits(L.vx);
+    s.w[3] = bits(L.vy);
+    s.w[4] = bits(L.u);
+    s.w[5] = bits(L.h);
+    s.w[6] = bits(L.k1x);
+    s.w[7] = bits(L.k1y);
+    s.w[8] = bits(L.k1u);
+    s.w[9] = bits(L.k1v);
+    s.w[10] = bits(v0n);
+    s.w[11] = pack2i(L.nacc, L.nrej);
+    s.w[12] = pack2i(L.natt, L.rej_prev ? 1 : 0);
+}
+__device__ __forceinline__ void unpack64(const LaneSave &s, Lane64 &L, double &v0n)
+{
+    L.x = dbl(s.w[0]);
+    L.y = dbl(s.w[1]);
+    L.vx = dbl(s.w[2]);
+    L.vy = dbl(s.w[3]);
+    L.u = dbl(s.w[4]);
+    L.h = dbl(s.w[5]);
+    L.k1x = dbl(s.w[6]);
+    L.k1y = dbl(s.w[7]);
+    L.k1u = dbl(s.w[8]);
+    L.k1v = dbl(s.w[9]);
+    v0n = dbl(s.w[10]);
+    L.nacc = hi_i(s.w[11]);
+    L.nrej = lo_i(s.w[11]);
+    L.natt = hi_i(s.w[12]);
+    L.rej_prev = lo_i(s.w[12]) != 0;
+}
+
+__device__ __forceinline__ void pack32(const Lane32 &L, double v0n, LaneSave &s)
+{
+    s.w[0] = pack2f(L.x, L.y);
+    s.w[1] = pack2f(L.xc, L.yc);
+    s.w[2] = pack2f(L.vx, L.vy);
+    s.w[3] = bits(L.u);
+    s.w[4] = bits(L.h);
+    s.w[5] = pack2f(L.k1x, L.k1y);
+    s.w[6] = pack2f(L.k1u, L.k1v);
+    s.w[7] = bits(v0n);
+    s.w[8] = pack2i(L.nacc, L.nrej);
+    s.w[9] = pack2i(L.natt, L.n64);
+    s.w[10] = L.rej_prev ? 1ull : 0ull;
+}
+__device__ __forceinline__ void unpack32(const LaneSave &s, Lane32 &L, double &v0n)
+{
+    L.x = hi_f(s.w[0]);
+    L.y = lo_f(s.w[0]);
+    L.xc = hi_f(s.w[1]);
+    L.yc = lo_f(s.w[1]);
+    L.vx = hi_f(s.w[2]);
+    L.vy = lo_f(s.w[2]);
+    L.u = dbl(s.w[3]);
+    L.h = dbl(s.w[4]);
+    L.k1x = hi_f(s.w[5]);
+    L.k1y = lo_f(s.w[5]);
+    L.k1u = hi_f(s.w[6]);
+    L.k1v = lo_f(s.w[6]);
+    v0n = dbl(s.w[7]);
+    L.nacc = hi_i(s.w[8]);
+    L.nrej = lo_i(s.w[8]);
+    L.natt = hi_i(s.w[9]);
+    L.n64 = lo_i(s.w[9]);
+    L.rej_prev = s.w[10] != 0ull;
+}
+
+// Per-lane parameters of a trajectory of request q whose table sits in `slot`.
+template <int NC>
+struct Lane64Params {
+    TabCoefB<NC> cf;
+    DpCtl ctl;
+};
+template <int NC>
+__device__ __forceinline__ void setup64(const BatchReq &q, const double *slot, Lane64Params<NC> &p)
+{
+    const TrajParams &P = q.P;
+    p.cf = TabCoefB<NC>{slot, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
+    p.ctl.u_end = P.u_end;
+    p.ctl.rtol = P.rtol;
+    p.ctl.atol_x = P.atol_x;
+    p.ctl.atol_v = P.atol_v;
+    p.ctl.r_exit2 = P.r_exit > 0.0 ? P.r_exit * P.r_exit : -1.0;
+    p.ctl.max_steps = (int)P.max_steps;
+}
+
+template <int NC>
+struct Lane32Params {
+    TabCoef32B<NC> cf;
+    TabCoefB<NC, NCOL> cf64;    // the promoted FP64 attempts read the FP64 table from HBM
+    DpCtl32 ctl;
+    DpCtl ctl64;
+    double h_fp64;
+};
+template <int NC>
+__device__ __forceinline__ void setup32(const BatchReq &q, const float *slot, Lane32Params<NC> &p)
+{
+    const TrajParams &P = q.P;
+    p.cf = TabCoef32B<NC>{slot, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30)};
+    p.cf64 = TabCoefB<NC, NCOL>{q.g.tab, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
+    f32c_controls(P, p.ctl, p.ctl64);
+    p.h_fp64 = P.h_fp64;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 slice kernel
+// ---------------------------------------------------------------------------
+
+template <int NC, int SLOTS>
+__global__ __launch_bounds__(512) void k_slice_f64(SliceArgs A)
+{
+    extern __shared__ double lds64[];
+    __shared__ WgSched S;
+    const int slot_n = A.n_tab * NC;
+    if (threadIdx.x == 0) sched_init(S, A);
+    __syncthreads();
+    for (int s = 0; s < SLOTS; ++s)
+        if (S.slot_req[s] >= 0) copy_table<NC>(lds64 + s * slot_n, A.reqs[S.slot_req[s]], threadIdx.x, blockDim.x);
+
+    long long t = -1;
+    int rq = 0, sl = 0;
+    double v0n = 1.0;
+    Lane64 L{};
+    Lane64Params<NC> lp{};
+    LaneSave *const my = A.lane_save ? A.lane_save + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) : nullptr;
+    if (A.resume && my) {
+        const LaneSave sv = *my;
+        if (sv.t >= 0 && !A.reqs[sv.req].retired) {
+            t = sv.t;
+            rq = sv.req;
+            sl = sv.slot;
+            unpack64(sv, L, v0n);
+            setup64(A.reqs[rq], lds64 + sl * slot_n, lp);
+            __hip_atomic_fetch_add(&S.active[sl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+
+    const unsigned long long t0 = wall_clock64();
+    bool expired = false;
+    for (;;) {
+        if (A.budget_ticks >= 0 && !expired) expired = (long long)(wall_clock64() - t0) > A.budget_ticks;
+        const unsigned long long mask = __ballot(t < 0 && !expired);
+        if (mask != 0ull && !__hip_atomic_load(&S.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            int r, s;
+            long long p;
+            wave_acquire<SLOTS>(S, A, mask, r, p, s, [&](int slot, int req) {
+                copy_table<NC>(lds64 + slot * slot_n, A.reqs[req], (int)__lane_id(), 64);
+            });
+            if (r >= 0) {
+                const BatchReq &q = A.reqs[r];
+                rq = r;
+                sl = s;
+                t = traj_of(p, q.P);
+                if (q.free_all) {
+                    finish_free(q, t);
+                    slot_release(S, s);
+                    t = -1;
+                } else {
+                    setup64(q, lds64 + s * slot_n, lp);
+                    double x0, vx0, vy0;
+                    initial_state(q, t, x0, vx0, vy0);
+                    v0n = sqrt(norm2(vx0, vy0));
+                    dp5_start(L, lp.cf, x0, vx0, vy0, q.P.h0, q.P.u_end);
+                }
+            }
+        }
+        if (__ballot(t >= 0) == 0ull) {
+            if (expired || __hip_atomic_load(&S.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+            __builtin_amdgcn_s_sleep(8);
+            continue;
+        }
+        if (expired) break;
+        if (t >= 0) {
+            const int st = dp5_attempt(L, lp.cf, lp.ctl);
+            if (st >= 0) {
+                const TrajOut o = A.reqs[rq].o;
+                o.ratio[t] = sqrt(norm2(L.vx, L.vy)) / v0n;
+                o.stat[t] = TrajStat{L.nacc, L.nrej, st, 0};
+                slot_release(S, sl);
+                t = -1;
+            }
+        }
+    }
+    if (my) {
+        LaneSave sv;
+        sv.t = t;
+        sv.req = rq;
+        sv.slot = sl;
+        if (t >= 0) {
+            pack64(L, v0n, sv);
+            atomicAdd(&A.inflight[rq], 1u);
+        }
+        *my = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && A.wg_save) A.wg_save[blockIdx.x] = WgSave{{S.slot_req[0], S.slot_req[1]}, S.cur, 0};
+}
+
+// ---------------------------------------------------------------------------
+// FP32-compensated slice kernel
+// ---------------------------------------------------------------------------
+
+template <int NC, int SLOTS>
+__global__ __launch_bounds__(512) void k_slice_f32c(SliceArgs A)
+{
+    extern __shared__ float lds32b[];
+    __shared__ WgSched S;
+    const int slot_n = A.n_tab * NC;
+    if (threadIdx.x == 0) sched_init(S, A);
+    __syncthreads();
+    for (int s = 0; s < SLOTS; ++s)
+        if (S.slot_req[s] >= 0) copy_table<NC>(lds32b + s * slot_n, A.reqs[S.slot_req[s]], threadIdx.x, blockDim.x);
+
+    long long t = -1;
+    int rq = 0, sl = 0;
+    double v0n = 1.0;
+    Lane32 L{};
+    Lane32Params<NC> lp{};
+    LaneSave *const my = A.lane_save ? A.lane_save + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) : nullptr;
+    if (A.resume && my) {
+        const LaneSave sv = *my;
+        if (sv.t >= 0 && !A.reqs[sv.req].retired) {
+            t = sv.t;
+            rq = sv.req;
+            sl = sv.slot;
+            unpack32(sv, L, v0n);
+            setup32(A.reqs[rq], lds32b + sl * slot_n, lp);
+            __hip_atomic_fetch_add(&S.active[sl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+
+    const unsigned long long t0 = wall_clock64();
+    bool expired = false;
+    for (;;) {
+        if (A.budget_ticks >= 0 && !expired) expired = (long long)(wall_clock64() - t0) > A.budget_ticks;
+        const unsigned long long mask = __ballot(t < 0 && !expired);
+        if (mask != 0ull && !__hip_atomic_load(&S.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            int r, s;
+            long long p;
+            wave_acquire<SLOTS>(S, A, mask, r, p, s, [&](int slot, int req) {
+                copy_table<NC>(lds32b + slot * slot_n, A.reqs[req], (int)__lane_id(), 64);
+            });
+            if (r >= 0) {
+                const BatchReq &q = A.reqs[r];
+                rq = r;
+                sl = s;
+                t = traj_of(p, q.P);
+                if (q.free_all) {
+                    finish_free(q, t);
+                    slot_release(S, s);
+                    t = -1;
+                } else {
+                    setup32(q, lds32b + s * slot_n, lp);
+                    double x0, vx0, vy0;
+                    initial_state(q, t, x0, vx0, vy0);
+                    v0n = sqrt(norm2(vx0, vy0));
+                    f32c_start(L, lp.cf, x0, vx0, vy0, q.P.h0, q.P.u_end);
+                }
+            }
+        }
+        if (__ballot(t >= 0) == 0ull) {
+            if (expired || __hip_atomic_load(&S.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+            __builtin_amdgcn_s_sleep(8);
+            continue;
+        }
+        if (expired) break;
+        if (t >= 0) {
+            const int st = f32c_attempt(L, lp.cf, lp.cf64, lp.ctl, lp.ctl64, lp.h_fp64);
+            if (st >= 0) {
+                const TrajOut o = A.reqs[rq].o;
+                const double fx = L.vx, fy = L.vy;
+                o.ratio[t] = sqrt(norm2(fx, fy)) / v0n;
+                o.stat[t] = TrajStat{L.nacc, L.nrej, st, L.n64};
+                slot_release(S, sl);
+                t = -1;
+            }
+        }
+    }
+    if (my) {
+        LaneSave sv;
+        sv.t = t;
+        sv.req = rq;
+        sv.slot = sl;
+        if (t >= 0) {
+            pack32(L, v0n, sv);
+            atomicAdd(&A.inflight[rq], 1u);
+        }
+        *my = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && A.wg_save) A.wg_save[blockIdx.x] = WgSave{{S.slot_req[0], S.slot_req[1]}, S.cur, 0};
+}
+
+// ---------------------------------------------------------------------------
+// reductions over listed requests
+// ---------------------------------------------------------------------------
+
+// One block per radius of the listed requests; rstart[i] = first block of list[i].
+__global__ __launch_bounds__(256) void k_reduce_profile_batch(const BatchReq *__restrict__ reqs,
+                                                              const int *__restrict__ list,
+                                                              const int *__restrict__ rstart, int n_list)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = n_list - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rstart[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchReq &q = reqs[list[lo]];
+    reduce_radius(q.P, q.g, q.o.ratio, q.f0_kind, b - rstart[lo], q.out);
+}
+
+// blockIdx.y: listed request; its statistics go to stats[8 * blockIdx.y ...].
+__global__ __launch_bounds__(256) void k_reduce_stats_batch(const BatchReq *__restrict__ reqs,
+                                                            const int *__restrict__ list,
+                                                            unsigned long long *stats)
+{
+    const BatchReq &q = reqs[list[blockIdx.y]];
+    reduce_stats_range(q.o.stat, (long long)blockIdx.x * blockDim.x + threadIdx.x, q.P.n_traj,
+                       (long long)gridDim.x * blockDim.x, stats + 8 * (size_t)blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+size_t slice_lds_bytes(bool f32c, int nc, int slots, int n_tab)
+{
+    return (size_t)slots * n_tab * nc * (f32c ? sizeof(float) : sizeof(double));
+}
+
+int slice_max_table_nodes(bool f32c, int nc, int slots)
+{
+    const size_t avail = 160 * 1024 - sizeof(WgSched) - 256;
+    return (int)(avail / ((size_t)slots * nc * (f32c ? sizeof(float) : sizeof(double))));
+}
+
+template <int NC, int SLOTS>
+static const void *slice_fn(bool f32c)
+{
+    return f32c ? (const void *)k_slice_f32c<NC, SLOTS> : (const void *)k_slice_f64<NC, SLOTS>;
+}
+
+static const void *slice_fn(bool f32c, int nc, int slots)
+{
+    if (nc == NCOL) return slots == 2 ? slice_fn<NCOL, 2>(f32c) : slice_fn<NCOL, 1>(f32c);
+    return slots == 2 ? slice_fn<NCOL - 1, 2>(f32c) : slice_fn<NCOL - 1, 1>(f32c);
+}
+
+// Workgroups that fit the device at once for this slice configuration.
+hipError_t slice_capacity(bool f32c, int nc, int slots, int n_tab, int block, int n_cu, int *grid)
+{
+    const void *fn = slice_fn(f32c, nc, slots);
+    const size_t lds = slice_lds_bytes(f32c, nc, slots, n_tab);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    *grid = n_cu * per_cu;
+    return hipSuccess;
+}
+
+hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, int grid, int block, hipStream_t s)
+{
+    const size_t lds = slice_lds_bytes(f32c, nc, slots, A.n_tab);
+    void *args[] = {(void *)&A};
+    return hipLaunchKernel(slice_fn(f32c, nc, slots), dim3(grid), dim3(block), args, lds, s);
+}
+
+hipError_t launch_reduce_batch(const BatchReq *reqs, const int *list, const int *rstart, int n_list,
+                               int n_blocks, unsigned long long *stats, int stat_chunks, hipStream_t s)
+{
+    if (n_list <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_profile_batch, dim3(n_blocks), dim3(256), 0, s, reqs, list, rstart, n_list);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_stats_batch, dim3(stat_chunks, n_list), dim3(256), 0, s, reqs, list, stats);
+    return hipGetLastError();
+}
+
+}  // namespace nh

@@ -30,22 +30,9 @@ __global__ __launch_bounds__(512) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
     const TabCoef32<NC> cf{lds32, P.n_tab, P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30)};
     // the promoted FP64 steps read the FP64 table from global memory (rows of NCOL)
     const TabCoef<NC, NCOL> cf64{g.tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
-    // FP32 cannot resolve the FP64 tolerance; it integrates at max(rtol, 1e-6)
-    const double rtol32 = fmax(P.rtol, 1.0e-6);
     DpCtl32 ctl;
-    ctl.u_end = P.u_end;
-    ctl.rtol = (float)rtol32;
-    ctl.atol_x = (float)fmax(P.atol_x, rtol32);
-    ctl.atol_v = (float)fmax(P.atol_v, rtol32);
-    ctl.r_exit2 = P.r_exit > 0.0 ? (float)(P.r_exit * P.r_exit) : -1.0f;
-    ctl.max_steps = (int)P.max_steps;
     DpCtl ctl64;
-    ctl64.u_end = P.u_end;
-    ctl64.rtol = rtol32;
-    ctl64.atol_x = fmax(P.atol_x, rtol32);
-    ctl64.atol_v = fmax(P.atol_v, rtol32);
-    ctl64.r_exit2 = P.r_exit > 0.0 ? P.r_exit * P.r_exit : -1.0;
-    ctl64.max_steps = (int)P.max_steps;
+    f32c_controls(P, ctl, ctl64);
 
     long long t = -1;
     double v0n = 1.0;
@@ -63,64 +50,14 @@ __global__ __launch_bounds__(512) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
                 const double V = g.y[j] * P.vfac;
                 const double vx0 = V * g.mu[l], vy0 = V * g.smu[l];
                 v0n = sqrt(norm2(vx0, vy0));
-                L.x = (float)g.r[k];
-                L.xc = (float)(g.r[k] - (double)L.x);
-                L.y = 0.0f;
-                L.yc = 0.0f;
-                L.vx = (float)vx0;
-                L.vy = (float)vy0;
-                L.u = 0.0;
-                L.h = -fabs(P.h0);
-                if (fabs(L.h) > fabs(P.u_end)) L.h = P.u_end;
-                L.nacc = L.nrej = L.natt = L.n64 = 0;
-                L.rej_prev = false;
-                float c[NCOL], R;
-                cf.at(0.0, c, R);
-                rhs32(c, R, L.x, L.y, L.vx, L.vy, L.k1x, L.k1y, L.k1u, L.k1v);
+                f32c_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_end);
             } else {
                 t = -2;
             }
         }
         if (__ballot(t >= 0) == 0ull) break;
         if (t >= 0) {
-            int st;
-            if (fabs(L.h) < P.h_fp64) {
-                // promoted attempt in FP64
-                Lane64 D;
-                D.x = (double)L.x + (double)L.xc;
-                D.y = (double)L.y + (double)L.yc;
-                D.vx = L.vx;
-                D.vy = L.vy;
-                D.u = L.u;
-                D.h = L.h;
-                D.nacc = L.nacc;
-                D.nrej = L.nrej;
-                D.natt = L.natt;
-                D.rej_prev = L.rej_prev;
-                double c[NCOL], R;
-                cf64.at(D.u, c, R);
-                rhs(c, R, D.x, D.y, D.vx, D.vy, D.k1x, D.k1y, D.k1u, D.k1v);
-                st = dp5_attempt(D, cf64, ctl64);
-                L.x = (float)D.x;
-                L.xc = (float)(D.x - (double)L.x);
-                L.y = (float)D.y;
-                L.yc = (float)(D.y - (double)L.y);
-                L.vx = (float)D.vx;
-                L.vy = (float)D.vy;
-                L.u = D.u;
-                L.h = D.h;
-                L.k1x = (float)D.k1x;
-                L.k1y = (float)D.k1y;
-                L.k1u = (float)D.k1u;
-                L.k1v = (float)D.k1v;
-                L.nacc = D.nacc;
-                L.nrej = D.nrej;
-                L.natt = D.natt;
-                L.rej_prev = D.rej_prev;
-                ++L.n64;
-            } else {
-                st = dp5_attempt32(L, cf, ctl);
-            }
+            const int st = f32c_attempt(L, cf, cf64, ctl, ctl64, P.h_fp64);
             if (st >= 0) {
                 const double fx = L.vx, fy = L.vy;
                 o.ratio[t] = sqrt(norm2(fx, fy)) / v0n;

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "nh_dp5.h"
+#include "nh_reduce.h"
 
 namespace nh {
 
@@ -166,30 +167,7 @@ __global__ __launch_bounds__(256) void k_reduce_profile(TrajParams P, GridPtrs g
                                                         const double *__restrict__ ratio,
                                                         int f0_kind, double *__restrict__ out)
 {
-    const int k = blockIdx.x;
-    const int ne = P.n_y * P.n_mu;
-    double num = 0.0, den = 0.0;
-    const double *rk = ratio + (size_t)k * ne;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-        const int j = e / P.n_mu;
-        const int l = e - j * P.n_mu;
-        const double W = g.wy[j] * g.wmu[l];
-        const double yj = g.y[j];
-        num += W * f0_eval(f0_kind, yj * rk[e]);
-        den += W * f0_eval(f0_kind, yj);
-    }
-    __shared__ double sn[256], sd[256];
-    sn[threadIdx.x] = num;
-    sd[threadIdx.x] = den;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            sn[threadIdx.x] += sn[threadIdx.x + s];
-            sd[threadIdx.x] += sd[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sn[0] / sd[0];
+    reduce_radius(P, g, ratio, f0_kind, blockIdx.x, out);
 }
 
 // Integer statistics (exact under any summation order).
@@ -197,35 +175,8 @@ __global__ __launch_bounds__(256) void k_reduce_profile(TrajParams P, GridPtrs g
 __global__ __launch_bounds__(256) void k_reduce_stats(long long n, TrajOut o,
                                                       unsigned long long *stats)
 {
-    unsigned long long acc = 0, rej = 0, mx = 0, fail = 0, f64 = 0, fre = 0;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (long long)gridDim.x * blockDim.x) {
-        const TrajStat ts = o.stat[t];
-        const unsigned long long a = (unsigned)ts.acc, r = (unsigned)ts.rej;
-        acc += a;
-        rej += r;
-        mx = a + r > mx ? a + r : mx;
-        fail += (ts.status & 0xff) != ST_OK;
-        fre += (ts.status & ST_FREE_EXIT) != 0;
-        f64 += (unsigned)ts.fp64;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        acc += __shfl_down(acc, off);
-        rej += __shfl_down(rej, off);
-        const unsigned long long m2 = __shfl_down(mx, off);
-        mx = m2 > mx ? m2 : mx;
-        fail += __shfl_down(fail, off);
-        f64 += __shfl_down(f64, off);
-        fre += __shfl_down(fre, off);
-    }
-    if (__lane_id() == 0) {
-        atomicAdd(stats + 0, acc);
-        atomicAdd(stats + 1, rej);
-        atomicMax(stats + 2, mx);
-        atomicAdd(stats + 3, fail);
-        atomicAdd(stats + 4, f64);
-        atomicAdd(stats + 5, fre);
-    }
+    reduce_stats_range(o.stat, (long long)blockIdx.x * blockDim.x + threadIdx.x, n,
+                       (long long)gridDim.x * blockDim.x, stats);
 }
 
 // ---------------------------------------------------------------------------

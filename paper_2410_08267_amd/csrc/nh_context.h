@@ -32,6 +32,7 @@ struct nh_context {
     char err[512] = "";
     hipStream_t stream = nullptr;                    // used by nh_solve
     nh::DevBuf blob, ratio, stat, small, out;
+    nh::DevBuf bctr;                                 // batched form: counters and statistics
     void *h_stage = nullptr;                         // pinned staging for the inputs
     size_t h_stage_cap = 0;
     hipEvent_t ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
@@ -43,6 +44,7 @@ struct nh_context {
     double h_fp64 = 1.0e-5;                          // FP32C: |h| below this runs in FP64
     int table_nodes = 0;                             // 0: default_table_nodes()
     int block_threads = 512;                         // Dormand-Prince workgroup size
+    int batch_slots = 0;                             // tables per workgroup, batched form (0: default)
     nh::ServeState *serve = nullptr;
 };
 
@@ -56,5 +58,16 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P)
 GridPtrs grid_ptrs(const Staged &s, const char *dev);
 size_t per_traj_bytes(const nh_request *q);
 void serve_shutdown(nh_context *ctx);
+int wait_pending(nh_context *ctx);
+int request_columns(const nh_request *q);
+int batch_slots(const nh_context *ctx, bool f32c);
+int batch_table_nodes(nh_context *ctx, bool f32c, int nc, int slots, int *n_tab);
+
+#define HIPCHK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return set_err(ctx, NH_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
 
 }  // namespace nh

@@ -132,27 +132,46 @@ __device__ __forceinline__ double norm2(double a, double b) { return fma(a, a, b
 // coefficients and right-hand side
 // ---------------------------------------------------------------------------
 
-// Coefficients at u from the uniform table (4-point Lagrange, cubic).  Nodes
-// u_i = u0 + i du, i = 0..n-1, rows of STRIDE doubles of which the first NC
-// columns are used (NC = NCOL - 1 when the compensation radius R is constant
-// and passed separately); the stencil is shifted inward at both ends.
-template <int NC, int STRIDE = NC>
-__device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int n_tab, double u0,
-                                            double inv_du, double u, double c[NCOL])
+// 4-point Lagrange (cubic) stencil at u on the uniform table with nodes
+// u_i = u0 + i du, i = 0..n-1: first row of the stencil and its four weights;
+// the stencil is shifted inward at both ends.
+struct Stencil4 {
+    int row;
+    double wa, wb, wc, wd;
+};
+__device__ __forceinline__ Stencil4 stencil_at(int n_tab, double u0, double inv_du, double u)
 {
     const double s = (u - u0) * inv_du;
     int i = (int)s;
     i = i < 1 ? 1 : (i > n_tab - 3 ? n_tab - 3 : i);
     const double p = s - (double)i;
     const double pm = p + 1.0, p1 = p - 1.0, p2 = p - 2.0;
-    const double wa = -(p * p1 * p2) * (1.0 / 6.0);
-    const double wb = (pm * p1 * p2) * 0.5;
-    const double wc = -(pm * p * p2) * 0.5;
-    const double wd = (pm * p * p1) * (1.0 / 6.0);
-    const double *row = tab + (i - 1) * STRIDE;
+    Stencil4 w;
+    w.row = i - 1;
+    w.wa = -(p * p1 * p2) * (1.0 / 6.0);
+    w.wb = (pm * p1 * p2) * 0.5;
+    w.wc = -(pm * p * p2) * 0.5;
+    w.wd = (pm * p * p1) * (1.0 / 6.0);
+    return w;
+}
+
+// Column k of the interpolated coefficients from rows of `stride` doubles.
+__device__ __forceinline__ double stencil_col(const Stencil4 &w, const double *row, int stride, int k)
+{
+    return w.wa * row[k] + w.wb * row[stride + k] + w.wc * row[2 * stride + k] + w.wd * row[3 * stride + k];
+}
+
+// Coefficients at u from the uniform table, rows of STRIDE doubles of which
+// the first NC columns are used (NC = NCOL - 1 when the compensation radius R
+// is constant and passed separately).
+template <int NC, int STRIDE = NC>
+__device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int n_tab, double u0,
+                                            double inv_du, double u, double c[NCOL])
+{
+    const Stencil4 w = stencil_at(n_tab, u0, inv_du, u);
+    const double *row = tab + w.row * STRIDE;
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
-        c[k] = wa * row[k] + wb * row[STRIDE + k] + wc * row[2 * STRIDE + k] + wd * row[3 * STRIDE + k];
+    for (int k = 0; k < NC; ++k) c[k] = stencil_col(w, row, STRIDE, k);
 }
 
 // dY/du for Y = (x, y, vx, vy): dx/du = A v, dv/du = -g x with

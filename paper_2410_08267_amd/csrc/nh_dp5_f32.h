@@ -63,8 +63,34 @@ __device__ __forceinline__ void rhs32(const float c[NCOL], float R, float x, flo
     dvy = -g * y;
 }
 
-// Cubic interpolation from the FP32 table (rows of NC floats); the node
-// index and fraction come from the FP64 time.
+// Cubic interpolation from the FP32 table; the node index and fraction come
+// from the FP64 time.
+struct Stencil4f {
+    int row;
+    float wa, wb, wc, wd;
+};
+__device__ __forceinline__ Stencil4f stencil32_at(int n_tab, double u0, double inv_du, double u)
+{
+    const double sd = (u - u0) * inv_du;
+    int i = (int)sd;
+    i = i < 1 ? 1 : (i > n_tab - 3 ? n_tab - 3 : i);
+    const float p = (float)(sd - (double)i);
+    const float pm = p + 1.0f, p1 = p - 1.0f, p2 = p - 2.0f;
+    Stencil4f w;
+    w.row = i - 1;
+    w.wa = -(p * p1 * p2) * (1.0f / 6.0f);
+    w.wb = (pm * p1 * p2) * 0.5f;
+    w.wc = -(pm * p * p2) * 0.5f;
+    w.wd = (pm * p * p1) * (1.0f / 6.0f);
+    return w;
+}
+
+__device__ __forceinline__ float stencil32_col(const Stencil4f &w, const float *row, int stride, int k)
+{
+    return fmaf(w.wa, row[k], fmaf(w.wb, row[stride + k], fmaf(w.wc, row[2 * stride + k], w.wd * row[3 * stride + k])));
+}
+
+// Rows of NC floats (NC = NCOL - 1 when R is constant).
 template <int NC>
 struct TabCoef32 {
     const float *tab;
@@ -73,19 +99,10 @@ struct TabCoef32 {
     float R_const;
     __device__ __forceinline__ void at(double u, float c[NCOL], float &R) const
     {
-        const double sd = (u - u0) * inv_du;
-        int i = (int)sd;
-        i = i < 1 ? 1 : (i > n_tab - 3 ? n_tab - 3 : i);
-        const float p = (float)(sd - (double)i);
-        const float pm = p + 1.0f, p1 = p - 1.0f, p2 = p - 2.0f;
-        const float wa = -(p * p1 * p2) * (1.0f / 6.0f);
-        const float wb = (pm * p1 * p2) * 0.5f;
-        const float wc = -(pm * p * p2) * 0.5f;
-        const float wd = (pm * p * p1) * (1.0f / 6.0f);
-        const float *row = tab + (i - 1) * NC;
+        const Stencil4f w = stencil32_at(n_tab, u0, inv_du, u);
+        const float *row = tab + w.row * NC;
 #pragma unroll
-        for (int k = 0; k < NC; ++k)
-            c[k] = fmaf(wa, row[k], fmaf(wb, row[NC + k], fmaf(wc, row[2 * NC + k], wd * row[3 * NC + k])));
+        for (int k = 0; k < NC; ++k) c[k] = stencil32_col(w, row, NC, k);
         R = (NC == NCOL) ? c[COL_R] : R_const;
     }
 };
@@ -199,6 +216,91 @@ __device__ __forceinline__ int dp5_attempt32(Lane32 &L, const CF &cf, const DpCt
     }
     if (fabs(L.h) <= 8.881784197001252e-16 * fmax(1.0, fabs(L.u))) return ST_UNDERFLOW;
     return -1;
+}
+
+// Start a trajectory at u = 0: FP32 state from the FP64 initial conditions,
+// first stage evaluated in FP32.
+template <class CF>
+__device__ __forceinline__ void f32c_start(Lane32 &L, const CF &cf, double x0, double vx0, double vy0,
+                                           double h0, double u_end)
+{
+    L.x = (float)x0;
+    L.xc = (float)(x0 - (double)L.x);
+    L.y = 0.0f;
+    L.yc = 0.0f;
+    L.vx = (float)vx0;
+    L.vy = (float)vy0;
+    L.u = 0.0;
+    L.h = -fabs(h0);
+    if (fabs(L.h) > fabs(u_end)) L.h = u_end;
+    L.nacc = L.nrej = L.natt = L.n64 = 0;
+    L.rej_prev = false;
+    float c[NCOL], R;
+    cf.at(0.0, c, R);
+    rhs32(c, R, L.x, L.y, L.vx, L.vy, L.k1x, L.k1y, L.k1u, L.k1v);
+}
+
+// One attempt of the FP32-compensated form: in FP64 (state widened, first
+// stage re-evaluated on the FP64 table cf64) when |h| < h_fp64, else in FP32.
+// Returns -1 while the trajectory continues, else its status.
+template <class CF32, class CF64>
+__device__ __forceinline__ int f32c_attempt(Lane32 &L, const CF32 &cf, const CF64 &cf64, const DpCtl32 &ctl,
+                                            const DpCtl &ctl64, double h_fp64)
+{
+    if (!(fabs(L.h) < h_fp64)) return dp5_attempt32(L, cf, ctl);
+    Lane64 D;
+    D.x = (double)L.x + (double)L.xc;
+    D.y = (double)L.y + (double)L.yc;
+    D.vx = L.vx;
+    D.vy = L.vy;
+    D.u = L.u;
+    D.h = L.h;
+    D.nacc = L.nacc;
+    D.nrej = L.nrej;
+    D.natt = L.natt;
+    D.rej_prev = L.rej_prev;
+    double c[NCOL], R;
+    cf64.at(D.u, c, R);
+    rhs(c, R, D.x, D.y, D.vx, D.vy, D.k1x, D.k1y, D.k1u, D.k1v);
+    const int st = dp5_attempt(D, cf64, ctl64);
+    L.x = (float)D.x;
+    L.xc = (float)(D.x - (double)L.x);
+    L.y = (float)D.y;
+    L.yc = (float)(D.y - (double)L.y);
+    L.vx = (float)D.vx;
+    L.vy = (float)D.vy;
+    L.u = D.u;
+    L.h = D.h;
+    L.k1x = (float)D.k1x;
+    L.k1y = (float)D.k1y;
+    L.k1u = (float)D.k1u;
+    L.k1v = (float)D.k1v;
+    L.nacc = D.nacc;
+    L.nrej = D.nrej;
+    L.natt = D.natt;
+    L.rej_prev = D.rej_prev;
+    ++L.n64;
+    return st;
+}
+
+// Step control of the FP32-compensated form: FP32 cannot resolve tolerances
+// below ~1e-6, so it integrates at max(rtol, 1e-6); the promoted FP64
+// attempts use the same tolerances.
+__device__ __forceinline__ void f32c_controls(const TrajParams &P, DpCtl32 &ctl, DpCtl &ctl64)
+{
+    const double rtol32 = fmax(P.rtol, 1.0e-6);
+    ctl.u_end = P.u_end;
+    ctl.rtol = (float)rtol32;
+    ctl.atol_x = (float)fmax(P.atol_x, rtol32);
+    ctl.atol_v = (float)fmax(P.atol_v, rtol32);
+    ctl.r_exit2 = P.r_exit > 0.0 ? (float)(P.r_exit * P.r_exit) : -1.0f;
+    ctl.max_steps = (int)P.max_steps;
+    ctl64.u_end = P.u_end;
+    ctl64.rtol = rtol32;
+    ctl64.atol_x = fmax(P.atol_x, rtol32);
+    ctl64.atol_v = fmax(P.atol_v, rtol32);
+    ctl64.r_exit2 = P.r_exit > 0.0 ? P.r_exit * P.r_exit : -1.0;
+    ctl64.max_steps = (int)P.max_steps;
 }
 
 }  // namespace nh

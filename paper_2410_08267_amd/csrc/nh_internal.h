@@ -84,6 +84,54 @@ struct TrajOut {
     TrajStat *stat;         // n_traj
 };
 
+// ---- batched and serving forms (scheduling: nh_batch.h) ----
+
+enum : int {
+    POLICY_OPEN_FIRST = 0,    // open requests in order, then help the one with most work left
+    POLICY_OLDEST_FIRST = 1,  // always draw from the oldest request with work left
+};
+
+// One request as the slice kernels see it (device array).
+struct BatchReq {
+    TrajParams P;
+    GridPtrs g;               // staged inputs; g.tab rows of NCOL doubles
+    TrajOut o;                // per-trajectory outputs of this request
+    double *out;              // n_r profile
+    int f0_kind;
+    int nc;                   // table columns used: NCOL, or NCOL - 1 when R is constant
+    int free_all;             // no halo: every trajectory streams freely (ratio 1)
+    int retired;              // cancelled: not claimed, saved lanes drop it
+};
+
+struct alignas(16) WgSave {
+    int slot_req[2];
+    int cur;
+    int pad;
+};
+
+// Saved state of one lane between slices (FP64 or FP32C lane, raw words).
+struct alignas(16) LaneSave {
+    long long t;              // trajectory index, < 0: none
+    int req, slot;
+    unsigned long long w[14];
+};
+
+struct SliceArgs {
+    const BatchReq *reqs;     // by request id
+    unsigned long long *next; // per request id: queue position of the next unclaimed trajectory
+    unsigned int *inflight;   // per request id: lanes saved with its trajectories at this slice's end
+    const int *order;         // request ids of this launch, oldest first
+    int n_order;
+    int policy;               // POLICY_*
+    unsigned long long *cursor;   // POLICY_OPEN_FIRST: next position of `order` to open
+    int n_tab;                // table nodes of every request (slot capacity)
+    long long budget_ticks;   // wall-clock ticks (100 MHz) until lanes save and exit; < 0: none
+    LaneSave *lane_save;      // per thread of the grid, or null
+    WgSave *wg_save;          // per workgroup, or null
+    int resume;               // restore lanes and slots saved by the previous slice
+};
+
+
 // Host-side physics of one request, evaluated in FP64 (tables, validation).
 struct Physics {
     double G, H0k, Om, OL;

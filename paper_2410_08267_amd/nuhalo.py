@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(HERE, "libnuhalo.so")
 
 NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ESTEPS = 0, -1, -2, -3, -4
 NH_ENONFINITE, NH_EBUSY, NH_ENOTREADY, NH_ENOTFOUND, NH_ECANCELED = -5, -6, -7, -8, -9
-OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4, "block_threads": 5}
+OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4, "block_threads": 5,
+           "batch_slots": 6}
 
 _MASS = {"zero": 0, "paper": 1, "exponential": 2}
 _CONC = {"constant": 0, "power": 1}
@@ -318,8 +319,12 @@ class Context:
         return acc, rej, st
 
     def solve_batch(self, reqs, out: "torch.Tensor", stream=None):
-        """Solve several requests in one persistent launch; out holds the concatenated profiles."""
+        """Solve several requests in one persistent launch; out (float64 device tensor)
+        receives the concatenated profiles in request order.  Waits for completion."""
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
         ms = [marshal(r) for r in reqs]
+        if out.numel() < sum(m.r.size for m in ms):
+            raise ValueError("out is too small")
         arr = (nh_request * len(ms))(*[m.q for m in ms])
         stats = (nh_stats * len(ms))()
         s = stream if stream is not None else torch.cuda.current_stream(out.device)

@@ -1,5 +1,9 @@
+import ctypes
 import os
+import subprocess
 import sys
+
+import numpy as np
 
 import pytest
 
@@ -18,3 +22,48 @@ def oracle_mod():
     from oracle import oracle as O
     O.lib()
     return O
+
+
+@pytest.fixture(scope="session")
+def oracle_fma(oracle_mod, tmp_path_factory):
+    """The oracle source built with FMA contraction: same arithmetic, other rounding."""
+    O = oracle_mod
+    so = tmp_path_factory.mktemp("fma") / "oracle_fma.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=fast", "-mfma",
+                    "-o", str(so), O._SRC, "-lm"], check=True)
+    L = ctypes.CDLL(str(so))
+    L.nho_integrate.argtypes = O.lib().nho_integrate.argtypes
+    return L
+
+
+@pytest.fixture(scope="session")
+def sensitivity(oracle_mod, oracle_fma):
+    """sensitivity(req, ref_profile): the largest relative change of the oracle's
+    profile under perturbations no larger than what separates two correct FP64
+    integrations of the request: re-rounding of the same arithmetic (the
+    FMA-contracted build), and relative changes of the force of 1e-12 (the
+    device interpolates its coefficient tables to ~1e-13): the halo mass scaled
+    by 1 + 1e-12, and G scaled by 1 + 1e-12 z/(1+z) when the request leaves G
+    unmodulated.  Adaptive step control turns such differences into flipped
+    accept/reject decisions, i.e. profile differences of order rtol, for some
+    halos; parity bounds scale with this measure where it exceeds them."""
+    O = oracle_mod
+
+    def dev(profile, ref):
+        return float(np.max(np.abs(np.asarray(profile) / np.asarray(ref) - 1.0)))
+
+    def f(req, ref_profile):
+        if req.mass_kind == "zero":
+            return 0.0
+        saved = O._lib
+        try:
+            O._lib = oracle_fma
+            worst = dev(O.solve(req)["n_over_nbar"], ref_profile)
+        finally:
+            O._lib = saved
+        worst = max(worst, dev(O.solve(req.with_(M0=req.M0 * (1.0 + 1e-12)))["n_over_nbar"], ref_profile))
+        if req.kappa_kind == "none":
+            kp = req.with_(kappa_kind="paper", kappa_a=1e-12, kappa_b=1.0)
+            worst = max(worst, dev(O.solve(kp)["n_over_nbar"], ref_profile))
+        return worst
+    return f

@@ -1,0 +1,186 @@
+"""Batched form (nh_solve_batch) on the GPU, through the C ABI.
+
+A request's trajectories run the same per-lane code in the batched slice
+kernel as in the plain kernels, on the same table when both use the same
+number of nodes (by default: FP64 keeps one 3073-node table per workgroup,
+like the plain form; FP32C two), and the same reduction; so a batched profile
+must equal the plain path's bit for bit, whatever else shares the launch.
+Against the oracle the bounds are those of the plain paths: FP32C within
+1e-4; FP64 at rtol 1e-8 within 1e-8 relative, or four times the oracle's own
+sensitivity to re-rounding and to 1e-12 relative force changes where that is
+larger (the `sensitivity` fixture).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_08267_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_08267_amd import nuhalo as N
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = N.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def small_mix(seed, n, prec="fp64", grid=(6, 14, 6)):
+    """n batched-workload requests on small grids (the physics of the full draws)."""
+    reqs = W.batched(seed, n_req=n, prec=prec, freeze_in_frac=0.3, kappa_frac=0.3)
+    out = []
+    for i, r in enumerate(reqs):
+        nr, ny, nm = grid
+        out.append(W.shrink(r, nr + i % 3, ny + (i % 4), nm + (i % 2)))
+    return out
+
+
+def run_batch(ctx, reqs):
+    n = sum(r.n_r for r in reqs)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    stats, rc = ctx.solve_batch(reqs, out)
+    torch.cuda.synchronize()
+    prof = out.cpu().numpy()
+    res, k = [], 0
+    for r in reqs:
+        res.append(prof[k:k + r.n_r].copy())
+        k += r.n_r
+    return res, stats, rc
+
+
+def run_plain(ctx, req):
+    out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+    ctx.solve_async(req, out)
+    st, _ = ctx.last_stats()
+    return out.cpu().numpy(), st
+
+
+class options:
+    """Context options for one test, restored to their defaults afterwards."""
+
+    def __init__(self, ctx, **kw):
+        self.ctx, self.kw = ctx, kw
+
+    def __enter__(self):
+        for k, v in self.kw.items():
+            self.ctx.set_option(k, v)
+
+    def __exit__(self, *exc):
+        for k in self.kw:
+            self.ctx.set_option(k, 0)
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) / np.asarray(b) - 1.0)
+
+
+@pytest.mark.parametrize("prec,slots,nodes", [("fp64", 0, 0), ("fp64", 2, 1537), ("fp32c", 0, 0),
+                                               ("fp32c", 1, 0)])
+def test_batch_equals_plain_bitwise(ctx, prec, slots, nodes):
+    reqs = small_mix(21, 12, prec)
+    say(f"batch {prec} of {len(reqs)} vs plain, slots {slots} nodes {nodes}, n_traj {sum(r.n_traj for r in reqs)}")
+    with options(ctx, batch_slots=slots, table_nodes=nodes):
+        profs, stats, rc = run_batch(ctx, reqs)
+        plain = [run_plain(ctx, r) for r in reqs]
+    assert rc == 0
+    for i, r in enumerate(reqs):
+        p, st = plain[i]
+        assert np.array_equal(p, profs[i]), (i, rel(p, profs[i]).max())
+        assert st["accepted_steps"] == stats[i]["accepted_steps"]
+        assert st["rejected_steps"] == stats[i]["rejected_steps"]
+        assert st["free_exits"] == stats[i]["free_exits"]
+        assert st["fp64_steps"] == stats[i]["fp64_steps"]
+
+
+def test_alone_equals_in_mix(ctx):
+    reqs = small_mix(5, 9)
+    say("batch fp64: request 4 alone vs in a mix of 9")
+    mix, _, _ = run_batch(ctx, reqs)
+    alone, _, _ = run_batch(ctx, [reqs[4]])
+    assert np.array_equal(alone[0], mix[4])
+    # and in a different order and company
+    other, _, _ = run_batch(ctx, [reqs[7], reqs[4], reqs[0]])
+    assert np.array_equal(other[1], mix[4])
+
+
+def mixed_kinds(rtol):
+    base = W.shrink(W.plain_small(), 6, 12, 6).with_(method="dp5", rtol=rtol)
+    return [
+        base.with_(M0=3e13),
+        base.with_(geometry="delta200", M0=5e13),
+        base.with_(f0_kind="freeze_in", kappa_kind="log", kappa_a=0.05, M0=2e13),
+        base.with_(compensated=False, M0=1e13),
+        base.with_(mass_kind="zero"),
+        W.shrink(W.plain_scale(4), 5, 12, 6).with_(rtol=rtol),
+    ]
+
+
+def test_mixed_geometry_kinds_vs_oracle(ctx, O, sensitivity):
+    """Constant-R and moving-R requests in one launch (the six-column slot layout),
+    freeze-in f0, G(z), an uncompensated halo and a halo-free request."""
+    reqs = mixed_kinds(1e-8)
+    say("batch fp64 mixed kinds vs oracle, rtol 1e-8")
+    profs, stats, rc = run_batch(ctx, reqs)
+    assert rc == 0
+    for i, r in enumerate(reqs):
+        ref = O.solve(r)["n_over_nbar"]
+        e = rel(profs[i], ref).max()
+        sens = sensitivity(r, ref)
+        print(f"request {i}: max rel {e:.2e} (oracle sensitivity {sens:.2e})", flush=True)
+        assert e <= max(1e-8, 4.0 * sens), i
+    assert np.array_equal(profs[4], np.ones(reqs[4].n_r))
+    assert stats[4]["accepted_steps"] == 0
+
+
+def test_batch_fp32c_vs_oracle(ctx, O):
+    reqs = small_mix(33, 6, "fp32c")
+    say("batch fp32c of 6 vs oracle")
+    profs, stats, rc = run_batch(ctx, reqs)
+    assert rc == 0
+    for i, r in enumerate(reqs):
+        ref = O.solve(r.with_(precision="fp64"))["n_over_nbar"]
+        e = rel(profs[i], ref).max()
+        print(f"request {i}: max rel {e:.2e} fp64 attempts {stats[i]['fp64_steps']}", flush=True)
+        assert e <= 1e-4
+
+
+def test_batch_full_size_requests_equal_plain(ctx):
+    """Requests of the batched workload at their full drawn sizes: the batch
+    must reproduce the plain path (itself checked against sampled oracle
+    trajectories at full size) bit for bit."""
+    reqs = W.batched(7, n_req=24)
+    say(f"batch fp64 24 full-size requests, n_traj {sum(r.n_traj for r in reqs)}")
+    profs, stats, rc = run_batch(ctx, reqs)
+    assert rc == 0
+    for i in (0, 5, 11, 23):
+        p, st = run_plain(ctx, reqs[i])
+        assert np.array_equal(p, profs[i]), (i, rel(p, profs[i]).max())
+        assert st["accepted_steps"] == stats[i]["accepted_steps"]
+
+
+def test_batch_rejects_mixed_precision_and_rk4(ctx):
+    from paper_2410_08267_amd import nuhalo as N
+    a = W.shrink(W.plain_scale(0), 3, 8, 4)
+    out = torch.empty(64, dtype=torch.float64, device="cuda")
+    with pytest.raises(N.NhError):
+        ctx.solve_batch([a, a.with_(precision="fp32c")], out)
+    with pytest.raises(N.NhError):
+        ctx.solve_batch([a.with_(method="rk4", n_steps=50)], out)
+    with options(ctx, batch_slots=2, table_nodes=3000):
+        with pytest.raises(N.NhError):
+            ctx.solve_batch([a], out)

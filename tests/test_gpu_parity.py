@@ -16,15 +16,15 @@ which average over all of them, carry the tolerance:
     GPU's elementary functions round differently from the C library's by a
     few ulps on every right-hand side).
   * Dormand-Prince FP64 at the oracle's rtol: n/nbar within 1e-8 relative (the
-    bound for the FP64 path), or within four times the oracle's own rounding
-    sensitivity where that is larger.  Adaptive step control amplifies
-    rounding: for some halos the oracle's profile moves by ~1e-8 when its
-    force is perturbed by 1e-15 relative.  The sensitivity is measured per
-    case by the oracle built with FMA contraction (a re-rounding of the same
-    arithmetic).  Conditioned trajectories agree to 1e-6.
+    bound for the FP64 path), or within four times the oracle's own
+    sensitivity where that is larger.  Adaptive step control amplifies tiny
+    force differences into flipped accept/reject decisions: for some halos
+    the oracle's profile moves by ~1e-8 when its force is perturbed by 1e-12
+    relative, the size of the device's table interpolation error.  The
+    sensitivity is measured per case (conftest: re-rounding by the oracle
+    built with FMA contraction, and 1e-12 relative changes of the halo mass
+    and of G(z)).  Conditioned trajectories agree to 1e-6.
 """
-import ctypes
-import subprocess
 import math
 
 import numpy as np
@@ -55,27 +55,6 @@ def O():
     from oracle import oracle
     oracle.lib()
     return oracle
-
-
-@pytest.fixture(scope="module")
-def O_fma(O, tmp_path_factory):
-    """The oracle source built with FMA contraction: same arithmetic, other rounding."""
-    so = tmp_path_factory.mktemp("fma") / "oracle_fma.so"
-    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=fast", "-mfma",
-                    "-o", str(so), O._SRC, "-lm"], check=True)
-    L = ctypes.CDLL(str(so))
-    L.nho_integrate.argtypes = O.lib().nho_integrate.argtypes
-    return L
-
-
-def rounding_sensitivity(O, O_fma, req, ref_profile):
-    saved = O._lib
-    try:
-        O._lib = O_fma
-        other = O.solve(req)["n_over_nbar"]
-    finally:
-        O._lib = saved
-    return float(rel(other, ref_profile).max())
 
 
 def rel(a, b):
@@ -164,7 +143,7 @@ DP5_CASES = {
 
 
 @pytest.mark.parametrize("name", sorted(DP5_CASES))
-def test_dp5_matches_oracle(ctx, O, O_fma, name):
+def test_dp5_matches_oracle(ctx, O, sensitivity, name):
     req = DP5_CASES[name]()
     say(f"dp5 {name} n_traj={req.n_traj} M0={req.M0:.3g} m={req.m_eV}")
     prof, ratio, stats = gpu_ratios(ctx, req)
@@ -173,8 +152,8 @@ def test_dp5_matches_oracle(ctx, O, O_fma, name):
     d = rel(ratio, ref["ratio"])
     acc_ref = int(ref["accepted"].sum())
     ok = conditioned(O, req, ref["ratio"])
-    sens = rounding_sensitivity(O, O_fma, req, ref["n_over_nbar"])
-    print(f"n/nbar max rel {e.max():.2e} (oracle rounding sensitivity {sens:.2e}); "
+    sens = sensitivity(req, ref["n_over_nbar"])
+    print(f"n/nbar max rel {e.max():.2e} (oracle sensitivity {sens:.2e}); "
           f"ratio median {np.median(d):.2e} p99 {np.quantile(d, 0.99):.2e} "
           f"max {d.max():.2e}; conditioned {ok.mean():.4f} p99 {np.quantile(d[ok], 0.99):.2e}; "
           f"steps gpu {stats['accepted_steps']} oracle {acc_ref} free exits {stats['free_exits']}",
