@@ -130,6 +130,53 @@ def batched_leg(ctx, n_req: int):
     return res
 
 
+def serving_leg(ctx, capacity: float, prec: str, n_req: int, loads=(0.5, 0.9), warm: int = 50):
+    """Poisson arrivals of serving-workload requests at fractions of the batched
+    capacity (profiles/s): p50/p99 latency from arrival to result, throughput."""
+    import numpy as np
+    from paper_2410_08267_amd import nuhalo as N
+    from paper_2410_08267_amd import workloads as W
+    out = {}
+    for frac in loads:
+        qps = frac * capacity
+        arrivals, reqs = W.serving(17, n_req + warm, qps, prec=prec)
+        t0 = time.monotonic()
+        pending = {}
+        lat = np.full(len(reqs), np.nan)
+        done_t = np.full(len(reqs), np.nan)
+        i = 0
+        while i < len(reqs) or pending:
+            now = time.monotonic() - t0
+            while i < len(reqs) and arrivals[i] <= now:
+                tk = ctx.submit(reqs[i])
+                if tk is None:
+                    break                     # over budget: retry (latency keeps counting)
+                pending[tk] = i
+                i += 1
+            for tk in list(pending):
+                j = pending[tk]
+                r = ctx.poll(tk, reqs[j].n_r)
+                if r is not None:
+                    tdone = time.monotonic() - t0
+                    lat[j] = tdone - arrivals[j]
+                    done_t[j] = tdone
+                    del pending[tk]
+            time.sleep(0.0005)
+        m = lat[warm:]
+        span = np.nanmax(done_t[warm:]) - arrivals[warm]
+        out[f"load_{frac:g}"] = {
+            "offered_qps": qps,
+            "requests": n_req,
+            "p50_ms": float(np.percentile(m, 50) * 1e3),
+            "p99_ms": float(np.percentile(m, 99) * 1e3),
+            "mean_ms": float(np.mean(m) * 1e3),
+            "profiles_per_s": n_req / span,
+        }
+        print(f"[bench] serving {prec} at {frac:g} C: p50 {out[f'load_{frac:g}']['p50_ms']:.1f} ms "
+              f"p99 {out[f'load_{frac:g}']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +189,9 @@ def main():
     ap.add_argument("--no-batched", dest="batched", action="store_false",
                     help="skip the batched leg (heterogeneous requests in one launch)")
     ap.add_argument("--batch-requests", type=int, default=512)
+    ap.add_argument("--no-serving", dest="serving", action="store_false",
+                    help="skip the serving leg (Poisson arrivals, p50/p99 latency)")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (counter calibration)")
     args = ap.parse_args()
@@ -226,6 +276,11 @@ def main():
     batched = {}
     if args.batched:
         batched = batched_leg(ctx, args.batch_requests)
+    serving = {}
+    if args.serving and args.batched:
+        for prec in ("fp32c", "fp64"):
+            serving[prec] = serving_leg(ctx, batched[prec]["profiles_per_s"], prec, args.serve_requests)
+            serving[prec]["capacity_profiles_per_s"] = batched[prec]["profiles_per_s"]
 
     value = acc / dt
     kern_s = sum(kernel_ms) / 1e3
@@ -270,6 +325,8 @@ def main():
         line["fp32c"] = prec
     if batched:
         line["batched"] = batched
+    if serving:
+        line["serving"] = serving
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     ctx.close()

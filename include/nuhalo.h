@@ -176,7 +176,9 @@ typedef struct {
     long long n_failed;            /* trajectories with a non-OK status */
     long long fp64_steps;          /* NH_FP32C: attempted steps run in FP64 */
     long long free_exits;          /* trajectories finished by the exact free-streaming exit */
-    double    kernel_ms;           /* device time of the trajectory kernel(s) */
+    double    kernel_ms;           /* device time of the trajectory kernel(s); serving: the
+                                      slices the request took part in */
+    double    latency_ms;          /* serving: nh_submit -> result ready on the host; else 0 */
 } nh_stats;
 
 typedef struct nh_context nh_context;
@@ -213,12 +215,14 @@ enum {
     NH_OPT_BLOCK_THREADS = 5,  /* Dormand-Prince threads per workgroup, multiple of 64 in
                                   [64, 1024] [512]; one table copy in LDS per workgroup
                                   (the batched and serving forms use at most 512) */
-    NH_OPT_BATCH_SLOTS   = 6   /* batched and serving forms: request tables per workgroup in
+    NH_OPT_BATCH_SLOTS   = 6,  /* batched and serving forms: request tables per workgroup in
                                   LDS, 1 or 2, or 0 for the default [0]: 1 for FP64 (3073
                                   nodes, the plain form's table; a workgroup drains before it
                                   changes request), 2 for FP32C (3073 FP32 nodes each; lanes
                                   keep integrating while the next table loads).  Two FP64
                                   tables hold at most 2044 (constant R) or 1703 nodes. */
+    NH_OPT_SLICE_US      = 7   /* serving: length of a time slice in microseconds, 200..1e6 [4000];
+                                  requests are admitted and retired between slices */
 };
 int nh_set_option(nh_context *ctx, int option, double value);
 
@@ -261,22 +265,37 @@ int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d
                    nh_stats *stats, void *stream);
 
 /* ---- serving (continuous batching) ------------------------------------ */
+/* A worker thread of the context runs the slice kernel in time slices over
+ * the admitted requests; in-flight trajectories are saved to device memory at
+ * the end of a slice and resumed bit for bit by the next one, and requests are
+ * admitted and retired between slices.  A request's profile does not depend
+ * on what else is being served.  Requests must use NH_DOPRI5; one precision at
+ * a time (that of the first request admitted while the server is empty).
+ * Tables and slots per workgroup follow NH_OPT_TABLE_NODES / NH_OPT_BATCH_SLOTS;
+ * the slice length is NH_OPT_SLICE_US.  All serving calls are thread-safe. */
 
-/* Device-memory budget (bytes) for admitted serving requests; 0 = 80 % of
- * free device memory at the first submit.  Needs no GPU when bytes > 0. */
+/* Device-memory budget (bytes) for admitted requests (their tables, grids,
+ * per-trajectory results and profile); 0 = the smaller of 80 % of the free
+ * device memory and 32 GiB, taken at the first submit.  The budget is
+ * allocated once, when the first request is admitted.  NH_EBUSY while
+ * requests are admitted.  Needs no GPU. */
 int nh_serve_set_budget(nh_context *ctx, size_t bytes);
 
-/* Admit a request into the running batch, or NH_EBUSY if its footprint does
- * not fit the free budget right now (nothing is queued then).
+/* Admit a request, or NH_EBUSY if its footprint (nh_footprint_bytes) does not
+ * fit the free budget right now (nothing is queued then).  NH_EINVAL for an
+ * invalid request, a method other than NH_DOPRI5 or another precision than
+ * the one being served.  Host inputs are copied before the call returns.
  * ticket: receives an id for nh_poll / nh_cancel. */
 int nh_submit(nh_context *ctx, const nh_request *req, uint64_t *ticket);
 
 /* Collect a finished ticket.  out: host, n_r doubles.  stats: may be NULL.
- * NH_ENOTREADY while the ticket runs; after a successful poll the ticket is gone. */
+ * NH_ENOTREADY while the ticket runs; NH_OK (or NH_ESTEPS / NH_ENONFINITE with
+ * the profile written) once, after which the ticket is gone. */
 int nh_poll(nh_context *ctx, uint64_t ticket, double *out, nh_stats *stats);
 
-/* Cancel a ticket; its trajectories are dropped from the batch and its memory
- * returns to the budget.  Polling it afterwards returns NH_ECANCELED once. */
+/* Cancel a ticket: its remaining trajectories are dropped and its memory
+ * returns to the budget (once the next slice boundary has passed).  Polling it
+ * afterwards returns NH_ECANCELED once.  NH_ENOTFOUND for an unknown ticket. */
 int nh_cancel(nh_context *ctx, uint64_t ticket);
 
 /* ---- host-side helpers (need no GPU) --------------------------------------- */

@@ -312,6 +312,10 @@ int nh_set_option(nh_context *ctx, int option, double value)
             return set_err(ctx, NH_EINVAL, "table nodes must be 0 (default) or an integer in [64, 3073]");
         ctx->table_nodes = (int)value;
         return NH_OK;
+    case NH_OPT_SLICE_US:
+        if (value < 200.0 || value > 1.0e6) return set_err(ctx, NH_EINVAL, "slice length must be in [200, 1e6] us");
+        ctx->slice_us = value;
+        return NH_OK;
     case NH_OPT_BATCH_SLOTS:
         if (value != 0.0 && value != 1.0 && value != 2.0)
             return set_err(ctx, NH_EINVAL, "batch slots is 0 (default), 1 or 2");

@@ -57,35 +57,39 @@ __device__ __forceinline__ int pick_request(const SliceArgs &A)
             const int r = A.order[c];
             if (remaining_of(A, r) > 0) return r;
         }
-        // every request is open: help the one with the most unclaimed trajectories
-        long long best = 0;
-        int bi = -1;
+    } else {
         for (int b = 0; b < A.n_order; b += 64) {
             const int i = b + lane;
-            const long long rem = i < A.n_order ? remaining_of(A, A.order[i]) : 0;
-            if (rem > best) {
-                best = rem;
-                bi = i;
+            bool fresh = false;
+            if (i < A.n_order) {
+                const int r = A.order[i];
+                fresh = !A.reqs[r].retired &&
+                        __hip_atomic_load(&A.next[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0ull;
             }
+            const unsigned long long m = __ballot(fresh);
+            if (m) return A.order[b + __ffsll((unsigned long long)m) - 1];
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const long long ob = __shfl_xor(best, off);
-            const int oi = __shfl_xor(bi, off);
-            if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        return best > 0 ? A.order[bi] : -1;
     }
-    // POLICY_OLDEST_FIRST
+    // every request is open: help the one with the most unclaimed trajectories
+    long long best = 0;
+    int bi = -1;
     for (int b = 0; b < A.n_order; b += 64) {
         const int i = b + lane;
-        const bool has = i < A.n_order && remaining_of(A, A.order[i]) > 0;
-        const unsigned long long m = __ballot(has);
-        if (m) return A.order[b + __ffsll((unsigned long long)m) - 1];
+        const long long rem = i < A.n_order ? remaining_of(A, A.order[i]) : 0;
+        if (rem > best) {
+            best = rem;
+            bi = i;
+        }
     }
-    return -1;
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    return best > 0 ? A.order[bi] : -1;
 }
 
 // Called by a whole wavefront (all 64 lanes converged) when the lanes in

@@ -45,6 +45,7 @@ struct nh_context {
     int table_nodes = 0;                             // 0: default_table_nodes()
     int block_threads = 512;                         // Dormand-Prince workgroup size
     int batch_slots = 0;                             // tables per workgroup, batched form (0: default)
+    double slice_us = 4000.0;                        // serving: time slice length
     nh::ServeState *serve = nullptr;
 };
 

@@ -87,8 +87,11 @@ struct TrajOut {
 // ---- batched and serving forms (scheduling: nh_batch.h) ----
 
 enum : int {
-    POLICY_OPEN_FIRST = 0,    // open requests in order, then help the one with most work left
-    POLICY_OLDEST_FIRST = 1,  // always draw from the oldest request with work left
+    POLICY_OPEN_FIRST = 0,      // open requests in order (a shared cursor: one workgroup each),
+                                // then help the one with the most work left
+    POLICY_UNOPENED_FIRST = 1,  // the oldest request nobody has drawn from yet, else help the
+                                // one with the most work left (no cursor: the request list
+                                // changes between slices)
 };
 
 // One request as the slice kernels see it (device array).

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libnuhalo.so")
 NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ESTEPS = 0, -1, -2, -3, -4
 NH_ENONFINITE, NH_EBUSY, NH_ENOTREADY, NH_ENOTFOUND, NH_ECANCELED = -5, -6, -7, -8, -9
 OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4, "block_threads": 5,
-           "batch_slots": 6}
+           "batch_slots": 6, "slice_us": 7}
 
 _MASS = {"zero": 0, "paper": 1, "exponential": 2}
 _CONC = {"constant": 0, "power": 1}
@@ -82,7 +82,8 @@ class nh_stats(ctypes.Structure):
     _fields_ = [("n_traj", ctypes.c_longlong), ("accepted_steps", ctypes.c_longlong),
                 ("rejected_steps", ctypes.c_longlong), ("max_steps_one_traj", ctypes.c_longlong),
                 ("n_failed", ctypes.c_longlong), ("fp64_steps", ctypes.c_longlong),
-                ("free_exits", ctypes.c_longlong), ("kernel_ms", ctypes.c_double)]
+                ("free_exits", ctypes.c_longlong), ("kernel_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
