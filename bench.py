@@ -35,15 +35,15 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # HBM bytes per k_dp5_f64 launch on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (seeds 0 and 1), each scaled by what the counter reads for a plain
-# 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the kernel
-# sources these hashes name; any change to them reports traffic as null.
-TRAFFIC_BYTES_PER_LAUNCH = 93211696
+# 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the sources and
+# build flags these hashes name; any change to them reports traffic as null.
+TRAFFIC_BYTES_PER_LAUNCH = 93592116
 TRAFFIC_SOURCES = {
-    "kernels_f64.hip": "81edee914d1b4482c38a623d1aeafbdafc095a74db2f73a2974ca9653b07f9bd",
+    "kernels_f64.hip": "565d784da533bea0462efd53e0d7ee3a455e14e95a5c767f11420c8c75f2788d",
     "nh_dp5.h": "25c2778fd6db8cf6f248f33be254c5f009357bb3983e01db98bc5782eb40254a",
-    "nh_device.h": "01c6def04c76201070f07642643834edd324e64cfbf5e9f23444961c56df8aba",
-    "nh_internal.h": "46c1b4588344e70e0d1c4a9093e339b8f878ba5f1d0ce4415b60a3a5fec1b684",
-    "../build.py": None,
+    "nh_device.h": "3323d5897aa888ad4f26bf235ed1e71a2deaa5501c63ec949c2f477631311a24",
+    "nh_internal.h": "0aca23be10b7948e506b6e674d212379305d975e194c13381940943b1beab691",
+    "../build.py": "02d0e50104314a81e52ea23b7739d80dc352af57069babf1308fd6cf5c118f35",
 }
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
 
@@ -53,8 +53,6 @@ def measured_traffic():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2410_08267_amd", "csrc")
     for name, digest in TRAFFIC_SOURCES.items():
-        if digest is None:
-            return None
         try:
             with open(os.path.join(csrc, name), "rb") as f:
                 if hashlib.sha256(f.read()).hexdigest() != digest:
@@ -117,6 +115,7 @@ def batched_leg(ctx, n_req: int):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         acc = sum(st["accepted_steps"] for st in stats)
+        att = acc + sum(st["rejected_steps"] for st in stats)
         res[prec] = {
             "profiles_per_s": n_req / dt,
             "seconds": dt,
@@ -125,6 +124,11 @@ def batched_leg(ctx, n_req: int):
             "trajectory_steps_per_s": acc / dt,
             "failed": sum(st["n_failed"] for st in stats),
         }
+        if prec == "fp64":
+            tf = FLOP_PER_DP5_ATTEMPT * att / (stats[0]["kernel_ms"] / 1e3) / 1e12
+            res[prec]["kernel"] = "k_slice_f64"
+            res[prec]["achieved_tflops"] = tf
+            res[prec]["frac_of_fp64_peak"] = tf / FP64_VECTOR_PEAK_TFLOPS
         print(f"[bench] batched {prec}: {n_req} requests {n_traj} trajectories in {dt:.2f} s", file=sys.stderr,
               flush=True)
     return res
@@ -177,6 +181,85 @@ def serving_leg(ctx, capacity: float, prec: str, n_req: int, loads=(0.5, 0.9), w
     return out
 
 
+def plain_leg(ctx, stream, reqs, warmup):
+    """The headline: one FP64 profile of the plain-at-scale workload per step."""
+    import torch
+    from paper_2410_08267_amd import workloads as W
+    out = torch.empty(128, dtype=torch.float64, device="cuda")
+    for i in range(warmup):
+        ctx.solve_async(W.plain_scale(1000 + i), out, stream=stream)
+        ctx.last_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = rej = 0
+    kernel_ms = []
+    for r in reqs:
+        ctx.solve_async(r, out, stream=stream)
+        st, _ = ctx.last_stats()
+        acc += st["accepted_steps"]
+        rej += st["rejected_steps"]
+        kernel_ms.append(st["kernel_ms"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_s = sum(kernel_ms) / 1e3
+    achieved = FLOP_PER_DP5_ATTEMPT * (acc + rej) / kern_s / 1e12
+    return {
+        "value": acc / dt,
+        "ms_per_step": dt / len(reqs) * 1e3,
+        "profiles_per_s": len(reqs) / dt,
+        "accepted_steps": acc,
+        "rejected_steps": rej,
+        "kernel_ms_avg": sum(kernel_ms) / len(kernel_ms),
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch",
+            "kernel": "k_dp5_f64",
+            "flop_per_attempt": FLOP_PER_DP5_ATTEMPT,
+        },
+    }
+
+
+def fp32c_leg(ctx, stream, reqs):
+    """The FP32-compensated form on the same halos: profiles/s and deviation from FP64."""
+    import numpy as np
+    import torch
+    from paper_2410_08267_amd import workloads as W
+    out = torch.empty(128, dtype=torch.float64, device="cuda")
+    prof64 = []
+    for r in reqs:
+        ctx.solve_async(r, out, stream=stream)
+        ctx.last_stats()
+        prof64.append(out[:r.n_r].cpu().numpy().copy())
+    reqs32 = [r.with_(precision="fp32c") for r in reqs]
+    ctx.solve_async(W.plain_scale(1000).with_(precision="fp32c"), out, stream=stream)
+    ctx.last_stats()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    acc32 = f64 = 0
+    errs = []
+    for r, p64 in zip(reqs32, prof64):
+        ctx.solve_async(r, out, stream=stream)
+        st, _ = ctx.last_stats()
+        acc32 += st["accepted_steps"]
+        f64 += st["fp64_steps"]
+        errs.append(float(np.max(np.abs(out[:r.n_r].cpu().numpy() / p64 - 1.0))))
+    torch.cuda.synchronize()
+    dt32 = time.perf_counter() - t1
+    return {
+        "trajectory_steps_per_s": acc32 / dt32,
+        "profiles_per_s": len(reqs32) / dt32,
+        "ms_per_step": dt32 / len(reqs32) * 1e3,
+        "fp64_attempts": f64,
+        "max_rel_err_vs_fp64_path": max(errs),
+        "rtol": 1e-6,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +267,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="plain,fp32c,batched,serving",
+                    help="comma list of legs: plain (the headline value), fp32c, batched, serving")
     ap.add_argument("--no-fp32c", dest="fp32c", action="store_false",
                     help="skip the FP32-compensated leg")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
@@ -195,6 +280,11 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (counter calibration)")
     args = ap.parse_args()
+    legs = set(args.legs.split(","))
+    args.fp32c = args.fp32c and "fp32c" in legs
+    args.batched = args.batched and "batched" in legs
+    args.serving = args.serving and "serving" in legs
+    plain = "plain" in legs
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the profile path is built and measured on a single "
@@ -221,78 +311,15 @@ def main():
         return
     ctx = N.Context(0)
     stream = torch.cuda.current_stream(dev)
-    out = torch.empty(128, dtype=torch.float64, device=dev)
-
-    for i in range(args.warmup):
-        ctx.solve_async(W.plain_scale(1000 + i), out, stream=stream)
-        ctx.last_stats()
     reqs = [W.plain_scale(s) for s in range(args.steps)]
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    acc = rej = 0
-    kernel_ms = []
-    for r in reqs:
-        ctx.solve_async(r, out, stream=stream)
-        st, _ = ctx.last_stats()
-        acc += st["accepted_steps"]
-        rej += st["rejected_steps"]
-        kernel_ms.append(st["kernel_ms"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
-    # FP32-compensated form on the same halos: profiles/s and deviation from FP64
-    prec = {}
-    if args.fp32c:
-        prof64 = []
-        for r in reqs:
-            ctx.solve_async(r, out, stream=stream)
-            ctx.last_stats()
-            prof64.append(out[:r.n_r].cpu().numpy().copy())
-        reqs32 = [r.with_(precision="fp32c") for r in reqs]
-        ctx.solve_async(W.plain_scale(1000).with_(precision="fp32c"), out, stream=stream)
-        ctx.last_stats()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        acc32 = f64 = 0
-        errs = []
-        for r, p64 in zip(reqs32, prof64):
-            ctx.solve_async(r, out, stream=stream)
-            st, _ = ctx.last_stats()
-            acc32 += st["accepted_steps"]
-            f64 += st["fp64_steps"]
-            errs.append(float(np.max(np.abs(out[:r.n_r].cpu().numpy() / p64 - 1.0))))
-        torch.cuda.synchronize()
-        dt32 = time.perf_counter() - t1
-        prec = {
-            "trajectory_steps_per_s": acc32 / dt32,
-            "profiles_per_s": len(reqs32) / dt32,
-            "ms_per_step": dt32 / len(reqs32) * 1e3,
-            "fp64_attempts": f64,
-            "max_rel_err_vs_fp64_path": max(errs),
-            "rtol": 1e-6,
-        }
-
-    batched = {}
-    if args.batched:
-        batched = batched_leg(ctx, args.batch_requests)
-    serving = {}
-    if args.serving and args.batched:
-        for prec in ("fp32c", "fp64"):
-            serving[prec] = serving_leg(ctx, batched[prec]["profiles_per_s"], prec, args.serve_requests)
-            serving[prec]["capacity_profiles_per_s"] = batched[prec]["profiles_per_s"]
-
-    value = acc / dt
-    kern_s = sum(kernel_ms) / 1e3
-    achieved = FLOP_PER_DP5_ATTEMPT * (acc + rej) / kern_s / 1e12
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": None,
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -305,27 +332,19 @@ def main():
             "trajectories_per_step": reqs[0].n_traj,
             "precision": "fp64",
         },
-        "profiles_per_s": args.steps / dt,
-        "accepted_steps": acc,
-        "rejected_steps": rej,
-        "kernel_ms_avg": sum(kernel_ms) / len(kernel_ms),
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": measured_traffic(),
-            "traffic_unit": "bytes per launch",
-            "kernel": "k_dp5_f64",
-            "flop_per_attempt": FLOP_PER_DP5_ATTEMPT,
-        },
     }
-    if prec:
-        line["fp32c"] = prec
-    if batched:
-        line["batched"] = batched
-    if serving:
+    if plain:
+        line.update(plain_leg(ctx, stream, reqs, args.warmup))
+    if args.fp32c:
+        line["fp32c"] = fp32c_leg(ctx, stream, reqs)
+    if args.batched:
+        line["batched"] = batched_leg(ctx, args.batch_requests)
+    if args.serving and args.batched:
+        serving = {}
+        for pr in ("fp32c", "fp64"):
+            cap = line["batched"][pr]["profiles_per_s"]
+            serving[pr] = serving_leg(ctx, cap, pr, args.serve_requests)
+            serving[pr]["capacity_profiles_per_s"] = cap
         line["serving"] = serving
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)

@@ -212,9 +212,11 @@ enum {
     NH_OPT_TABLE_NODES   = 4,  /* Dormand-Prince coefficient table nodes, 64..3073, or 0 for the
                                   default [0]: 3073, or for the batched and serving forms as many
                                   as their LDS slots hold (a larger value is NH_EINVAL there) */
-    NH_OPT_BLOCK_THREADS = 5,  /* Dormand-Prince threads per workgroup, multiple of 64 in
-                                  [64, 1024] [512]; one table copy in LDS per workgroup
-                                  (the batched and serving forms use at most 512) */
+    NH_OPT_BLOCK_THREADS = 5,  /* Dormand-Prince threads per workgroup, a multiple of 64 in
+                                  [64, 1024], or 0 for the defaults [0]: 512 for nh_solve (one
+                                  table copy in LDS per workgroup; more lanes per profile
+                                  lengthen its tail) and for the FP32C kernels (their limit),
+                                  1024 for FP64 batches and serving (four waves per SIMD) */
     NH_OPT_BATCH_SLOTS   = 6,  /* batched and serving forms: request tables per workgroup in
                                   LDS, 1 or 2, or 0 for the default [0]: 1 for FP64 (3073
                                   nodes, the plain form's table; a workgroup drains before it

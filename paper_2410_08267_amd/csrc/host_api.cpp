@@ -303,8 +303,8 @@ int nh_set_option(nh_context *ctx, int option, double value)
         ctx->h_fp64 = value;
         return NH_OK;
     case NH_OPT_BLOCK_THREADS:
-        if (value < 64 || value > 1024 || value != (double)(64 * (int)(value / 64)))
-            return set_err(ctx, NH_EINVAL, "block threads must be a multiple of 64 in [64, 1024]");
+        if (value != 0.0 && (value < 64 || value > 1024 || value != (double)(64 * (int)(value / 64))))
+            return set_err(ctx, NH_EINVAL, "block threads must be 0 (default) or a multiple of 64 in [64, 1024]");
         ctx->block_threads = (int)value;
         return NH_OK;
     case NH_OPT_TABLE_NODES:

@@ -23,6 +23,13 @@ int request_columns(const nh_request *q)
     return (q->halo.compensated && q->halo.geometry == NH_GEOM_DELTA200) ? NCOL : NCOL - 1;
 }
 
+int batch_block(const nh_context *ctx, bool f32c)
+{
+    // FP64 slices fit four waves per SIMD (1024 threads); the FP32C lane state two
+    const int cap = f32c ? 512 : 1024;
+    return ctx->block_threads > 0 ? std::min(ctx->block_threads, cap) : cap;
+}
+
 int batch_slots(const nh_context *ctx, bool f32c)
 {
     return ctx->batch_slots > 0 ? ctx->batch_slots : (f32c ? 2 : 1);
@@ -123,7 +130,7 @@ int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d
     const int slots = batch_slots(ctx, f32c);
     int n_tab = 0;
     if ((rc = batch_table_nodes(ctx, f32c, nc, slots, &n_tab)) != NH_OK) return rc;
-    const int block = std::min(ctx->block_threads, 512);
+    const int block = batch_block(ctx, f32c);
     hipStream_t s = (hipStream_t)stream;
 
     HIPCHK(hipSetDevice(ctx->device));

@@ -207,8 +207,10 @@ __device__ __forceinline__ void setup32(const BatchReq &q, const float *slot, La
 // FP64 slice kernel
 // ---------------------------------------------------------------------------
 
+// FP64 slices run up to 1024 threads per workgroup (four waves per SIMD); the
+// FP32-compensated lane state needs more than the 128 VGPRs that allows.
 template <int NC, int SLOTS>
-__global__ __launch_bounds__(512) void k_slice_f64(SliceArgs A)
+__global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
 {
     extern __shared__ double lds64[];
     __shared__ WgSched S;

@@ -72,7 +72,7 @@ template <int NC>
 static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                  unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    const int B = P.block > 0 ? P.block : 512;
+    const int B = P.block > 0 && P.block < 512 ? P.block : 512;   // launch bound of k_dp5_f32c
     const size_t lds = (size_t)P.n_tab * NC * sizeof(float);
     hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f32c<NC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -100,10 +100,13 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
 // Dormand-Prince 5(4), adaptive; persistent waves refill lanes from a queue
 // ---------------------------------------------------------------------------
 
-// One block per CU: the table takes most of the LDS, and the register budget
-// (<= 128 VGPRs) allows four waves per SIMD.
+// One block per CU: the table takes most of the LDS.  The kernel fits 128
+// VGPRs, so blocks of up to 1024 threads (four waves per SIMD) are possible;
+// 512 is the default: a single profile has ~1e6 trajectories, and more lanes
+// per profile lengthen the tail where the last long trajectories run alone.
 template <int NC>
 constexpr int dp5_block() { return 1024; }
+constexpr int DP5_DEFAULT_BLOCK = 512;
 
 template <int NC>
 __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
@@ -206,7 +209,7 @@ template <int NC>
 static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                 unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    const int B = P.block > 0 ? P.block : dp5_block<NC>();
+    const int B = P.block > 0 ? P.block : DP5_DEFAULT_BLOCK;
     const size_t lds = (size_t)P.n_tab * NC * sizeof(double);
     hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f64<NC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

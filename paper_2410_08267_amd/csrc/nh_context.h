@@ -43,7 +43,7 @@ struct nh_context {
     bool free_exit = true;
     double h_fp64 = 1.0e-5;                          // FP32C: |h| below this runs in FP64
     int table_nodes = 0;                             // 0: default_table_nodes()
-    int block_threads = 512;                         // Dormand-Prince workgroup size
+    int block_threads = 0;                           // Dormand-Prince workgroup size (0: default)
     int batch_slots = 0;                             // tables per workgroup, batched form (0: default)
     double slice_us = 4000.0;                        // serving: time slice length
     nh::ServeState *serve = nullptr;
@@ -62,6 +62,7 @@ void serve_shutdown(nh_context *ctx);
 int wait_pending(nh_context *ctx);
 int request_columns(const nh_request *q);
 int batch_slots(const nh_context *ctx, bool f32c);
+int batch_block(const nh_context *ctx, bool f32c);
 int batch_table_nodes(nh_context *ctx, bool f32c, int nc, int slots, int *n_tab);
 
 #define HIPCHK(call)                                                                     \
