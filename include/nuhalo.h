@@ -63,20 +63,39 @@ typedef struct {
 enum {
     NH_MASS_ZERO        = 0,  /* no halo: free streaming, n/nbar = 1 */
     NH_MASS_PAPER       = 1,  /* M0 * xi(z)^alpha, xi = clamp((z_form - z)/z_form, 0, 1) */
-    NH_MASS_EXPONENTIAL = 2   /* M0 * exp(-beta z) */
+    NH_MASS_EXPONENTIAL = 2,  /* M0 * exp(-beta z) */
+    NH_MASS_TABLE       = 3   /* sampled: halo.history.M_Msun (M0 unused) */
 };
 /* Concentration history c(z). */
 enum {
     NH_CONC_CONSTANT = 0,     /* c0 */
-    NH_CONC_POWER    = 1      /* c0 * (1+z)^(-gamma) */
+    NH_CONC_POWER    = 1,     /* c0 * (1+z)^(-gamma) */
+    NH_CONC_TABLE    = 2      /* sampled: halo.history.c */
 };
 /* Modulation of Newton's constant, G -> kappa(z) G (Sec. IV.B). */
 enum {
     NH_KAPPA_NONE     = 0,    /* kappa = 1 */
     NH_KAPPA_LOG      = 1,    /* 1 + a ln(1+z) */
     NH_KAPPA_PAPER    = 2,    /* 1 + a [z/(1+z)]^b */
-    NH_KAPPA_CONSTANT = 3     /* a */
+    NH_KAPPA_CONSTANT = 3,    /* a */
+    NH_KAPPA_TABLE    = 4     /* sampled: halo.history.kappa */
 };
+
+/* Histories given as samples (any halo growth model, Sec. IV.A; any G(z),
+ * Sec. IV.B).  Sample i is the value at u_i = u_min + i (0 - u_min)/(n-1),
+ * u = ln a = -ln(1+z), u_min = -ln(1 + z_max); i = n-1 is z = 0.  Between
+ * samples the value is the not-a-knot cubic spline through all samples (twice
+ * continuously differentiable, exact for cubics; with n = 4 the single cubic
+ * through them).  n >= 4, z_max >= integ.z_end.  Masses >= 0 with M(0) > 0;
+ * concentrations > 0 (also between samples); kappa finite.  Arrays are read
+ * only for the kinds set to *_TABLE and may be NULL otherwise. */
+typedef struct {
+    int           n;
+    double        z_max;
+    const double *M_Msun;    /* host, n */
+    const double *c;         /* host, n */
+    const double *kappa;     /* host, n */
+} nh_history;
 /* Halo geometry. */
 enum {
     NH_GEOM_PAPER    = 0,     /* Sec. II.B: R from M(0) via M = (4 pi/3) R^3 rhobar_m0;
@@ -104,16 +123,26 @@ typedef struct {
     double kappa_b;
     int    geometry;     /* NH_GEOM_*; NH_GEOM_PAPER needs z_end <= 200^(1/3) - 1 */
     int    compensated;  /* 1 (paper) or 0 */
+    nh_history history;  /* samples for the *_TABLE kinds */
 } nh_halo;
 
 /* Initial (pre-halo) phase-space distribution of the relic, y = P / (k_B T). */
 enum {
     NH_F0_FERMI_DIRAC = 0,    /* 1 / (1 + e^y)  (Sec. II.C) */
-    NH_F0_FREEZE_IN   = 1     /* y^(-1/2) e^(-y) (Sec. IV.B; normalisation cancels) */
+    NH_F0_FREEZE_IN   = 1,    /* y^(-1/2) e^(-y) (Sec. IV.B; normalisation cancels) */
+    NH_F0_TABLE       = 2     /* sampled: ln f0 at ln y_i = ln_y0 + i d_ln_y, i = 0..n-1
+                                 (n >= 4, d_ln_y > 0); inside the range the cubic through
+                                 the four samples around ln y (stencil shifted inward at
+                                 the ends), outside it continued linearly with the slope
+                                 of the end interval (power-law tails, Sec. IV.B) */
 };
 typedef struct {
-    int    kind;             /* NH_F0_* */
-    double T_K;              /* > 0; 1.95 K for the neutrino background */
+    int           kind;      /* NH_F0_* */
+    double        T_K;       /* > 0; 1.95 K for the neutrino background */
+    int           n;         /* NH_F0_TABLE */
+    double        ln_y0;
+    double        d_ln_y;
+    const double *ln_f;      /* host, n, finite; the normalisation cancels */
 } nh_f0;
 
 /* Grid.  Trajectory t = (k * n_y + j) * n_mu + l starts at x0 = (r_k, 0) with

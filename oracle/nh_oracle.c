@@ -48,19 +48,29 @@ typedef struct {
     double Omega_L;
     int    static_background;  /* test only: a == 1, u is plain time, no Hubble drag */
     /* halo (Sec. II.B) */
-    int    mass_kind;          /* 0 none, 1 paper xi(z)^alpha * M_h, 2 M0 exp(-beta z), 3 point mass (test) */
+    int    mass_kind;          /* 0 none, 1 paper xi(z)^alpha * M_h, 2 M0 exp(-beta z), 3 point mass (test),
+                                  4 sampled (hist_M) */
     double M0_Msun;
     double mass_alpha;         /* exponent of xi (Sec. IV.A); 1 is the base model */
     double z_form;             /* z_i of xi; 200^(1/3) - 1 in the base model */
     double mass_beta;          /* rate of the exponential M(z) */
-    int    conc_kind;          /* 0 constant c0, 1 c0 (1+z)^(-gamma) */
+    int    conc_kind;          /* 0 constant c0, 1 c0 (1+z)^(-gamma), 2 sampled (hist_c) */
     double c0;
     double conc_gamma;
-    int    kappa_kind;         /* 0 none, 1 1 + a ln(1+z), 2 1 + a [z/(1+z)]^b, 3 constant a (Sec. IV.B) */
+    int    kappa_kind;         /* 0 none, 1 1 + a ln(1+z), 2 1 + a [z/(1+z)]^b, 3 constant a, 4 sampled
+                                  (hist_kappa) (Sec. IV.B) */
     double kappa_a;
     double kappa_b;
     int    geometry;           /* 0 paper: fixed physical r200 = R / 200^(1/3); 1: 200 x mean density at each z */
     int    compensated;        /* 1 paper: underdense shell out to comoving R; 0 plain NFW + point mass */
+    /* sampled histories: samples at u_i = hist_u_min + i (0 - hist_u_min) / (hist_n - 1), u = ln a,
+       given as the pieces of their cubic spline: on [u_i, u_{i+1}] the value is
+       p[4i] t^3 + p[4i+1] t^2 + p[4i+2] t + p[4i+3] with t = u - u_i */
+    int           hist_n;
+    double        hist_u_min;
+    const double *hist_M;
+    const double *hist_c;
+    const double *hist_kappa;
 } nho_model;
 
 typedef struct {
@@ -117,6 +127,20 @@ double nho_nfw_I(double q)
 
 /* M(z): the perturbation's mass scale.  Paper: xi(z) M_h with
  * xi = [(z_i - z)/(z_i - z0)]^alpha clamped to [0,1], z0 = 0 (Sec. II.B, IV.A). */
+/* A sampled history at redshift z: the spline piece of the interval that
+ * holds u = ln a (the end pieces continue beyond the sampled range). */
+static double nho_sampled(const nho_model *m, const double *p, double z)
+{
+    double u = -log1p(z);
+    double du = (0.0 - m->hist_u_min) / (double)(m->hist_n - 1);
+    int i = (int)floor((u - m->hist_u_min) / du);
+    if (i < 0) i = 0;
+    if (i > m->hist_n - 2) i = m->hist_n - 2;
+    double t = u - (m->hist_u_min + (double)i * du);
+    const double *c = p + 4 * i;
+    return ((c[0] * t + c[1]) * t + c[2]) * t + c[3];
+}
+
 double nho_mass(const nho_model *m, double z)
 {
     switch (m->mass_kind) {
@@ -130,6 +154,8 @@ double nho_mass(const nho_model *m, double z)
         return m->M0_Msun * exp(-m->mass_beta * z);
     case 3:
         return m->M0_Msun;
+    case 4:
+        return nho_sampled(m, m->hist_M, z);
     default:
         return 0.0;
     }
@@ -138,6 +164,7 @@ double nho_mass(const nho_model *m, double z)
 double nho_conc(const nho_model *m, double z)
 {
     if (m->conc_kind == 1) return m->c0 * pow(1.0 + z, -m->conc_gamma);
+    if (m->conc_kind == 2) return nho_sampled(m, m->hist_c, z);
     return m->c0;
 }
 
@@ -148,6 +175,7 @@ double nho_kappa(const nho_model *m, double z)
     case 1: return 1.0 + m->kappa_a * log1p(z);
     case 2: return 1.0 + m->kappa_a * pow(z / (1.0 + z), m->kappa_b);
     case 3: return m->kappa_a;
+    case 4: return nho_sampled(m, m->hist_kappa, z);
     default: return 1.0;
     }
 }

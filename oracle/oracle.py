@@ -43,9 +43,9 @@ T_NU0_K = 1.95
 
 STATUS_OK, STATUS_MAXSTEPS, STATUS_UNDERFLOW, STATUS_NONFINITE = 0, 1, 2, 3
 
-_MASS_KIND = {"zero": 0, "paper": 1, "exponential": 2, "point": 3}
-_CONC_KIND = {"constant": 0, "power": 1}
-_KAPPA_KIND = {"none": 0, "log": 1, "paper": 2, "constant": 3}
+_MASS_KIND = {"zero": 0, "paper": 1, "exponential": 2, "point": 3, "table": 4}
+_CONC_KIND = {"constant": 0, "power": 1, "table": 2}
+_KAPPA_KIND = {"none": 0, "log": 1, "paper": 2, "constant": 3, "table": 4}
 _GEOMETRY = {"paper": 0, "delta200": 1}
 _METHOD = {"rk4": 0, "dp5": 1, "dp5_fixed": 2}
 
@@ -69,6 +69,11 @@ class _Model(ctypes.Structure):
         ("kappa_b", ctypes.c_double),
         ("geometry", ctypes.c_int),
         ("compensated", ctypes.c_int),
+        ("hist_n", ctypes.c_int),
+        ("hist_u_min", ctypes.c_double),
+        ("hist_M", ctypes.POINTER(ctypes.c_double)),
+        ("hist_c", ctypes.POINTER(ctypes.c_double)),
+        ("hist_kappa", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -162,6 +167,24 @@ def model_of(req, static_background: bool = False) -> _Model:
     m.kappa_b = float(req.kappa_b)
     m.geometry = _GEOMETRY[req.geometry]
     m.compensated = int(bool(req.compensated))
+    # sampled histories: the not-a-knot cubic spline through the samples in
+    # u = ln a (scipy's CubicSpline), handed to the C side as its polynomial
+    # pieces; the model keeps the coefficient arrays alive
+    m._keep = []
+    arrays = [getattr(req, "hist_" + k, None) for k in ("M", "c", "kappa")]
+    if any(a is not None for a in arrays):
+        from scipy.interpolate import CubicSpline
+        u_min = -math.log1p(float(req.hist_z_max))
+        m.hist_u_min = u_min
+        for name, a in zip(("hist_M", "hist_c", "hist_kappa"), arrays):
+            if a is None:
+                continue
+            a = np.asarray(a, dtype=np.float64)
+            u = u_min + np.arange(a.size) * (0.0 - u_min) / (a.size - 1)
+            pieces = np.ascontiguousarray(CubicSpline(u, a, bc_type="not-a-knot").c.T)   # (n-1, 4)
+            m._keep.append(pieces)
+            m.hist_n = a.size
+            setattr(m, name, pieces.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return m
 
 
@@ -228,6 +251,33 @@ def f0(kind: str, y):
         if kind == "freeze_in":
             return np.exp(-y) / np.sqrt(y)
     raise ValueError(f"unknown f0 kind {kind!r}")
+
+
+def f0_of(req, y):
+    """f0 of a request at y: the named distributions, or for f0_kind "table"
+    exp of the sampled ln f0 (samples at ln y = f0_ln_y0 + i f0_d_ln_y): the
+    cubic through four consecutive samples in Lagrange's form inside the
+    sampled range (nodes i-1..i+2 around the interval, moved inward in the
+    first and last one), the straight line through the two end samples
+    outside it."""
+    if req.f0_kind != "table":
+        return f0(req.f0_kind, y)
+    v = np.asarray(req.f0_ln_f, dtype=np.float64)
+    n = v.size
+    s = (np.log(np.asarray(y, dtype=np.float64)) - req.f0_ln_y0) / req.f0_d_ln_y
+    i = np.clip(np.floor(s).astype(np.int64), 1, n - 3)
+    inner = np.zeros_like(s)
+    for a in (-1, 0, 1, 2):
+        L = np.ones_like(s)
+        for b in (-1, 0, 1, 2):
+            if b != a:
+                L *= (s - (i + b)) / (a - b)
+        inner += L * v[i + a]
+    below = v[0] + (v[1] - v[0]) * s
+    above = v[n - 1] + (v[n - 1] - v[n - 2]) * (s - (n - 1))
+    lnf = np.where(s < 0, below, np.where(s > n - 1, above, inner))
+    with np.errstate(over="ignore"):
+        return np.exp(lnf)
 
 
 def velocity_per_y(m_eV: float, T_K: float) -> float:
@@ -328,12 +378,12 @@ def profile_from_ratio(req, ratio: np.ndarray) -> np.ndarray:
     ratio = np.asarray(ratio, dtype=np.float64).reshape(nr, ny, nm)
     wy = y_weights(y)
     W = wy[:, None] * w_mu[None, :]                     # (j, l)
-    f_bg = f0(req.f0_kind, np.broadcast_to(y[:, None], (ny, nm)))
+    f_bg = f0_of(req, np.broadcast_to(y[:, None], (ny, nm)))
     den = math.fsum((W * f_bg).ravel().tolist())
     out = np.empty(nr)
     for k in range(nr):
         yi = y[:, None] * ratio[k]
-        num = math.fsum((W * f0(req.f0_kind, yi)).ravel().tolist())
+        num = math.fsum((W * f0_of(req, yi)).ravel().tolist())
         out[k] = num / den
     return out
 
@@ -374,6 +424,17 @@ def halo_radii(req, z: float):
     m = model_of(req)
     lib().nho_radii(ctypes.byref(m), float(z), ctypes.byref(R), ctypes.byref(rv))
     return R.value, rv.value
+
+
+def histories(req, z):
+    """(M(z), c(z), kappa(z)) of the request's halo at each redshift in z."""
+    m = model_of(req)
+    L = lib()
+    z = np.atleast_1d(np.asarray(z, dtype=np.float64))
+    M = np.array([L.nho_mass(ctypes.byref(m), float(zz)) for zz in z])
+    c = np.array([L.nho_conc(ctypes.byref(m), float(zz)) for zz in z])
+    k = np.array([L.nho_kappa(ctypes.byref(m), float(zz)) for zz in z])
+    return M, c, k
 
 
 def hubble(req, z: float) -> float:

@@ -83,6 +83,11 @@ Staged stage_layout(const nh_request *q, int table_nodes)
     s.off_mu = off;   off = align_up(off + (size_t)q->grid.n_mu * sizeof(double));
     s.off_smu = off;  off = align_up(off + (size_t)q->grid.n_mu * sizeof(double));
     s.off_wmu = off;  off = align_up(off + (size_t)q->grid.n_mu * sizeof(double));
+    s.f0_kind = q->f0.kind;
+    s.f0_n = q->f0.kind == NH_F0_TABLE ? q->f0.n : 0;
+    s.f0_x0 = q->f0.kind == NH_F0_TABLE ? q->f0.ln_y0 : 0.0;
+    s.f0_inv_dx = q->f0.kind == NH_F0_TABLE ? 1.0 / q->f0.d_ln_y : 0.0;
+    s.off_f0 = off;   off = align_up(off + (size_t)s.f0_n * sizeof(double));
     s.bytes = off;
     return s;
 }
@@ -137,6 +142,7 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P)
         gauss_legendre(q->grid.n_mu, mu, wmu);
     }
     for (int l = 0; l < q->grid.n_mu; ++l) smu[l] = std::sqrt(1.0 - mu[l] * mu[l]);
+    if (s.f0_n > 0) std::memcpy(base + s.off_f0, q->f0.ln_f, sizeof(double) * s.f0_n);
 }
 
 GridPtrs grid_ptrs(const Staged &s, const char *dev)
@@ -149,6 +155,11 @@ GridPtrs grid_ptrs(const Staged &s, const char *dev)
     g.mu = (const double *)(dev + s.off_mu);
     g.smu = (const double *)(dev + s.off_smu);
     g.wmu = (const double *)(dev + s.off_wmu);
+    g.f0.kind = s.f0_kind;
+    g.f0.n = s.f0_n;
+    g.f0.x0 = s.f0_x0;
+    g.f0.inv_dx = s.f0_inv_dx;
+    g.f0.ln_f = s.f0_n > 0 ? (const double *)(dev + s.off_f0) : nullptr;
     return g;
 }
 
@@ -212,7 +223,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
         else HIPCHK(launch_dp5_f64(P, g, o, counter, ctx->n_cu, stream));
     }
     HIPCHK(hipEventRecord(ctx->ev_t1, stream));
-    HIPCHK(launch_reduce_profile(P, g, d_ratio, q->f0.kind, d_out, stream));
+    HIPCHK(launch_reduce_profile(P, g, d_ratio, d_out, stream));
     HIPCHK(launch_reduce_stats(n, o, stats, stream));
     HIPCHK(hipEventRecord(ctx->ev_done, stream));
     ctx->pending = true;

@@ -62,7 +62,6 @@ void describe(const nh_context *ctx, const nh_request *q, const Staged &s, char 
     d.o.ratio = ratio;
     d.o.stat = stat;
     d.out = out;
-    d.f0_kind = q->f0.kind;
     d.nc = d.P.R_const > 0.0 ? NCOL - 1 : NCOL;
     d.free_all = q->halo.mass_kind == NH_MASS_ZERO;
     d.retired = 0;

@@ -31,6 +31,52 @@ double nfw_I_host(double q)
     return std::log1p(q) - q / (1.0 + q);
 }
 
+void spline_second_derivatives(const double *v, int n, double dx, double *m2)
+{
+    // Continuity of the first derivative at the interior nodes gives
+    // m[i-1] + 4 m[i] + m[i+1] = 6 (v[i-1] - 2 v[i] + v[i+1]) / dx^2, i = 1..n-2.
+    // Not-a-knot (third derivative continuous at nodes 1 and n-2) gives
+    // m0 = 2 m1 - m2 and m[n-1] = 2 m[n-2] - m[n-3]; substituted, the first and
+    // last equations become 6 m1 = r1 and 6 m[n-2] = r[n-2].  Thomas algorithm.
+    const int k = n - 2;                       // unknowns m[1..n-2]
+    std::vector<double> a(k), b(k), c(k), r(k);
+    for (int j = 0; j < k; ++j) {
+        const int i = j + 1;
+        a[j] = 1.0;
+        b[j] = 4.0;
+        c[j] = 1.0;
+        r[j] = 6.0 * (v[i - 1] - 2.0 * v[i] + v[i + 1]) / (dx * dx);
+    }
+    b[0] = 6.0;
+    c[0] = 0.0;
+    b[k - 1] = 6.0;
+    a[k - 1] = 0.0;
+    for (int j = 1; j < k; ++j) {
+        const double w = a[j] / b[j - 1];
+        b[j] -= w * c[j - 1];
+        r[j] -= w * r[j - 1];
+    }
+    m2[k] = r[k - 1] / b[k - 1];
+    for (int j = k - 2; j >= 0; --j) m2[j + 1] = (r[j] - c[j] * m2[j + 2]) / b[j];
+    m2[0] = 2.0 * m2[1] - m2[2];
+    m2[n - 1] = 2.0 * m2[n - 2] - m2[n - 3];
+}
+
+double spline_eval(const double *v, const double *m2, int n, double x0, double dx, double x)
+{
+    const double s = (x - x0) / dx;
+    int i = (int)std::floor(s);
+    i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
+    const double t = s - (double)i, w = 1.0 - t;
+    return w * v[i] + t * v[i + 1] + dx * dx / 6.0 * ((w * w * w - w) * m2[i] + (t * t * t - t) * m2[i + 1]);
+}
+
+double Physics::history(const double *v, const std::vector<double> &v2, double z) const
+{
+    const double u = -std::log1p(z);
+    return spline_eval(v, v2.data(), hist_n, hist_u_min, (0.0 - hist_u_min) / (double)(hist_n - 1), u);
+}
+
 Physics::Physics(const nh_request &q)
 {
     G = GM_SUN_SI / (KPC_IN_M * 1.0e6);
@@ -50,6 +96,27 @@ Physics::Physics(const nh_request &q)
     kb = q.halo.kappa_b;
     geometry = q.halo.geometry;
     compensated = q.halo.compensated;
+    const nh_history &hs = q.halo.history;
+    if (mass_kind == NH_MASS_TABLE || conc_kind == NH_CONC_TABLE || kappa_kind == NH_KAPPA_TABLE) {
+        hist_n = hs.n;
+        hist_u_min = -std::log1p(hs.z_max);
+        hist_M = hs.M_Msun;
+        hist_c = hs.c;
+        hist_kappa = hs.kappa;
+        const double du = (0.0 - hist_u_min) / (double)(hist_n - 1);
+        if (mass_kind == NH_MASS_TABLE) {
+            hist_M2.resize(hist_n);
+            spline_second_derivatives(hist_M, hist_n, du, hist_M2.data());
+        }
+        if (conc_kind == NH_CONC_TABLE) {
+            hist_c2.resize(hist_n);
+            spline_second_derivatives(hist_c, hist_n, du, hist_c2.data());
+        }
+        if (kappa_kind == NH_KAPPA_TABLE) {
+            hist_kappa2.resize(hist_n);
+            spline_second_derivatives(hist_kappa, hist_n, du, hist_kappa2.data());
+        }
+    }
     // M(0) = (4 pi/3) R^3 rhobar_m0, rhobar_m0 = 3 Om H0^2 / (8 pi G)  =>  R^3 = 2 G M / (Om H0^2)
     R_fixed = std::cbrt(2.0 * G * mass(0.0) / (Om * H0k * H0k));
 }
@@ -64,6 +131,8 @@ double Physics::mass(double z) const
     }
     case NH_MASS_EXPONENTIAL:
         return M0 * std::exp(-beta * z);
+    case NH_MASS_TABLE:
+        return history(hist_M, hist_M2, z);
     default:
         return 0.0;
     }
@@ -71,6 +140,7 @@ double Physics::mass(double z) const
 
 double Physics::conc(double z) const
 {
+    if (conc_kind == NH_CONC_TABLE) return history(hist_c, hist_c2, z);
     return conc_kind == NH_CONC_POWER ? c0 * std::pow(1.0 + z, -gamma) : c0;
 }
 
@@ -80,6 +150,7 @@ double Physics::kappa(double z) const
     case NH_KAPPA_LOG: return 1.0 + ka * std::log1p(z);
     case NH_KAPPA_PAPER: return 1.0 + ka * std::pow(z / (1.0 + z), kb);
     case NH_KAPPA_CONSTANT: return ka;
+    case NH_KAPPA_TABLE: return history(hist_kappa, hist_kappa2, z);
     default: return 1.0;
     }
 }
@@ -138,7 +209,9 @@ double Physics::r_exit(double u_end) const
         double R = std::cbrt(2.0 * G * M / (Om * H0k * H0k));
         Rmax = R > Rmax ? R : Rmax;
     }
-    return Rmax;
+    // a sampled M(z) may peak between the scan points: keep a margin so the
+    // exit stays exact
+    return mass_kind == NH_MASS_TABLE ? Rmax * 1.001 : Rmax;
 }
 
 // 3073 nodes over u in [-ln 5, 0]: cubic interpolation error below ~2e-13
@@ -231,22 +304,72 @@ int validate(const nh_request *q, char *msg, size_t msg_len)
     if (!std::isfinite(c.Omega_L) || c.Omega_L < 0) NH_BAD("Omega_L must be finite and >= 0");
     if (std::fabs(c.Omega_m + c.Omega_L - 1.0) > 1e-12) NH_BAD("background must be flat: |Om + OL - 1| <= 1e-12");
     const nh_halo &h = q->halo;
-    if (h.mass_kind < NH_MASS_ZERO || h.mass_kind > NH_MASS_EXPONENTIAL) NH_BAD("unknown mass_kind %d", h.mass_kind);
-    if (h.mass_kind != NH_MASS_ZERO && (!std::isfinite(h.M0_Msun) || h.M0_Msun <= 0)) NH_BAD("M0 must be finite and > 0");
+    if (h.mass_kind < NH_MASS_ZERO || h.mass_kind > NH_MASS_TABLE) NH_BAD("unknown mass_kind %d", h.mass_kind);
+    if (h.mass_kind != NH_MASS_ZERO && h.mass_kind != NH_MASS_TABLE && (!std::isfinite(h.M0_Msun) || h.M0_Msun <= 0))
+        NH_BAD("M0 must be finite and > 0");
     if (h.mass_kind == NH_MASS_PAPER) {
         if (!std::isfinite(h.z_form) || h.z_form <= 0) NH_BAD("z_form must be finite and > 0");
         if (!std::isfinite(h.mass_alpha) || h.mass_alpha < 0) NH_BAD("mass_alpha must be finite and >= 0");
     }
     if (h.mass_kind == NH_MASS_EXPONENTIAL && !std::isfinite(h.mass_beta)) NH_BAD("mass_beta must be finite");
-    if (h.conc_kind < NH_CONC_CONSTANT || h.conc_kind > NH_CONC_POWER) NH_BAD("unknown conc_kind %d", h.conc_kind);
-    if (!std::isfinite(h.c0) || h.c0 <= 0) NH_BAD("c0 must be finite and > 0");
+    if (h.conc_kind < NH_CONC_CONSTANT || h.conc_kind > NH_CONC_TABLE) NH_BAD("unknown conc_kind %d", h.conc_kind);
+    if (h.conc_kind != NH_CONC_TABLE && (!std::isfinite(h.c0) || h.c0 <= 0)) NH_BAD("c0 must be finite and > 0");
     if (!std::isfinite(h.conc_gamma)) NH_BAD("conc_gamma must be finite");
-    if (h.kappa_kind < NH_KAPPA_NONE || h.kappa_kind > NH_KAPPA_CONSTANT) NH_BAD("unknown kappa_kind %d", h.kappa_kind);
+    if (h.kappa_kind < NH_KAPPA_NONE || h.kappa_kind > NH_KAPPA_TABLE) NH_BAD("unknown kappa_kind %d", h.kappa_kind);
+    const bool tabulated = h.mass_kind == NH_MASS_TABLE || h.conc_kind == NH_CONC_TABLE || h.kappa_kind == NH_KAPPA_TABLE;
+    if (tabulated) {
+        const nh_history &hs = h.history;
+        if (hs.n < 4 || hs.n > (1 << 24)) NH_BAD("history needs n in [4, 2^24] samples");
+        if (!std::isfinite(hs.z_max) || hs.z_max <= 0) NH_BAD("history z_max must be finite and > 0");
+        if (!(hs.z_max >= q->integ.z_end)) NH_BAD("history must cover z_end: z_max >= z_end");
+        const double *arrs[3] = {h.mass_kind == NH_MASS_TABLE ? hs.M_Msun : nullptr,
+                                 h.conc_kind == NH_CONC_TABLE ? hs.c : nullptr,
+                                 h.kappa_kind == NH_KAPPA_TABLE ? hs.kappa : nullptr};
+        const bool need[3] = {h.mass_kind == NH_MASS_TABLE, h.conc_kind == NH_CONC_TABLE,
+                              h.kappa_kind == NH_KAPPA_TABLE};
+        const char *names[3] = {"M_Msun", "c", "kappa"};
+        for (int a = 0; a < 3; ++a) {
+            if (!need[a]) continue;
+            if (!arrs[a]) NH_BAD("history.%s is required", names[a]);
+            for (int i = 0; i < hs.n; ++i)
+                if (!std::isfinite(arrs[a][i])) NH_BAD("history.%s[%d] must be finite", names[a], i);
+        }
+        if (need[0]) {
+            for (int i = 0; i < hs.n; ++i) {
+                if (hs.M_Msun[i] < 0) NH_BAD("history.M_Msun[%d] must be >= 0", i);
+                if (h.geometry == NH_GEOM_DELTA200 && !(hs.M_Msun[i] > 0))
+                    NH_BAD("delta200 geometry needs M > 0 at every sample (index %d)", i);
+            }
+            if (!(hs.M_Msun[hs.n - 1] > 0)) NH_BAD("history.M_Msun at z = 0 (the last sample) must be > 0");
+        }
+        if (need[1]) {
+            // the spline must stay positive: check the samples and 8 points per interval
+            const double dx = 1.0 / (double)(hs.n - 1);
+            for (int i = 0; i < hs.n; ++i)
+                if (!(hs.c[i] > 0)) NH_BAD("history.c[%d] must be > 0", i);
+            std::vector<double> m2(hs.n);
+            spline_second_derivatives(hs.c, hs.n, dx, m2.data());
+            for (int i = 0; i + 1 < hs.n; ++i)
+                for (int k = 1; k < 8; ++k)
+                    if (!(spline_eval(hs.c, m2.data(), hs.n, 0.0, dx, (i + k / 8.0) * dx) > 0))
+                        NH_BAD("the interpolated concentration is not positive near sample %d", i);
+        }
+    }
     if (!std::isfinite(h.kappa_a) || !std::isfinite(h.kappa_b)) NH_BAD("kappa parameters must be finite");
     if (h.geometry != NH_GEOM_PAPER && h.geometry != NH_GEOM_DELTA200) NH_BAD("unknown geometry %d", h.geometry);
     if (h.compensated != 0 && h.compensated != 1) NH_BAD("compensated must be 0 or 1");
     if (!std::isfinite(q->m_eV) || q->m_eV <= 0) NH_BAD("m_eV must be finite and > 0");
-    if (q->f0.kind != NH_F0_FERMI_DIRAC && q->f0.kind != NH_F0_FREEZE_IN) NH_BAD("unknown f0 kind %d", q->f0.kind);
+    if (q->f0.kind != NH_F0_FERMI_DIRAC && q->f0.kind != NH_F0_FREEZE_IN && q->f0.kind != NH_F0_TABLE)
+        NH_BAD("unknown f0 kind %d", q->f0.kind);
+    if (q->f0.kind == NH_F0_TABLE) {
+        const nh_f0 &f = q->f0;
+        if (f.n < 4 || f.n > (1 << 20)) NH_BAD("f0 table needs n in [4, 2^20] samples");
+        if (!std::isfinite(f.ln_y0) || !std::isfinite(f.d_ln_y) || !(f.d_ln_y > 0))
+            NH_BAD("f0 table needs finite ln_y0 and d_ln_y > 0");
+        if (!f.ln_f) NH_BAD("f0 table values are required");
+        for (int i = 0; i < f.n; ++i)
+            if (!std::isfinite(f.ln_f[i])) NH_BAD("f0 ln_f[%d] must be finite", i);
+    }
     if (!std::isfinite(q->f0.T_K) || q->f0.T_K <= 0) NH_BAD("T_K must be finite and > 0");
     const nh_grid &g = q->grid;
     if (g.n_r < 1 || !g.r_kpc) NH_BAD("need n_r >= 1 radii");

@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void k_reduce_profile_batch(const BatchReq *__
         else hi = mid - 1;
     }
     const BatchReq &q = reqs[list[lo]];
-    reduce_radius(q.P, q.g, q.o.ratio, q.f0_kind, b - rstart[lo], q.out);
+    reduce_radius(q.P, q.g, q.o.ratio, b - rstart[lo], q.out);
 }
 
 // blockIdx.y: listed request; its statistics go to stats[8 * blockIdx.y ...].

@@ -168,9 +168,9 @@ __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridP
 
 __global__ __launch_bounds__(256) void k_reduce_profile(TrajParams P, GridPtrs g,
                                                         const double *__restrict__ ratio,
-                                                        int f0_kind, double *__restrict__ out)
+                                                        double *__restrict__ out)
 {
-    reduce_radius(P, g, ratio, f0_kind, blockIdx.x, out);
+    reduce_radius(P, g, ratio, blockIdx.x, out);
 }
 
 // Integer statistics (exact under any summation order).
@@ -234,9 +234,9 @@ hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut 
 }
 
 hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,
-                                 int f0_kind, double *out, hipStream_t s)
+                                 double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_profile, dim3(P.n_r), dim3(256), 0, s, P, g, ratio, f0_kind, out);
+    hipLaunchKernelGGL(k_reduce_profile, dim3(P.n_r), dim3(256), 0, s, P, g, ratio, out);
     return hipGetLastError();
 }
 

@@ -18,7 +18,9 @@ struct DevBuf {
 // Byte offsets of one request's inputs inside the staged blob.
 struct Staged {
     int n_tab;
-    size_t off_tab, off_r, off_y, off_wy, off_mu, off_smu, off_wmu;
+    size_t off_tab, off_r, off_y, off_wy, off_mu, off_smu, off_wmu, off_f0;
+    int f0_kind, f0_n;
+    double f0_x0, f0_inv_dx;
     size_t bytes;
 };
 

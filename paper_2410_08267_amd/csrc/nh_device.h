@@ -132,26 +132,39 @@ __device__ __forceinline__ double norm2(double a, double b) { return fma(a, a, b
 // coefficients and right-hand side
 // ---------------------------------------------------------------------------
 
-// 4-point Lagrange (cubic) stencil at u on the uniform table with nodes
-// u_i = u0 + i du, i = 0..n-1: first row of the stencil and its four weights;
-// the stencil is shifted inward at both ends.
+// 4-point Lagrange (cubic) interpolation on a uniform grid: interval i
+// (nodes i..i+1) uses nodes i-1..i+2, the stencil shifted inward in the first
+// and last interval.
 struct Stencil4 {
     int row;
     double wa, wb, wc, wd;
 };
-__device__ __forceinline__ Stencil4 stencil_at(int n_tab, double u0, double inv_du, double u)
+
+// Weights of nodes i-1..i+2 at fractional position p = s - i.
+__device__ __forceinline__ void stencil_weights(double p, Stencil4 &w)
 {
-    const double s = (u - u0) * inv_du;
-    int i = (int)s;
-    i = i < 1 ? 1 : (i > n_tab - 3 ? n_tab - 3 : i);
-    const double p = s - (double)i;
     const double pm = p + 1.0, p1 = p - 1.0, p2 = p - 2.0;
-    Stencil4 w;
-    w.row = i - 1;
     w.wa = -(p * p1 * p2) * (1.0 / 6.0);
     w.wb = (pm * p1 * p2) * 0.5;
     w.wc = -(pm * p * p2) * 0.5;
     w.wd = (pm * p * p1) * (1.0 / 6.0);
+}
+
+// Interval of grid coordinate s on n nodes, clamped to [1, n-3].
+__device__ __forceinline__ int stencil_interval(int n, double s)
+{
+    const int i = (int)s;
+    return i < 1 ? 1 : (i > n - 3 ? n - 3 : i);
+}
+
+// Stencil of the coefficient table (nodes u_i = u0 + i du) at u.
+__device__ __forceinline__ Stencil4 stencil_at(int n_tab, double u0, double inv_du, double u)
+{
+    const double s = (u - u0) * inv_du;
+    const int i = stencil_interval(n_tab, s);
+    Stencil4 w;
+    w.row = i - 1;
+    stencil_weights(s - (double)i, w);
     return w;
 }
 
@@ -193,9 +206,28 @@ __device__ __forceinline__ void rhs(const double c[NCOL], double R, double x, do
 }
 
 // Relic distribution before the halo formed, y = P / (k_B T).
-__device__ __forceinline__ double f0_eval(int kind, double y)
+__device__ __forceinline__ double f0_eval(const F0Desc &f, double y)
 {
-    if (kind == NH_F0_FREEZE_IN) return exp(-y) / sqrt(y);
+    if (f.kind == NH_F0_FREEZE_IN) return exp(-y) / sqrt(y);
+    if (f.kind == NH_F0_TABLE) {
+        // ln f0 from its samples in ln y: the cubic through the four samples
+        // around ln y inside the range, the end interval's line outside it
+        const double s = (log(y) - f.x0) * f.inv_dx;
+        const double *v = f.ln_f;
+        const int n = f.n;
+        double lf;
+        if (s < 0.0) {
+            lf = v[0] + (v[1] - v[0]) * s;
+        } else if (s > (double)(n - 1)) {
+            lf = v[n - 1] + (v[n - 1] - v[n - 2]) * (s - (double)(n - 1));
+        } else {
+            const int i = stencil_interval(n, s);
+            Stencil4 w;
+            stencil_weights(s - (double)i, w);
+            lf = w.wa * v[i - 1] + w.wb * v[i] + w.wc * v[i + 1] + w.wd * v[i + 2];
+        }
+        return exp(lf);
+    }
     return 1.0 / (1.0 + exp(y));
 }
 

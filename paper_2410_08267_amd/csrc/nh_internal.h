@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "nuhalo.h"
 
@@ -60,6 +61,14 @@ struct TrajParams {
     double h_fp64;
 };
 
+// The relic's initial distribution as the reduction evaluates it.
+struct F0Desc {
+    int kind;               // NH_F0_*
+    int n;                  // NH_F0_TABLE: samples of ln f0 at ln y = x0 + i dx
+    double x0, inv_dx;
+    const double *ln_f;     // device, n
+};
+
 // Device pointers of one request's staged inputs (one contiguous blob).
 struct GridPtrs {
     const double *tab;      // n_tab * NCOL (DP5) or (2 n_steps + 1) * NCOL (RK4)
@@ -69,6 +78,7 @@ struct GridPtrs {
     const double *mu;       // n_mu
     const double *smu;      // n_mu: sqrt(1 - mu^2)
     const double *wmu;      // n_mu
+    F0Desc f0;
 };
 
 // Per-trajectory counters, written with one 16-byte store.
@@ -100,7 +110,6 @@ struct BatchReq {
     GridPtrs g;               // staged inputs; g.tab rows of NCOL doubles
     TrajOut o;                // per-trajectory outputs of this request
     double *out;              // n_r profile
-    int f0_kind;
     int nc;                   // table columns used: NCOL, or NCOL - 1 when R is constant
     int free_all;             // no halo: every trajectory streams freely (ratio 1)
     int retired;              // cancelled: not claimed, saved lanes drop it
@@ -146,8 +155,15 @@ struct Physics {
     double ka, kb;
     int geometry, compensated;
     double R_fixed;         // NH_GEOM_PAPER: comoving Lagrangian radius from M(z=0)
+    // sampled histories (the *_TABLE kinds): samples at u_i = hist_u_min + i du and
+    // the second derivatives of their not-a-knot cubic splines
+    int hist_n = 0;
+    double hist_u_min = 0.0;
+    const double *hist_M = nullptr, *hist_c = nullptr, *hist_kappa = nullptr;
+    std::vector<double> hist_M2, hist_c2, hist_kappa2;
 
     explicit Physics(const nh_request &q);
+    double history(const double *v, const std::vector<double> &v2, double z) const;
     double mass(double z) const;
     double conc(double z) const;
     double kappa(double z) const;
@@ -163,6 +179,11 @@ constexpr double KB_EV_PER_K = 8.617333262e-5;        // eV / K
 constexpr double C_KM_S = 299792.458;                 // km / s
 
 double nfw_I_host(double q);
+// Not-a-knot cubic spline through samples v[0..n-1] on a uniform grid (n >= 4):
+// spline_second_derivatives fills m2 with its second derivatives at the nodes,
+// spline_eval evaluates it at x (the end pieces continue outside the grid).
+void spline_second_derivatives(const double *v, int n, double dx, double *m2);
+double spline_eval(const double *v, const double *m2, int n, double x0, double dx, double x);
 void gauss_legendre(int n, double *x, double *w);
 void y_weights(int n, const double *y, double *w);
 int validate(const nh_request *q, char *msg, size_t msg_len);

@@ -15,7 +15,7 @@ hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut 
 hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                            unsigned long long *counter, int n_cu, hipStream_t s);
 hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,
-                                 int f0_kind, double *out, hipStream_t s);
+                                 double *out, hipStream_t s);
 hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long *stats,
                                hipStream_t s);
 

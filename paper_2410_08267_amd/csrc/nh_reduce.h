@@ -11,7 +11,7 @@ namespace nh {
 // W_jl = w_y,j w_mu,l.  Fixed summation order: thread-strided partial sums,
 // then a tree in LDS.
 __device__ __forceinline__ void reduce_radius(const TrajParams &P, const GridPtrs &g,
-                                              const double *__restrict__ ratio, int f0_kind, int k,
+                                              const double *__restrict__ ratio, int k,
                                               double *__restrict__ out)
 {
     const int ne = P.n_y * P.n_mu;
@@ -22,8 +22,8 @@ __device__ __forceinline__ void reduce_radius(const TrajParams &P, const GridPtr
         const int l = e - j * P.n_mu;
         const double W = g.wy[j] * g.wmu[l];
         const double yj = g.y[j];
-        num += W * f0_eval(f0_kind, yj * rk[e]);
-        den += W * f0_eval(f0_kind, yj);
+        num += W * f0_eval(g.f0, yj * rk[e]);
+        den += W * f0_eval(g.f0, yj);
     }
     __shared__ double sn[256], sd[256];
     sn[threadIdx.x] = num;

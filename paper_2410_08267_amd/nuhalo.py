@@ -25,11 +25,11 @@ NH_ENONFINITE, NH_EBUSY, NH_ENOTREADY, NH_ENOTFOUND, NH_ECANCELED = -5, -6, -7, 
 OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4, "block_threads": 5,
            "batch_slots": 6, "slice_us": 7}
 
-_MASS = {"zero": 0, "paper": 1, "exponential": 2}
-_CONC = {"constant": 0, "power": 1}
-_KAPPA = {"none": 0, "log": 1, "paper": 2, "constant": 3}
+_MASS = {"zero": 0, "paper": 1, "exponential": 2, "table": 3}
+_CONC = {"constant": 0, "power": 1, "table": 2}
+_KAPPA = {"none": 0, "log": 1, "paper": 2, "constant": 3, "table": 4}
 _GEOM = {"paper": 0, "delta200": 1}
-_F0 = {"fermi_dirac": 0, "freeze_in": 1}
+_F0 = {"fermi_dirac": 0, "freeze_in": 1, "table": 2}
 _METHOD = {"rk4": 0, "dp5": 1}
 _PREC = {"fp64": 0, "fp32c": 1}
 
@@ -47,6 +47,11 @@ class nh_cosmology(ctypes.Structure):
                 ("Omega_L", ctypes.c_double)]
 
 
+class nh_history(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("z_max", ctypes.c_double), ("M_Msun", _dp), ("c", _dp),
+                ("kappa", _dp)]
+
+
 class nh_halo(ctypes.Structure):
     _fields_ = [("mass_kind", ctypes.c_int), ("M0_Msun", ctypes.c_double),
                 ("mass_alpha", ctypes.c_double), ("z_form", ctypes.c_double),
@@ -54,11 +59,12 @@ class nh_halo(ctypes.Structure):
                 ("c0", ctypes.c_double), ("conc_gamma", ctypes.c_double),
                 ("kappa_kind", ctypes.c_int), ("kappa_a", ctypes.c_double),
                 ("kappa_b", ctypes.c_double), ("geometry", ctypes.c_int),
-                ("compensated", ctypes.c_int)]
+                ("compensated", ctypes.c_int), ("history", nh_history)]
 
 
 class nh_f0(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("T_K", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int), ("T_K", ctypes.c_double), ("n", ctypes.c_int),
+                ("ln_y0", ctypes.c_double), ("d_ln_y", ctypes.c_double), ("ln_f", _dp)]
 
 
 class nh_grid(ctypes.Structure):
@@ -150,6 +156,9 @@ class _Marshalled:
         self.y = _arr(req.y)
         self.mu = None if req.mu is None else _arr(req.mu)
         self.w_mu = None if req.w_mu is None else _arr(req.w_mu)
+        self.hist = {k: (None if getattr(req, "hist_" + k) is None else _arr(getattr(req, "hist_" + k)))
+                     for k in ("M", "c", "kappa")}
+        self.ln_f = None if req.f0_ln_f is None else _arr(req.f0_ln_f)
         q = nh_request()
         q.cosmo.H0_km_s_Mpc = req.H0
         q.cosmo.Omega_m = req.Omega_m
@@ -168,9 +177,22 @@ class _Marshalled:
         h.kappa_b = req.kappa_b
         h.geometry = _GEOM[req.geometry]
         h.compensated = int(bool(req.compensated))
+        sizes = {a.size for a in self.hist.values() if a is not None}
+        if len(sizes) > 1:
+            raise ValueError("hist_M, hist_c and hist_kappa must have the same length")
+        h.history.n = sizes.pop() if sizes else 0
+        h.history.z_max = req.hist_z_max
+        h.history.M_Msun = None if self.hist["M"] is None else self.hist["M"].ctypes.data_as(_dp)
+        h.history.c = None if self.hist["c"] is None else self.hist["c"].ctypes.data_as(_dp)
+        h.history.kappa = None if self.hist["kappa"] is None else self.hist["kappa"].ctypes.data_as(_dp)
         q.m_eV = req.m_eV
         q.f0.kind = _F0[req.f0_kind]
         q.f0.T_K = req.T_K
+        if self.ln_f is not None:
+            q.f0.n = self.ln_f.size
+            q.f0.ln_y0 = req.f0_ln_y0
+            q.f0.d_ln_y = req.f0_d_ln_y
+            q.f0.ln_f = self.ln_f.ctypes.data_as(_dp)
         g = q.grid
         g.n_r = self.r.size
         g.r_kpc = self.r.ctypes.data_as(_dp)

@@ -18,11 +18,11 @@ import numpy as np
 # 200^(1/3) - 1: the collapse redshift of a halo virialised at z0 = 0 (Sec. II.B)
 Z_FORM_PAPER = 200.0 ** (1.0 / 3.0) - 1.0
 
-MASS_KINDS = ("zero", "paper", "exponential")
-CONC_KINDS = ("constant", "power")
-KAPPA_KINDS = ("none", "log", "paper", "constant")
+MASS_KINDS = ("zero", "paper", "exponential", "table")
+CONC_KINDS = ("constant", "power", "table")
+KAPPA_KINDS = ("none", "log", "paper", "constant", "table")
 GEOMETRIES = ("paper", "delta200")
-F0_KINDS = ("fermi_dirac", "freeze_in")
+F0_KINDS = ("fermi_dirac", "freeze_in", "table")
 METHODS = ("rk4", "dp5")
 PRECISIONS = ("fp64", "fp32c")
 
@@ -49,10 +49,20 @@ class Request:
     kappa_b: float = 1.0
     geometry: str = "paper"          # paper (fixed physical r200) | delta200 (200 rhobar_m(z))
     compensated: bool = True
+    # sampled histories for the "table" kinds: sample i at u_i = u_min + i (0 - u_min)/(n-1),
+    # u = ln a, u_min = -ln(1 + hist_z_max); the last sample is z = 0
+    hist_z_max: float = 4.0
+    hist_M: Optional[np.ndarray] = None      # Msun
+    hist_c: Optional[np.ndarray] = None
+    hist_kappa: Optional[np.ndarray] = None
     # relic
     m_eV: float = 0.1
-    f0_kind: str = "fermi_dirac"     # fermi_dirac | freeze_in
+    f0_kind: str = "fermi_dirac"     # fermi_dirac | freeze_in | table
     T_K: float = 1.95
+    # f0 "table": ln f0 at ln y = f0_ln_y0 + i f0_d_ln_y
+    f0_ln_y0: float = 0.0
+    f0_d_ln_y: float = 1.0
+    f0_ln_f: Optional[np.ndarray] = None
     # grids
     r_kpc: np.ndarray = field(default_factory=lambda: np.geomspace(10.0, 1000.0, 10))
     y: np.ndarray = field(default_factory=lambda: np.geomspace(0.01, 100.0, 50))

@@ -42,11 +42,14 @@ def sensitivity(oracle_mod, oracle_fma):
     profile under perturbations no larger than what separates two correct FP64
     integrations of the request: re-rounding of the same arithmetic (the
     FMA-contracted build), and relative changes of the force of 1e-12 (the
-    device interpolates its coefficient tables to ~1e-13): the halo mass scaled
-    by 1 + 1e-12, and G scaled by 1 + 1e-12 z/(1+z) when the request leaves G
-    unmodulated.  Adaptive step control turns such differences into flipped
-    accept/reject decisions, i.e. profile differences of order rtol, for some
-    halos; parity bounds scale with this measure where it exceeds them."""
+    device interpolates its coefficient tables to ~1e-13-1e-12): the halo mass
+    scaled by 1 + 1e-12; when the request leaves G unmodulated, G scaled by
+    1 + 1e-12 z/(1+z) and by 1 + 1e-12 sin(40 ln a); and the first trial
+    step scaled by 1 + 1e-12, which shifts every later step.  Adaptive step control
+    turns such differences into flipped accept/reject decisions, i.e. profile
+    differences of order rtol, for some halos, and how much depends on the
+    shape of the perturbation; parity bounds scale with this measure where it
+    exceeds them."""
     O = oracle_mod
 
     def dev(profile, ref):
@@ -61,9 +64,19 @@ def sensitivity(oracle_mod, oracle_fma):
             worst = dev(O.solve(req)["n_over_nbar"], ref_profile)
         finally:
             O._lib = saved
-        worst = max(worst, dev(O.solve(req.with_(M0=req.M0 * (1.0 + 1e-12)))["n_over_nbar"], ref_profile))
+        if req.mass_kind == "table":
+            heavier = req.with_(hist_M=np.asarray(req.hist_M) * (1.0 + 1e-12))
+        else:
+            heavier = req.with_(M0=req.M0 * (1.0 + 1e-12))
+        probes = [heavier, req.with_(h0=req.h0 * (1.0 + 1e-12))]
         if req.kappa_kind == "none":
-            kp = req.with_(kappa_kind="paper", kappa_a=1e-12, kappa_b=1.0)
-            worst = max(worst, dev(O.solve(kp)["n_over_nbar"], ref_profile))
+            probes.append(req.with_(kappa_kind="paper", kappa_a=1e-12, kappa_b=1.0))
+            # an oscillating G(z), sampled on the request's own history grid if it has one
+            n = len(req.hist_M) if req.hist_M is not None else (len(req.hist_c) if req.hist_c is not None else 257)
+            z_max = req.hist_z_max if (req.hist_M is not None or req.hist_c is not None) else req.z_end
+            u = -np.log1p(z_max) + np.arange(n) * np.log1p(z_max) / (n - 1)
+            probes.append(req.with_(kappa_kind="table", hist_z_max=z_max, hist_kappa=1.0 + 1e-12 * np.sin(40.0 * u)))
+        for p in probes:
+            worst = max(worst, dev(O.solve(p)["n_over_nbar"], ref_profile))
         return worst
     return f

@@ -62,6 +62,16 @@ def test_strerror_and_version(N):
     dict(z_end=-1.0),
     dict(z_end=5.0),                              # beyond z_i in the paper geometry
     dict(r_kpc=np.array([10.0, np.nan])),
+    dict(mass_kind="table", hist_M=np.full(3, 1e12)),                       # fewer than 4 samples
+    dict(mass_kind="table", hist_M=np.full(8, 1e12), hist_z_max=3.0),       # does not reach z_end
+    dict(mass_kind="table", hist_M=np.r_[np.full(7, 1e12), 0.0]),           # M(0) = 0
+    dict(mass_kind="table", hist_M=np.r_[-1.0, np.full(7, 1e12)]),          # negative mass
+    dict(conc_kind="table", hist_c=np.r_[1.0, 1.0, -2.0, 1.0, 1.0]),       # non-positive c
+    dict(kappa_kind="table", hist_kappa=np.r_[1.0, np.inf, 1.0, 1.0]),
+    dict(mass_kind="table"),                                                # samples missing
+    dict(f0_kind="table", f0_ln_f=np.zeros(3)),                             # fewer than 4 samples
+    dict(f0_kind="table", f0_ln_f=np.zeros(8), f0_d_ln_y=0.0),
+    dict(f0_kind="table", f0_ln_f=np.r_[0.0, np.nan, 0.0, 0.0]),
 ])
 def test_validation_rejects(N, bad):
     req = W.plain_small().with_(**bad)
@@ -76,7 +86,10 @@ def test_validation_accepts_variants(N):
                dict(mass_kind="zero"), dict(geometry="delta200", z_end=9.0),
                dict(kappa_kind="paper", kappa_a=0.2, kappa_b=1.5), dict(compensated=False),
                dict(f0_kind="freeze_in"), dict(method="dp5", precision="fp32c"),
-               dict(mu=np.array([-0.5, 0.5]), w_mu=np.array([1.0, 1.0]))]:
+               dict(mu=np.array([-0.5, 0.5]), w_mu=np.array([1.0, 1.0])),
+               dict(mass_kind="table", conc_kind="table", kappa_kind="table", hist_z_max=4.0,
+                    hist_M=np.full(6, 1e12), hist_c=np.full(6, 9.0), hist_kappa=np.ones(6)),
+               dict(f0_kind="table", f0_ln_y0=-5.0, f0_d_ln_y=0.5, f0_ln_f=-np.arange(20.0))]:
         assert N.footprint_bytes(base.with_(**kw)) > 0
 
 
@@ -103,7 +116,19 @@ REQS = {
     "delta200": lambda: W.plain_small().with_(geometry="delta200", M0=3e13),
     "kappa_log": lambda: W.plain_small().with_(kappa_kind="log", kappa_a=0.05, M0=5e14, c0=4.0),
     "uncompensated": lambda: W.plain_small().with_(compensated=False, M0=2e12),
+    "sampled_histories": lambda: _sampled(W.plain_small().with_(M0=4e13), "paper"),
+    "sampled_delta200": lambda: _sampled(W.plain_small().with_(M0=4e13), "delta200"),
 }
+
+
+def _sampled(req, geometry, n=37):
+    """The request's halo given as samples of a wiggly growth history, c(z) and G(z)."""
+    u = -math.log1p(4.0) + np.arange(n) * math.log1p(4.0) / (n - 1)
+    z = np.expm1(-u)
+    M = req.M0 * np.exp(-0.8 * z) * (1.0 + 0.1 * np.sin(3.0 * u))
+    return req.with_(mass_kind="table", conc_kind="table", kappa_kind="table", geometry=geometry,
+                     hist_z_max=4.0, hist_M=M, hist_c=9.0 / (1.0 + z) ** 0.7,
+                     hist_kappa=1.0 + 0.1 * (z / (1.0 + z)) ** 1.5)
 
 
 @pytest.mark.parametrize("name", sorted(REQS))

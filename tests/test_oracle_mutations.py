@@ -35,6 +35,13 @@ MUTANTS = {
     "dp_error_weight": ("-92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};", "-92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 30.0};"),
     "mass_xi": ("double xi = (m->z_form - z) / m->z_form;", "double xi = (m->z_form - z) / (m->z_form + 1.0);"),
     "conc_power": ("return m->c0 * pow(1.0 + z, -m->conc_gamma);", "return m->c0 * pow(1.0 + z, m->conc_gamma);"),
+    "sampled_horner": ("return ((c[0] * t + c[1]) * t + c[2]) * t + c[3];",
+                       "return ((c[0] * t + c[2]) * t + c[1]) * t + c[3];"),
+    "sampled_piece_origin": ("double t = u - (m->hist_u_min + (double)i * du);",
+                             "double t = u - (m->hist_u_min + (double)(i + 1) * du);"),
+    "sampled_time_sign": ("double u = -log1p(z);\n    double du", "double u = log1p(z);\n    double du"),
+    "sampled_spacing": ("double du = (0.0 - m->hist_u_min) / (double)(m->hist_n - 1);",
+                        "double du = (0.0 - m->hist_u_min) / (double)m->hist_n;"),
 }
 
 

@@ -486,3 +486,118 @@ def test_qualitative_profile_shape(oracle_mod):
     heavier_m = O.solve(base.with_(m_eV=0.3))["n_over_nbar"]
     heavier_M = O.solve(base.with_(M0=1e14))["n_over_nbar"]
     assert heavier_m[0] > p[0] and heavier_M[0] > p[0]
+
+
+# ---------------------------------------------------------------------------
+# Sampled histories (any growth model, Sec. IV.A; any G(z), Sec. IV.B): the
+# not-a-knot cubic spline through the samples, which is exact for a cubic and
+# converges to a smooth history as h^4.  A sampled f0 (any pre-halo
+# distribution, Sec. IV.B): the cubic through four consecutive samples of
+# ln f in ln y, and straight lines beyond the ends.
+# ---------------------------------------------------------------------------
+
+def _u_grid(z_max, n):
+    u_min = -math.log1p(z_max)
+    return u_min + np.arange(n) * (0.0 - u_min) / (n - 1)
+
+
+def test_sampled_history_is_exact_for_cubics(oracle_mod):
+    """Samples of cubic polynomials in u = ln a come back exactly at any z,
+    in the first, interior and last intervals alike."""
+    O = oracle_mod
+    z_max, n = 4.5, 9
+    u = _u_grid(z_max, n)
+    pM = lambda x: 1e12 * (2.0 + 0.3 * x - 0.2 * x ** 2 + 0.05 * x ** 3)
+    pc = lambda x: 8.0 + 1.5 * x + 0.4 * x ** 2 - 0.1 * x ** 3
+    pk = lambda x: 1.0 - 0.02 * x + 0.01 * x ** 3
+    req = W.plain_small().with_(mass_kind="table", conc_kind="table", kappa_kind="table",
+                                hist_z_max=z_max, hist_M=pM(u), hist_c=pc(u), hist_kappa=pk(u))
+    z = np.concatenate([np.linspace(0.0, z_max, 41), [z_max, 1e-9, 0.0]])
+    M, c, k = O.histories(req, z)
+    x = -np.log1p(z)
+    np.testing.assert_allclose(M, pM(x), rtol=1e-13)
+    np.testing.assert_allclose(c, pc(x), rtol=1e-13)
+    np.testing.assert_allclose(k, pk(x), rtol=1e-13, atol=1e-15)
+
+
+def test_sampled_history_is_the_spline_through_the_samples(oracle_mod):
+    """At the samples the history returns them; between samples it is twice
+    continuously differentiable (finite differences across every node)."""
+    O = oracle_mod
+    z_max, n = 4.0, 13
+    u = _u_grid(z_max, n)
+    rng = np.random.default_rng(5)
+    vals = 1e12 * (1.0 + 0.5 * rng.uniform(size=n))
+    req = W.plain_small().with_(mass_kind="table", hist_z_max=z_max, hist_M=vals)
+    M, _, _ = O.histories(req, np.expm1(-u))
+    np.testing.assert_allclose(M, vals, rtol=1e-13)
+    # one-sided differences on either side of each interior sample: a kink in the
+    # first or second derivative would show as a jump of the size of that derivative
+    h = 1e-6
+    for ui in u[1:-1]:
+        Mz = lambda x: O.histories(req, np.expm1(-np.asarray(x)))[0]
+        l, r = Mz([ui - 2 * h, ui - h, ui]), Mz([ui, ui + h, ui + 2 * h])
+        d1l, d1r = (l[2] - l[1]) / h, (r[1] - r[0]) / h
+        d2l, d2r = (l[2] - 2 * l[1] + l[0]) / h ** 2, (r[2] - 2 * r[1] + r[0]) / h ** 2
+        assert abs(d1l - d1r) < 1e-3 * max(abs(d1l), abs(d1r))
+        assert abs(d2l - d2r) < 1e-3 * max(abs(d2l), abs(d2r))
+
+
+def test_sampled_history_converges_to_the_closed_forms(oracle_mod):
+    """M0 e^{-0.8 z}, c0/(1+z) and 1 + 0.05 ln(1+z) sampled at 801 points
+    reproduce the closed-form halo: deltaM and the right-hand side agree to
+    the cubic's O(h^4) error, and halving the spacing cuts the error ~16x."""
+    O = oracle_mod
+    base = W.plain_small().with_(kappa_kind="log", kappa_a=0.05)
+    rng = np.random.default_rng(3)
+    r = np.exp(rng.uniform(np.log(1.0), np.log(2000.0), 400))
+    z = rng.uniform(0.0, 4.0, 400)
+    ref = O.deltaM(base, r, z)
+    errs = []
+    for n in (201, 401, 801):
+        u = _u_grid(4.0, n)
+        zz = np.expm1(-u)
+        tab = base.with_(mass_kind="table", conc_kind="table", kappa_kind="table", hist_z_max=4.0,
+                         hist_M=base.M0 * np.exp(-base.mass_beta * zz), hist_c=base.c0 / (1.0 + zz),
+                         hist_kappa=1.0 + 0.05 * np.log1p(zz))
+        got = O.deltaM(tab, r, z)
+        ok = np.abs(ref) > 1e-6 * np.abs(ref).max()
+        errs.append(float(np.max(np.abs(got[ok] / ref[ok] - 1.0))))
+    assert errs[-1] < 2e-10
+    assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 10
+    # the full right-hand side, including kappa, at the finest sampling
+    u = rng.uniform(-math.log(5.0), 0.0, 200)
+    Y = np.column_stack([rng.uniform(5, 500, 200), rng.uniform(-50, 50, 200),
+                         rng.normal(0, 300, 200), rng.normal(0, 300, 200)])
+    np.testing.assert_allclose(O.rhs(tab, u, Y), O.rhs(base, u, Y), rtol=2e-10, atol=1e-30)
+
+
+def test_sampled_f0_power_law_is_exact_inside_and_outside(oracle_mod):
+    """ln f linear in ln y (a power law) is reproduced exactly by the cubic
+    inside the sampled range and by the end lines outside it."""
+    O = oracle_mod
+    x0, dx, n = math.log(0.05), 0.25, 12
+    lnf = 0.7 - 0.5 * (x0 + dx * np.arange(n))           # f = e^0.7 y^-1/2
+    req = W.plain_small().with_(f0_kind="table", f0_ln_y0=x0, f0_d_ln_y=dx, f0_ln_f=lnf)
+    y = np.geomspace(1e-4, 1e3, 301)
+    np.testing.assert_allclose(O.f0_of(req, y), math.exp(0.7) / np.sqrt(y), rtol=1e-13)
+
+
+def test_sampled_f0_converges_to_fermi_dirac(oracle_mod):
+    """A finely sampled ln of the Fermi-Dirac distribution gives back the
+    closed form between samples, and the background sum 1.5 zeta(3) with it."""
+    O = oracle_mod
+    x0, n = math.log(1e-3), 2001
+    dx = (math.log(200.0) - x0) / (n - 1)
+    ys = np.exp(x0 + dx * np.arange(n))
+    req = W.plain_small().with_(f0_kind="table", f0_ln_y0=x0, f0_d_ln_y=dx,
+                                f0_ln_f=-np.logaddexp(0.0, ys))
+    y = np.geomspace(1.1e-3, 150.0, 997)
+    # the cubic's error in ln f is at most ~(9/16)/24 dx^4 max|d^4 ln f/d(ln y)^4|, and that
+    # derivative of -ln(1 + e^y) is below 1 + y
+    err = np.abs(np.log(O.f0_of(req, y)) - np.log(O.f0("fermi_dirac", y)))
+    assert np.all(err <= 0.03 * dx ** 4 * (1.0 + y))
+    assert err.max() > 0.0
+    yq = np.geomspace(0.01, 100.0, 200)
+    w = O.y_weights(yq)
+    assert abs(math.fsum(w * O.f0_of(req, yq)) / math.fsum(w * O.f0("fermi_dirac", yq)) - 1.0) < 1e-10
