@@ -335,6 +335,9 @@ def main():
     }
     if plain:
         line.update(plain_leg(ctx, stream, reqs, args.warmup))
+        measured = ctx.fp64_fma_peak()
+        line["roofline"]["peak_measured"] = measured
+        line["roofline"]["frac_of_measured_peak"] = line["roofline"]["achieved"] / measured
     if args.fp32c:
         line["fp32c"] = fp32c_leg(ctx, stream, reqs)
     if args.batched:

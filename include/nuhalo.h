@@ -160,7 +160,8 @@ typedef struct {
     const double *w_mu;      /* host, n_mu, required when mu != NULL */
 } nh_grid;
 
-/* Integrator, in u = ln a from 0 (z = 0) down to -ln(1 + z_end). */
+/* Integrator, in u = ln a from -ln(1 + z_obs) (0 for observation today) down to
+ * -ln(1 + z_end). */
 enum {
     NH_RK4    = 0,           /* classical RK4, n_steps equal steps */
     NH_DOPRI5 = 1            /* Dormand-Prince 5(4), adaptive */
@@ -183,8 +184,13 @@ typedef struct {
     double    atol_v;        /* km/s; <= 0 means rtol * 1 km/s */
     double    h0;            /* first trial step in u; 0 means -1e-3 */
     long long max_steps;     /* attempted-step budget per trajectory; <= 0 means 1e6 */
-    double    z_end;         /* > 0 */
+    double    z_end;         /* > z_obs */
     int       precision;     /* NH_FP64 | NH_FP32C (NH_FP32C needs NH_DOPRI5) */
+    double    z_obs;         /* >= 0: the profile is observed at z_obs (the paper's z0, Sec. II.B):
+                                integration runs from u = -ln(1+z_obs); the halo's reference
+                                epoch is z_obs (NH_GEOM_PAPER: R from M(z_obs), fixed physical
+                                r200 = R / ((1+z_obs) 200^(1/3)), z_end <= (1+z_obs) 200^(1/3) - 1;
+                                NH_MASS_PAPER: xi = (z_form - z) / (z_form - z_obs)) */
 } nh_integrator;
 
 typedef struct {
@@ -275,6 +281,19 @@ int nh_solve(nh_context *ctx, const nh_request *req, double *n_over_nbar, nh_sta
 int nh_solve_async(nh_context *ctx, const nh_request *req, double *d_out, double *d_ratio,
                    void *stream);
 
+/* Several relic masses from one integration (Sec. II.D: the equations of
+ * motion do not involve the mass).  The request fixes the velocities: its y
+ * grid at its m_eV.  For mass m_k the same trajectories carry momenta
+ * y_j m_k / m_eV, and the profile is the quadrature over that grid (its
+ * weights computed from the scaled grid as for any request), so mass k's
+ * profile is the profile of the request with m = m_k and y scaled by
+ * m_k / m_eV.  Enqueued like nh_solve_async (statistics: nh_last_stats).
+ * m_eV: host, n_mass > 0 finite masses, 1 <= n_mass <= 4096.
+ * d_out: device, n_mass * n_r doubles, mass-major (mass k at d_out + k n_r).
+ * d_ratio: as for nh_solve_async, or NULL. */
+int nh_solve_masses(nh_context *ctx, const nh_request *req, int n_mass, const double *m_eV,
+                    double *d_out, double *d_ratio, void *stream);
+
 /* Wait for the last nh_solve_async on this context and return its statistics
  * and status (NH_OK, NH_ESTEPS or NH_ENONFINITE). */
 int nh_last_stats(nh_context *ctx, nh_stats *stats);
@@ -338,7 +357,7 @@ int nh_gauss_legendre(int n, double *x, double *w);
 
 /* The u-dependent coefficients of the equations of motion as the library
  * tabulates them on the host in FP64, at n points u (u = ln a, in
- * [-ln(1+z_end), 0]).  out: host, 6*n doubles, row i = (A, K, Kc, 1/s, c, R):
+ * [-ln(1+z_end), -ln(1+z_obs)]).  out: host, 6*n doubles, row i = (A, K, Kc, 1/s, c, R):
  *   dx/du = A v,   dv/du = -[K I(min(r/s, c)) / r^3 - Kc] x  for r < R, else 0,
  * A = (1+z)^2/H, K = kappa G (1+z) M / (H I(c)), Kc = kappa G (1+z) M / (H R^3),
  * s the comoving NFW scale radius, R the compensation radius (1e300 when
@@ -352,6 +371,12 @@ const char *nh_last_error(const nh_context *ctx);
 
 /* Library version string. */
 const char *nh_version(void);
+
+/* Measured FP64 vector FMA throughput of the context's device (TFLOP/s, FMA =
+ * 2 FLOP): a kernel of independent v_fma_f64 chains in every lane of every CU,
+ * best of three launches.  The datasheet peak of an MI355X is 78.6 TFLOP/s;
+ * this is the ceiling the trajectory kernels are judged against as well. */
+int nh_fp64_fma_peak(nh_context *ctx, double *tflops);
 
 #ifdef __cplusplus
 }

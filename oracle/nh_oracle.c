@@ -63,6 +63,7 @@ typedef struct {
     double kappa_b;
     int    geometry;           /* 0 paper: fixed physical r200 = R / 200^(1/3); 1: 200 x mean density at each z */
     int    compensated;        /* 1 paper: underdense shell out to comoving R; 0 plain NFW + point mass */
+    double z_obs;              /* observation redshift z0 (Sec. II.B): the halo's reference epoch */
     /* sampled histories: samples at u_i = hist_u_min + i (0 - hist_u_min) / (hist_n - 1), u = ln a,
        given as the pieces of their cubic spline: on [u_i, u_{i+1}] the value is
        p[4i] t^3 + p[4i+1] t^2 + p[4i+2] t + p[4i+3] with t = u - u_i */
@@ -145,7 +146,7 @@ double nho_mass(const nho_model *m, double z)
 {
     switch (m->mass_kind) {
     case 1: {
-        double xi = (m->z_form - z) / m->z_form;
+        double xi = (m->z_form - z) / (m->z_form - m->z_obs);
         if (xi < 0.0) xi = 0.0;
         if (xi > 1.0) xi = 1.0;
         return m->M0_Msun * pow(xi, m->mass_alpha);
@@ -184,9 +185,9 @@ double nho_kappa(const nho_model *m, double z)
  * R: comoving Lagrangian radius, M = (4 pi/3) R^3 rhobar_m0 with
  *    rhobar_m0 = 3 Om H0^2 / (8 pi G), i.e. R^3 = 2 G M / (Om H0^2).
  * rv: comoving image of the NFW truncation radius.  Paper geometry: the
- *    physical r200 = R/(1+z_i) with (1+z_i) = 200^(1/3) is fixed, so the
- *    comoving radius is r200 (1+z) and R uses M(z=0).  Geometry 1: R and
- *    r200 = R / 200^(1/3) follow M(z). */
+ *    physical r200 = R/(1+z_i) with (1+z_i)/(1+z0) = 200^(1/3) is fixed, so
+ *    the comoving radius is r200 (1+z) and R uses M(z0), z0 the observation
+ *    redshift.  Geometry 1: R and r200 = R / 200^(1/3) follow M(z). */
 void nho_radii(const nho_model *m, double z, double *R, double *rv)
 {
     double H0k = m->H0_km_s_Mpc / 1000.0;
@@ -196,8 +197,8 @@ void nho_radii(const nho_model *m, double z, double *R, double *rv)
         *R = cbrt(fac * nho_mass(m, z));
         *rv = *R / c200;
     } else {
-        *R = cbrt(fac * nho_mass(m, 0.0));
-        *rv = (*R / c200) * (1.0 + z);
+        *R = cbrt(fac * nho_mass(m, m->z_obs));
+        *rv = (*R / c200) * ((1.0 + z) / (1.0 + m->z_obs));
     }
 }
 

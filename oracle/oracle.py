@@ -69,6 +69,7 @@ class _Model(ctypes.Structure):
         ("kappa_b", ctypes.c_double),
         ("geometry", ctypes.c_int),
         ("compensated", ctypes.c_int),
+        ("z_obs", ctypes.c_double),
         ("hist_n", ctypes.c_int),
         ("hist_u_min", ctypes.c_double),
         ("hist_M", ctypes.POINTER(ctypes.c_double)),
@@ -167,6 +168,7 @@ def model_of(req, static_background: bool = False) -> _Model:
     m.kappa_b = float(req.kappa_b)
     m.geometry = _GEOMETRY[req.geometry]
     m.compensated = int(bool(req.compensated))
+    m.z_obs = float(getattr(req, "z_obs", 0.0))
     # sampled histories: the not-a-knot cubic spline through the samples in
     # u = ln a (scipy's CubicSpline), handed to the C side as its polynomial
     # pieces; the model keeps the coefficient arrays alive
@@ -197,7 +199,7 @@ def integ_of(req) -> _Integ:
     it = _Integ()
     it.method = _METHOD[req.method]
     it.n_steps = int(req.n_steps)
-    it.u_start = 0.0
+    it.u_start = -math.log1p(float(getattr(req, "z_obs", 0.0)))
     it.u_end = u_end_of(float(req.z_end))
     it.rtol = float(req.rtol)
     it.atol_x = float(req.rtol if req.atol_x is None else req.atol_x)
@@ -394,6 +396,21 @@ def solve(req, threads: int | None = None):
     prof = profile_from_ratio(req, tr["ratio"])
     tr["n_over_nbar"] = prof
     return tr
+
+
+def solve_masses(req, m_eV, threads: int | None = None):
+    """Profiles for several relic masses from one set of trajectories (Sec. II.D:
+    the equations of motion do not contain the mass).  The request's y grid at
+    its own mass fixes the velocities; for mass m the same trajectories carry
+    momenta y m / m_req, so mass m's profile is the quadrature of the request
+    with that mass and that scaled grid.  Returns (n_mass, n_r)."""
+    tr = trajectories(req, threads)
+    y = np.asarray(req.y, dtype=np.float64)
+    out = []
+    for m in np.atleast_1d(np.asarray(m_eV, dtype=np.float64)):
+        rq = req.with_(m_eV=float(m), y=y * (float(m) / req.m_eV))
+        out.append(profile_from_ratio(rq, tr["ratio"]))
+    return np.array(out)
 
 
 # --------------------------------------------------------------------------

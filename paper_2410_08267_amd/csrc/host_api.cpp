@@ -70,7 +70,7 @@ int ensure_pinned(nh_context *ctx, size_t bytes)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Staged inputs of one request: layout and host construction.
-Staged stage_layout(const nh_request *q, int table_nodes)
+Staged stage_layout(const nh_request *q, int table_nodes, int n_mass)
 {
     Staged s{};
     const bool rk4 = q->integ.method == NH_RK4;
@@ -88,14 +88,18 @@ Staged stage_layout(const nh_request *q, int table_nodes)
     s.f0_x0 = q->f0.kind == NH_F0_TABLE ? q->f0.ln_y0 : 0.0;
     s.f0_inv_dx = q->f0.kind == NH_F0_TABLE ? 1.0 / q->f0.d_ln_y : 0.0;
     s.off_f0 = off;   off = align_up(off + (size_t)s.f0_n * sizeof(double));
+    s.n_mass = n_mass;
+    s.off_ym = off;   off = align_up(off + (size_t)n_mass * q->grid.n_y * sizeof(double));
+    s.off_wm = off;   off = align_up(off + (size_t)n_mass * q->grid.n_y * sizeof(double));
     s.bytes = off;
     return s;
 }
 
-void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P)
+void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P, const double *m_eV)
 {
     Physics ph(*q);
     const double u_end = -std::log1p(q->integ.z_end);
+    const double u_start = -std::log1p(q->integ.z_obs);
     double *tab = (double *)(base + s.off_tab);
     std::memset(&P, 0, sizeof(P));
     P.n_r = q->grid.n_r;
@@ -104,16 +108,17 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P)
     P.n_traj = n_traj_of(q);
     // km/s per unit y: v = P/m = y k_B T c / m (non-relativistic, Sec. II.D)
     P.vfac = KB_EV_PER_K * q->f0.T_K * C_KM_S / q->m_eV;
+    P.u_start = u_start;
     P.u_end = u_end;
     if (q->integ.method == NH_RK4) {
         build_rk4_table(ph, u_end, q->integ.n_steps, tab);
         P.n_steps = q->integ.n_steps;
-        P.rk_h = u_end / (double)q->integ.n_steps;
+        P.rk_h = (u_end - u_start) / (double)q->integ.n_steps;
     } else {
         build_interp_table(ph, u_end, s.n_tab, tab);
         P.n_tab = s.n_tab;
         P.tab_u0 = u_end;
-        P.tab_inv_du = (double)(s.n_tab - 1) / (0.0 - u_end);
+        P.tab_inv_du = (double)(s.n_tab - 1) / (u_start - u_end);
     }
     const double rt = q->integ.rtol;
     P.rtol = rt;
@@ -123,6 +128,15 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P)
     P.max_steps = q->integ.max_steps > 0 ? q->integ.max_steps : 1000000;
     if (P.max_steps > 2000000000LL) P.max_steps = 2000000000LL;
     P.r_exit = ph.r_exit(u_end);
+    // App. B cull, enabled only where it can act: a relic that starts inside
+    // R_exit is never farther than its start radius from the halo, so only
+    // start radii at or beyond R_exit (with a margin) can hold culled relics
+    P.cull_D = 0.0;
+    if (P.r_exit > 0.0) {
+        double rmax = 0.0;
+        for (int k = 0; k < q->grid.n_r; ++k) rmax = std::max(rmax, q->grid.r_kpc[k]);
+        if (rmax * rmax >= 0.999 * P.r_exit * P.r_exit) P.cull_D = ph.drift(u_end);
+    }
     // paper geometry (or no compensation): R does not depend on u
     if (q->halo.geometry == NH_GEOM_PAPER || !q->halo.compensated)
         P.R_const = q->halo.compensated ? ph.R_fixed : 1.0e300;
@@ -143,6 +157,14 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P)
     }
     for (int l = 0; l < q->grid.n_mu; ++l) smu[l] = std::sqrt(1.0 - mu[l] * mu[l]);
     if (s.f0_n > 0) std::memcpy(base + s.off_f0, q->f0.ln_f, sizeof(double) * s.f0_n);
+    // other masses: the same velocities are momenta y m_k / m, weights of that grid
+    for (int k = 0; k < s.n_mass; ++k) {
+        double *ym = (double *)(base + s.off_ym) + (size_t)k * q->grid.n_y;
+        double *wm = (double *)(base + s.off_wm) + (size_t)k * q->grid.n_y;
+        const double f = m_eV[k] / q->m_eV;
+        for (int j = 0; j < q->grid.n_y; ++j) ym[j] = q->grid.y[j] * f;
+        y_weights(q->grid.n_y, ym, wm);
+    }
 }
 
 GridPtrs grid_ptrs(const Staged &s, const char *dev)
@@ -177,19 +199,26 @@ int wait_pending(nh_context *ctx)
 }
 
 int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d_ratio,
-                  hipStream_t stream)
+                  hipStream_t stream, int n_mass, const double *m_eV)
 {
     int rc = validate(q, ctx->err, sizeof(ctx->err));
     if (rc != NH_OK) return rc;
+    if (n_mass < 0 || n_mass > 4096) return set_err(ctx, NH_EINVAL, "n_mass must be in [1, 4096]");
+    for (int k = 0; k < n_mass; ++k)
+        if (!m_eV || !std::isfinite(m_eV[k]) || !(m_eV[k] > 0))
+            return set_err(ctx, NH_EINVAL, "mass %d must be finite and > 0", k);
     HIPCHK(hipSetDevice(ctx->device));
     if ((rc = wait_pending(ctx)) != NH_OK) return rc;
     ctx->pending = false;
 
-    const Staged s = stage_layout(q, ctx->table_nodes);
+    const Staged s = stage_layout(q, ctx->table_nodes, n_mass);
     if ((rc = ensure_pinned(ctx, s.bytes)) != NH_OK) return rc;
     TrajParams P;
-    stage_fill(q, s, (char *)ctx->h_stage, P);
-    if (!ctx->free_exit && P.r_exit > 0.0) P.r_exit = -1.0;
+    stage_fill(q, s, (char *)ctx->h_stage, P, m_eV);
+    if (!ctx->free_exit && P.r_exit > 0.0) {
+        P.r_exit = -1.0;
+        P.cull_D = 0.0;
+    }
     if ((rc = ensure_dev(ctx, ctx->blob, s.bytes)) != NH_OK) return rc;
     HIPCHK(hipMemcpyAsync(ctx->blob.p, ctx->h_stage, s.bytes, hipMemcpyHostToDevice, stream));
     const GridPtrs g = grid_ptrs(s, (const char *)ctx->blob.p);
@@ -223,7 +252,12 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
         else HIPCHK(launch_dp5_f64(P, g, o, counter, ctx->n_cu, stream));
     }
     HIPCHK(hipEventRecord(ctx->ev_t1, stream));
-    HIPCHK(launch_reduce_profile(P, g, d_ratio, d_out, stream));
+    if (n_mass > 0)
+        HIPCHK(launch_reduce_masses(P, g, d_ratio, (const double *)((const char *)ctx->blob.p + s.off_ym),
+                                    (const double *)((const char *)ctx->blob.p + s.off_wm), n_mass, d_out,
+                                    stream));
+    else
+        HIPCHK(launch_reduce_profile(P, g, d_ratio, d_out, stream));
     HIPCHK(launch_reduce_stats(n, o, stats, stream));
     HIPCHK(hipEventRecord(ctx->ev_done, stream));
     ctx->pending = true;
@@ -265,6 +299,28 @@ using namespace nh;
 extern "C" {
 
 const char *nh_version(void) { return "nuhalo 0.1 (gfx950)"; }
+
+int nh_fp64_fma_peak(nh_context *ctx, double *tflops)
+{
+    if (!ctx || !tflops) return set_err(ctx, NH_EINVAL, "context and tflops are required");
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc;
+    if ((rc = wait_pending(ctx)) != NH_OK) return rc;
+    const int blocks = ctx->n_cu * 8;
+    if ((rc = ensure_dev(ctx, ctx->out, (size_t)blocks * 1024 * sizeof(double))) != NH_OK) return rc;
+    double best = 0.0, flop = 0.0;
+    for (int rep = 0; rep < 4; ++rep) {
+        HIPCHK(hipEventRecord(ctx->ev_t0, ctx->stream));
+        HIPCHK(launch_fma_probe((double *)ctx->out.p, blocks, ctx->stream, &flop));
+        HIPCHK(hipEventRecord(ctx->ev_t1, ctx->stream));
+        HIPCHK(hipEventSynchronize(ctx->ev_t1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+        if (rep > 0 && ms > 0.f) best = std::max(best, flop / (ms * 1e-3) / 1e12);   // first launch warms up
+    }
+    *tflops = best;
+    return NH_OK;
+}
 
 const char *nh_strerror(int code)
 {
@@ -404,7 +460,16 @@ int nh_solve_async(nh_context *ctx, const nh_request *req, double *d_out, double
 {
     if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
     if (!d_out) return set_err(ctx, NH_EINVAL, "d_out is NULL");
-    return solve_enqueue(ctx, req, d_out, d_ratio, (hipStream_t)stream);
+    return solve_enqueue(ctx, req, d_out, d_ratio, (hipStream_t)stream, 0, nullptr);
+}
+
+int nh_solve_masses(nh_context *ctx, const nh_request *req, int n_mass, const double *m_eV, double *d_out,
+                    double *d_ratio, void *stream)
+{
+    if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
+    if (!d_out || !m_eV) return set_err(ctx, NH_EINVAL, "d_out and m_eV are required");
+    if (n_mass < 1) return set_err(ctx, NH_EINVAL, "n_mass must be in [1, 4096]");
+    return solve_enqueue(ctx, req, d_out, d_ratio, (hipStream_t)stream, n_mass, m_eV);
 }
 
 int nh_last_stats(nh_context *ctx, nh_stats *stats)
@@ -437,7 +502,7 @@ int nh_solve(nh_context *ctx, const nh_request *req, double *n_over_nbar, nh_sta
     int rc = validate(req, ctx->err, sizeof(ctx->err));
     if (rc != NH_OK) return rc;
     if ((rc = ensure_dev(ctx, ctx->out, (size_t)req->grid.n_r * sizeof(double))) != NH_OK) return rc;
-    rc = solve_enqueue(ctx, req, (double *)ctx->out.p, nullptr, ctx->stream);
+    rc = solve_enqueue(ctx, req, (double *)ctx->out.p, nullptr, ctx->stream, 0, nullptr);
     if (rc != NH_OK) return rc;
     rc = collect_stats(ctx, stats);
     if (rc != NH_OK && rc != NH_ESTEPS) return rc;

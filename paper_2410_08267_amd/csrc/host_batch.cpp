@@ -55,7 +55,10 @@ void describe(const nh_context *ctx, const nh_request *q, const Staged &s, char 
 {
     std::memset(&d, 0, sizeof(d));
     stage_fill(q, s, host_base, d.P);
-    if (!ctx->free_exit && d.P.r_exit > 0.0) d.P.r_exit = -1.0;
+    if (!ctx->free_exit && d.P.r_exit > 0.0) {
+        d.P.r_exit = -1.0;
+        d.P.cull_D = 0.0;
+    }
     d.P.order = ctx->queue_order;
     d.P.h_fp64 = q->integ.precision == NH_FP32C ? ctx->h_fp64 : 0.0;
     d.g = grid_ptrs(s, dev_base);

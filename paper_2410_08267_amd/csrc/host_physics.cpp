@@ -96,6 +96,8 @@ Physics::Physics(const nh_request &q)
     kb = q.halo.kappa_b;
     geometry = q.halo.geometry;
     compensated = q.halo.compensated;
+    z_obs = q.integ.z_obs;
+    u_start = -std::log1p(z_obs);
     const nh_history &hs = q.halo.history;
     if (mass_kind == NH_MASS_TABLE || conc_kind == NH_CONC_TABLE || kappa_kind == NH_KAPPA_TABLE) {
         hist_n = hs.n;
@@ -117,15 +119,15 @@ Physics::Physics(const nh_request &q)
             spline_second_derivatives(hist_kappa, hist_n, du, hist_kappa2.data());
         }
     }
-    // M(0) = (4 pi/3) R^3 rhobar_m0, rhobar_m0 = 3 Om H0^2 / (8 pi G)  =>  R^3 = 2 G M / (Om H0^2)
-    R_fixed = std::cbrt(2.0 * G * mass(0.0) / (Om * H0k * H0k));
+    // M(z_obs) = (4 pi/3) R^3 rhobar_m0, rhobar_m0 = 3 Om H0^2 / (8 pi G)  =>  R^3 = 2 G M / (Om H0^2)
+    R_fixed = std::cbrt(2.0 * G * mass(z_obs) / (Om * H0k * H0k));
 }
 
 double Physics::mass(double z) const
 {
     switch (mass_kind) {
     case NH_MASS_PAPER: {
-        double xi = (z_form - z) / z_form;
+        double xi = (z_form - z) / (z_form - z_obs);
         xi = xi < 0.0 ? 0.0 : (xi > 1.0 ? 1.0 : xi);
         return M0 * std::pow(xi, alpha);
     }
@@ -185,7 +187,7 @@ void Physics::coef(double u, double out[NCOL]) const
         rv = R / kCbrt200;
     } else {
         R = R_fixed;
-        rv = (R_fixed / kCbrt200) * opz;   // fixed physical r200, comoving image
+        rv = (R_fixed / kCbrt200) * (opz / (1.0 + z_obs));   // fixed physical r200, comoving image
     }
     const double B = kappa(z) * G * opz / H;
     out[COL_K] = B * M / nfw_I_host(c);
@@ -196,7 +198,7 @@ void Physics::coef(double u, double out[NCOL]) const
 
 double Physics::r_exit(double u_end) const
 {
-    // Beyond the largest compensation radius over [u_end, 0] the force is
+    // Beyond the largest compensation radius over [u_end, u_start] the force is
     // exactly zero; an outward-moving relic there never returns (backward
     // motion is along -v, and x.v <= 0 makes |x - s v| grow with s).
     if (!compensated || mass_kind == NH_MASS_ZERO) return compensated ? 0.0 : -1.0;
@@ -204,7 +206,7 @@ double Physics::r_exit(double u_end) const
     double Rmax = 0.0;
     const int n = 4097;
     for (int i = 0; i < n; ++i) {
-        double u = u_end * (double)i / (double)(n - 1);
+        double u = u_start + (u_end - u_start) * (double)i / (double)(n - 1);
         double M = mass(std::expm1(-u));
         double R = std::cbrt(2.0 * G * M / (Om * H0k * H0k));
         Rmax = R > Rmax ? R : Rmax;
@@ -214,24 +216,39 @@ double Physics::r_exit(double u_end) const
     return mass_kind == NH_MASS_TABLE ? Rmax * 1.001 : Rmax;
 }
 
+double Physics::drift(double u_end) const
+{
+    // composite Simpson over 2048 intervals of A(u) = e^{-2u} / H(u) (smooth, so
+    // the error is ~1e-13 relative; the cull that uses it keeps a 1e-9 margin)
+    const int n = 2048;
+    const double h = (u_start - u_end) / n;
+    auto A = [&](double u) {
+        const double opz = std::exp(-u);
+        return opz * opz / (H0k * std::sqrt(Om * opz * opz * opz + OL));
+    };
+    double s = A(u_end) + A(u_start);
+    for (int i = 1; i < n; ++i) s += (i & 1 ? 4.0 : 2.0) * A(u_end + i * h);
+    return s * h / 3.0;
+}
+
 // 3073 nodes over u in [-ln 5, 0]: cubic interpolation error below ~2e-13
 // relative for the columns of the benchmark halos (checked on the host).
 int default_table_nodes() { return 3073; }
 
 void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out)
 {
-    const double du = (0.0 - u_end) / (double)(n_tab - 1);
+    const double du = (ph.u_start - u_end) / (double)(n_tab - 1);
     for (int i = 0; i < n_tab; ++i) {
-        double u = (i == n_tab - 1) ? 0.0 : u_end + (double)i * du;
+        double u = (i == n_tab - 1) ? ph.u_start : u_end + (double)i * du;
         ph.coef(u, out + (size_t)i * NCOL);
     }
 }
 
 void build_rk4_table(const Physics &ph, double u_end, int n_steps, double *out)
 {
-    // Stage abscissae u_m = m * (u_end / (2N)), m = 0..2N.
-    const double hh = u_end / (double)(2 * n_steps);
-    for (int m = 0; m <= 2 * n_steps; ++m) ph.coef((double)m * hh, out + (size_t)m * NCOL);
+    // Stage abscissae u_m = u_start + m (u_end - u_start) / (2N), m = 0..2N.
+    const double hh = (u_end - ph.u_start) / (double)(2 * n_steps);
+    for (int m = 0; m <= 2 * n_steps; ++m) ph.coef(ph.u_start + (double)m * hh, out + (size_t)m * NCOL);
 }
 
 void gauss_legendre(int n, double *x, double *w)
@@ -390,8 +407,12 @@ int validate(const nh_request *q, char *msg, size_t msg_len)
     }
     const nh_integrator &it = q->integ;
     if (!std::isfinite(it.z_end) || it.z_end <= 0) NH_BAD("z_end must be finite and > 0");
-    if (h.geometry == NH_GEOM_PAPER && h.mass_kind != NH_MASS_ZERO && it.z_end > kCbrt200 - 1.0 + 1e-12)
-        NH_BAD("paper geometry is defined up to z_i = 200^(1/3) - 1");
+    if (!std::isfinite(it.z_obs) || it.z_obs < 0) NH_BAD("z_obs must be finite and >= 0");
+    if (!(it.z_end > it.z_obs)) NH_BAD("z_end must exceed z_obs");
+    if (h.geometry == NH_GEOM_PAPER && h.mass_kind != NH_MASS_ZERO &&
+        it.z_end > (1.0 + it.z_obs) * kCbrt200 - 1.0 + 1e-12)
+        NH_BAD("paper geometry is defined up to z_i = (1 + z_obs) 200^(1/3) - 1");
+    if (h.mass_kind == NH_MASS_PAPER && !(h.z_form > it.z_obs)) NH_BAD("z_form must exceed z_obs");
     if (h.geometry == NH_GEOM_DELTA200 && h.mass_kind == NH_MASS_PAPER && !(it.z_end < h.z_form))
         NH_BAD("delta200 geometry needs M(z_end) > 0: z_end < z_form");
     if (it.method == NH_RK4) {

@@ -264,7 +264,13 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
                     double x0, vx0, vy0;
                     initial_state(q, t, x0, vx0, vy0);
                     v0n = sqrt(norm2(vx0, vy0));
-                    dp5_start(L, lp.cf, x0, vx0, vy0, q.P.h0, q.P.u_end);
+                    if (q.P.cull_D > 0.0 && never_enters(x0, vx0, vy0, q.P.cull_D, cull_radius2(q.P.r_exit))) {
+                        finish_free(q, t);
+                        slot_release(S, s);
+                        t = -1;
+                    } else {
+                        dp5_start(L, lp.cf, x0, vx0, vy0, q.P.h0, q.P.u_start, q.P.u_end);
+                    }
                 }
             }
         }
@@ -359,7 +365,13 @@ __global__ __launch_bounds__(512) void k_slice_f32c(SliceArgs A)
                     double x0, vx0, vy0;
                     initial_state(q, t, x0, vx0, vy0);
                     v0n = sqrt(norm2(vx0, vy0));
-                    f32c_start(L, lp.cf, x0, vx0, vy0, q.P.h0, q.P.u_end);
+                    if (q.P.cull_D > 0.0 && never_enters(x0, vx0, vy0, q.P.cull_D, cull_radius2(q.P.r_exit))) {
+                        finish_free(q, t);
+                        slot_release(S, s);
+                        t = -1;
+                    } else {
+                        f32c_start(L, lp.cf, x0, vx0, vy0, q.P.h0, q.P.u_start, q.P.u_end);
+                    }
                 }
             }
         }

@@ -16,7 +16,9 @@
 
 namespace nh {
 
-template <int NC>
+// CULL: some start radius lies beyond R_exit (otherwise no relic can be culled
+// and the test is left out of the trajectory loop)
+template <int NC, bool CULL>
 __global__ __launch_bounds__(512) void k_dp5_f32c(TrajParams P, GridPtrs g, TrajOut o,
                                                    unsigned long long *counter)
 {
@@ -50,12 +52,21 @@ __global__ __launch_bounds__(512) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
                 const double V = g.y[j] * P.vfac;
                 const double vx0 = V * g.mu[l], vy0 = V * g.smu[l];
                 v0n = sqrt(norm2(vx0, vy0));
-                f32c_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_end);
+                if (CULL && never_enters(g.r[k], vx0, vy0, P.cull_D, cull_radius2(P.r_exit))) {
+                    // App. B cull: the path never reaches R, the momentum is final
+                    o.ratio[t] = 1.0;
+                    o.stat[t] = TrajStat{0, 0, ST_OK | ST_FREE_EXIT, 0};
+                    t = -1;
+                } else {
+                    f32c_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_start, P.u_end);
+                }
             } else {
                 t = -2;
             }
         }
-        if (__ballot(t >= 0) == 0ull) break;
+        // leave once every lane found the queue drained; lanes whose new
+        // trajectory was culled (t == -1) claim again on the next pass
+        if (__ballot(t != -2) == 0ull) break;
         if (t >= 0) {
             const int st = f32c_attempt(L, cf, cf64, ctl, ctl64, P.h_fp64);
             if (st >= 0) {
@@ -68,32 +79,37 @@ __global__ __launch_bounds__(512) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
     }
 }
 
-template <int NC>
+template <int NC, bool CULL>
 static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                  unsigned long long *counter, int n_cu, hipStream_t s)
 {
     const int B = P.block > 0 && P.block < 512 ? P.block : 512;   // launch bound of k_dp5_f32c
     const size_t lds = (size_t)P.n_tab * NC * sizeof(float);
-    hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f32c<NC>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f32c<NC, CULL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dp5_f32c<NC>, B, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dp5_f32c<NC, CULL>, B, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long long grid = (long long)n_cu * per_cu;
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_dp5_f32c<NC>, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
+    auto *kern = k_dp5_f32c<NC, CULL>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                            unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    if (P.R_const > 0.0) return launch_f32c_nc<NCOL - 1>(P, g, o, counter, n_cu, s);
-    return launch_f32c_nc<NCOL>(P, g, o, counter, n_cu, s);
+    const bool cull = P.cull_D > 0.0;
+    if (P.R_const > 0.0)
+        return cull ? launch_f32c_nc<NCOL - 1, true>(P, g, o, counter, n_cu, s)
+                    : launch_f32c_nc<NCOL - 1, false>(P, g, o, counter, n_cu, s);
+    return cull ? launch_f32c_nc<NCOL, true>(P, g, o, counter, n_cu, s)
+                : launch_f32c_nc<NCOL, false>(P, g, o, counter, n_cu, s);
 }
 
 }  // namespace nh

@@ -55,8 +55,10 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
         v0n = sqrt(norm2(vx, vy));
     }
     const double r_exit2 = P.r_exit * P.r_exit;
-    bool active = valid;
-    bool freed = false;
+    // App. B cull: a path that never reaches R needs no steps
+    const bool culled = valid && P.cull_D > 0.0 && never_enters(x, vx, vy, P.cull_D, cull_radius2(P.r_exit));
+    bool active = valid && !culled;
+    bool freed = culled;
     int steps = 0;
     const double h = P.rk_h;
     const double hh = 0.5 * h;
@@ -108,7 +110,10 @@ template <int NC>
 constexpr int dp5_block() { return 1024; }
 constexpr int DP5_DEFAULT_BLOCK = 512;
 
-template <int NC>
+// CULL: some start radius lies beyond R_exit.  Without one no relic can be
+// culled, and the kernel leaves the test out: its branch alone costs the
+// trajectory loop a few percent in register moves.
+template <int NC, bool CULL>
 __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
                                                              unsigned long long *counter)
 {
@@ -145,12 +150,21 @@ __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridP
                 const double V = g.y[j] * P.vfac;
                 const double vx0 = V * g.mu[l], vy0 = V * g.smu[l];
                 v0n = sqrt(norm2(vx0, vy0));
-                dp5_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_end);
+                if (CULL && never_enters(g.r[k], vx0, vy0, P.cull_D, cull_radius2(P.r_exit))) {
+                    // App. B cull: the path never reaches R, the momentum is final
+                    o.ratio[t] = 1.0;
+                    o.stat[t] = TrajStat{0, 0, ST_OK | ST_FREE_EXIT, 0};
+                    t = -1;
+                } else {
+                    dp5_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_start, P.u_end);
+                }
             } else {
                 t = -2;
             }
         }
-        if (__ballot(t >= 0) == 0ull) break;
+        // leave once every lane found the queue drained; lanes whose new
+        // trajectory was culled (t == -1) claim again on the next pass
+        if (__ballot(t != -2) == 0ull) break;
         if (t >= 0) {
             const int st = dp5_attempt(L, cf, ctl);
             if (st >= 0) {
@@ -171,6 +185,21 @@ __global__ __launch_bounds__(256) void k_reduce_profile(TrajParams P, GridPtrs g
                                                         double *__restrict__ out)
 {
     reduce_radius(P, g, ratio, blockIdx.x, out);
+}
+
+// Several masses from the same ratios: block (mass, radius) uses that mass's
+// momentum grid and weights.
+__global__ __launch_bounds__(256) void k_reduce_masses(TrajParams P, GridPtrs g,
+                                                       const double *__restrict__ ratio,
+                                                       const double *__restrict__ ym,
+                                                       const double *__restrict__ wm,
+                                                       double *__restrict__ out)
+{
+    const int im = blockIdx.x / P.n_r, k = blockIdx.x - im * P.n_r;
+    GridPtrs gm = g;
+    gm.y = ym + (size_t)im * P.n_y;
+    gm.wy = wm + (size_t)im * P.n_y;
+    reduce_radius(P, gm, ratio, k, out + (size_t)im * P.n_r);
 }
 
 // Integer statistics (exact under any summation order).
@@ -205,38 +234,51 @@ hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut 
     return hipGetLastError();
 }
 
-template <int NC>
+template <int NC, bool CULL>
 static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                 unsigned long long *counter, int n_cu, hipStream_t s)
 {
     const int B = P.block > 0 ? P.block : DP5_DEFAULT_BLOCK;
     const size_t lds = (size_t)P.n_tab * NC * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f64<NC>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f64<NC, CULL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dp5_f64<NC>, B, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dp5_f64<NC, CULL>, B, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long long grid = (long long)n_cu * per_cu;
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_dp5_f64<NC>, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
+    auto *kern = k_dp5_f64<NC, CULL>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                           unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    if (P.R_const > 0.0) return launch_dp5_nc<NCOL - 1>(P, g, o, counter, n_cu, s);
-    return launch_dp5_nc<NCOL>(P, g, o, counter, n_cu, s);
+    const bool cull = P.cull_D > 0.0;
+    if (P.R_const > 0.0)
+        return cull ? launch_dp5_nc<NCOL - 1, true>(P, g, o, counter, n_cu, s)
+                    : launch_dp5_nc<NCOL - 1, false>(P, g, o, counter, n_cu, s);
+    return cull ? launch_dp5_nc<NCOL, true>(P, g, o, counter, n_cu, s)
+                : launch_dp5_nc<NCOL, false>(P, g, o, counter, n_cu, s);
 }
 
 hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,
                                  double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reduce_profile, dim3(P.n_r), dim3(256), 0, s, P, g, ratio, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_masses(const TrajParams &P, const GridPtrs &g, const double *ratio, const double *ym,
+                                const double *wm, int n_mass, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_masses, dim3((unsigned)(P.n_r * n_mass)), dim3(256), 0, s, P, g, ratio, ym, wm,
+                       out);
     return hipGetLastError();
 }
 
@@ -247,6 +289,41 @@ hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_reduce_stats, dim3((unsigned)blocks), dim3(256), 0, s, n, o, stats);
+    return hipGetLastError();
+}
+
+}  // namespace nh
+
+namespace nh {
+
+// ---------------------------------------------------------------------------
+// FP64 FMA throughput probe: 8 independent chains per lane, no memory traffic
+// in the loop; the sum is stored so nothing is dead code.
+// ---------------------------------------------------------------------------
+
+constexpr int FMA_PROBE_ITERS = 4096;
+constexpr int FMA_PROBE_CHAINS = 8;
+
+__global__ __launch_bounds__(1024) void k_fma_probe(double *out, double seed)
+{
+    double a[FMA_PROBE_CHAINS];
+#pragma unroll
+    for (int c = 0; c < FMA_PROBE_CHAINS; ++c) a[c] = seed + threadIdx.x * 1e-9 + c;
+    const double m = 0.999999999, k = 1e-9;
+    for (int it = 0; it < FMA_PROBE_ITERS; ++it) {
+#pragma unroll
+        for (int c = 0; c < FMA_PROBE_CHAINS; ++c) a[c] = fma(a[c], m, k);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < FMA_PROBE_CHAINS; ++c) s += a[c];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+hipError_t launch_fma_probe(double *out, int blocks, hipStream_t s, double *flop)
+{
+    hipLaunchKernelGGL(k_fma_probe, dim3(blocks), dim3(1024), 0, s, out, 1.0);
+    *flop = 2.0 * FMA_PROBE_ITERS * FMA_PROBE_CHAINS * 1024.0 * blocks;
     return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@ struct DevBuf {
 struct Staged {
     int n_tab;
     size_t off_tab, off_r, off_y, off_wy, off_mu, off_smu, off_wmu, off_f0;
+    int n_mass;             // multi-mass solve: scaled y grids and weights per mass
+    size_t off_ym, off_wm;
     int f0_kind, f0_n;
     double f0_x0, f0_inv_dx;
     size_t bytes;
@@ -56,8 +58,9 @@ namespace nh {
 int set_err(nh_context *ctx, int code, const char *fmt, ...);
 int ensure_dev(nh_context *ctx, DevBuf &b, size_t bytes);
 int ensure_pinned(nh_context *ctx, size_t bytes);
-Staged stage_layout(const nh_request *q, int table_nodes);
-void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P);
+Staged stage_layout(const nh_request *q, int table_nodes, int n_mass = 0);
+void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P,
+                const double *m_eV = nullptr);
 GridPtrs grid_ptrs(const Staged &s, const char *dev);
 size_t per_traj_bytes(const nh_request *q);
 void serve_shutdown(nh_context *ctx);

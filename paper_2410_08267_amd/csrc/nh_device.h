@@ -205,6 +205,19 @@ __device__ __forceinline__ void rhs(const double c[NCOL], double R, double x, do
     dvy = -g * y;
 }
 
+// App. B: a relic whose straight backward path x0 - v0 s, 0 <= s <= D, stays
+// at or beyond R_exit (the largest compensation radius) never feels the halo,
+// so its momentum is final.  x0 = (r0, 0); R2 = R_exit^2 with a 1e-9 margin.
+__device__ __forceinline__ bool never_enters(double r0, double vx0, double vy0, double D, double R2)
+{
+    double s = r0 * vx0 / norm2(vx0, vy0);
+    s = s < 0.0 ? 0.0 : (s > D ? D : s);
+    const double px = r0 - vx0 * s, py = -(vy0 * s);
+    return norm2(px, py) >= R2;
+}
+
+__device__ __forceinline__ double cull_radius2(double r_exit) { return r_exit * r_exit * (1.0 + 1.0e-9); }
+
 // Relic distribution before the halo formed, y = P / (k_B T).
 __device__ __forceinline__ double f0_eval(const F0Desc &f, double y)
 {

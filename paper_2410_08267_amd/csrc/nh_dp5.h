@@ -43,7 +43,7 @@ struct TabCoef {
 };
 
 struct DpCtl {
-    double u_end;      // integration ends here (< 0)
+    double u_end;      // integration ends here (below the start)
     double rtol, atol_x, atol_v;
     double r_exit2;    // squared free-streaming exit radius; < 0 disables
     int max_steps;
@@ -56,22 +56,22 @@ struct Lane64 {
     bool rej_prev;
 };
 
-// Start a trajectory at u = 0 (first stage evaluated here).
+// Start a trajectory at u = u_start (first stage evaluated here).
 template <class CF>
 __device__ __forceinline__ void dp5_start(Lane64 &L, const CF &cf, double x0, double vx0, double vy0,
-                                          double h0, double u_end)
+                                          double h0, double u_start, double u_end)
 {
     L.x = x0;
     L.y = 0.0;
     L.vx = vx0;
     L.vy = vy0;
-    L.u = 0.0;
+    L.u = u_start;
     L.h = -fabs(h0);
-    if (fabs(L.h) > fabs(u_end)) L.h = u_end;
+    if (fabs(L.h) > fabs(u_end - u_start)) L.h = u_end - u_start;
     L.nacc = L.nrej = L.natt = 0;
     L.rej_prev = false;
     double c[NCOL], R;
-    cf.at(0.0, c, R);
+    cf.at(u_start, c, R);
     rhs(c, R, L.x, L.y, L.vx, L.vy, L.k1x, L.k1y, L.k1u, L.k1v);
 }
 

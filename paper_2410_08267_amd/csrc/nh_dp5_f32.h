@@ -218,11 +218,11 @@ __device__ __forceinline__ int dp5_attempt32(Lane32 &L, const CF &cf, const DpCt
     return -1;
 }
 
-// Start a trajectory at u = 0: FP32 state from the FP64 initial conditions,
+// Start a trajectory at u = u_start: FP32 state from the FP64 initial conditions,
 // first stage evaluated in FP32.
 template <class CF>
 __device__ __forceinline__ void f32c_start(Lane32 &L, const CF &cf, double x0, double vx0, double vy0,
-                                           double h0, double u_end)
+                                           double h0, double u_start, double u_end)
 {
     L.x = (float)x0;
     L.xc = (float)(x0 - (double)L.x);
@@ -230,13 +230,13 @@ __device__ __forceinline__ void f32c_start(Lane32 &L, const CF &cf, double x0, d
     L.yc = 0.0f;
     L.vx = (float)vx0;
     L.vy = (float)vy0;
-    L.u = 0.0;
+    L.u = u_start;
     L.h = -fabs(h0);
-    if (fabs(L.h) > fabs(u_end)) L.h = u_end;
+    if (fabs(L.h) > fabs(u_end - u_start)) L.h = u_end - u_start;
     L.nacc = L.nrej = L.natt = L.n64 = 0;
     L.rej_prev = false;
     float c[NCOL], R;
-    cf.at(0.0, c, R);
+    cf.at(u_start, c, R);
     rhs32(c, R, L.x, L.y, L.vx, L.vy, L.k1x, L.k1y, L.k1u, L.k1v);
 }
 

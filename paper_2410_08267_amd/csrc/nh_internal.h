@@ -40,7 +40,8 @@ struct TrajParams {
     int n_r, n_y, n_mu;
     long long n_traj;
     double vfac;            // k_B T c / m: km/s per unit y
-    // integration interval (u = ln a, backward from 0)
+    // integration interval (u = ln a, backward from u_start = -ln(1 + z_obs))
+    double u_start;
     double u_end;
     // interpolation table: n_tab nodes u_i = u_end + i * du, i = 0..n_tab-1 (DP5)
     int n_tab;
@@ -53,7 +54,9 @@ struct TrajParams {
     double rtol, atol_x, atol_v, h0;
     long long max_steps;
     // exact free-streaming exit: beyond r_exit moving outward the force is zero forever
-    double r_exit;          // <= 0 disables
+    double r_exit;          // <= 0 disables (and disables the cull below)
+    double cull_D;          // int_{u_end}^{u_start} A du: the straight backward path is x0 - v0 s, s <= cull_D;
+                            // 0 where no start radius reaches R_exit (no relic can be culled)
     double R_const;         // > 0: the compensation radius is this constant (no R column)
     int order;              // ORDER_*
     int block;              // workgroup size of the persistent kernels
@@ -154,7 +157,8 @@ struct Physics {
     int kappa_kind;
     double ka, kb;
     int geometry, compensated;
-    double R_fixed;         // NH_GEOM_PAPER: comoving Lagrangian radius from M(z=0)
+    double z_obs, u_start;  // observation epoch (the halo's reference epoch) and u = -ln(1+z_obs)
+    double R_fixed;         // NH_GEOM_PAPER: comoving Lagrangian radius from M(z_obs)
     // sampled histories (the *_TABLE kinds): samples at u_i = hist_u_min + i du and
     // the second derivatives of their not-a-knot cubic splines
     int hist_n = 0;
@@ -170,6 +174,7 @@ struct Physics {
     double hubble(double z) const;
     void coef(double u, double out[NCOL]) const;
     double r_exit(double u_end) const;   // radius beyond which the force is zero at every u
+    double drift(double u_end) const;    // int_{u_end}^{u_start} (1+z)^2 / H du
 };
 
 // Physical constants (the paper states only T_nu0 = 1.95 K).
@@ -191,7 +196,7 @@ long long n_traj_of(const nh_request *q);
 
 // Table builders (host, FP64).
 int default_table_nodes();
-void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out);
+void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out);   // nodes on [u_end, u_start]
 void build_rk4_table(const Physics &ph, double u_end, int n_steps, double *out);
 
 }  // namespace nh

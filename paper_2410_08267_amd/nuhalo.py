@@ -76,7 +76,7 @@ class nh_integrator(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("n_steps", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("atol_x", ctypes.c_double), ("atol_v", ctypes.c_double), ("h0", ctypes.c_double),
                 ("max_steps", ctypes.c_longlong), ("z_end", ctypes.c_double),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("z_obs", ctypes.c_double)]
 
 
 class nh_request(ctypes.Structure):
@@ -116,6 +116,9 @@ _SIGNATURES = {
     "nh_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "nh_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "nh_version": (ctypes.c_char_p, []),
+    "nh_fp64_fma_peak": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "nh_solve_masses": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_request), ctypes.c_int, _dp,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nh_gauss_legendre": (ctypes.c_int, [ctypes.c_int, _dp, _dp]),
     "nh_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
     "nh_coefficients": (ctypes.c_int, [ctypes.POINTER(nh_request), ctypes.c_int, _dp, _dp]),
@@ -216,6 +219,7 @@ class _Marshalled:
         it.max_steps = int(req.max_steps)
         it.z_end = req.z_end
         it.precision = _PREC[req.precision]
+        it.z_obs = req.z_obs
         self.q = q
 
 
@@ -340,6 +344,27 @@ class Context:
         self._check(self._lib.nh_last_trajectory_stats(self.h, acc.ctypes.data_as(ip),
                                                        rej.ctypes.data_as(ip), st.ctypes.data_as(ip)))
         return acc, rej, st
+
+    def solve_masses(self, req: Request, masses, out: "torch.Tensor", ratio=None, stream=None):
+        """Profiles for several relic masses from one integration (velocities fixed by
+        req.y at req.m_eV); out: float64 device tensor of len(masses) * n_r, mass-major."""
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        m = marshal(req)
+        ms = np.ascontiguousarray(np.asarray(masses, dtype=np.float64))
+        if out.numel() < ms.size * m.r.size:
+            raise ValueError("out is too small")
+        s = stream if stream is not None else torch.cuda.current_stream(out.device)
+        rc = self._lib.nh_solve_masses(self.h, ctypes.byref(m.q), int(ms.size), ms.ctypes.data_as(_dp),
+                                       ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(ratio.data_ptr()) if ratio is not None else None,
+                                       ctypes.c_void_p(s.cuda_stream))
+        self._check(rc)
+
+    def fp64_fma_peak(self) -> float:
+        """Measured FP64 vector FMA throughput of the device, TFLOP/s."""
+        t = ctypes.c_double()
+        self._check(self._lib.nh_fp64_fma_peak(self.h, ctypes.byref(t)))
+        return t.value
 
     def solve_batch(self, reqs, out: "torch.Tensor", stream=None):
         """Solve several requests in one persistent launch; out (float64 device tensor)

@@ -79,6 +79,7 @@ class Request:
     max_steps: int = 1_000_000
     z_end: float = 4.0
     precision: str = "fp64"           # fp64 | fp32c
+    z_obs: float = 0.0                # observation redshift (the paper's z0); integration starts there
 
     @property
     def n_r(self) -> int:

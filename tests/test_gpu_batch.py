@@ -127,6 +127,7 @@ def mixed_kinds(rtol):
         base.with_(compensated=False, M0=1e13),
         base.with_(mass_kind="zero"),
         W.shrink(W.plain_scale(4), 5, 12, 6).with_(rtol=rtol),
+        base.with_(M0=4e13, z_obs=0.6, z_end=4.5),
         base.with_(mass_kind="table", conc_kind="table", hist_z_max=4.0,
                    hist_M=2e13 * np.exp(-0.8 * np.expm1(-np.linspace(-np.log(5.0), 0.0, 33))),
                    hist_c=8.0 / np.exp(-np.linspace(-np.log(5.0), 0.0, 33)),
@@ -139,9 +140,11 @@ def mixed_kinds(rtol):
 def test_mixed_geometry_kinds_vs_oracle(ctx, O, sensitivity, rtol):
     """Constant-R and moving-R requests in one launch (the six-column slot layout),
     freeze-in f0, G(z), an uncompensated halo, a halo-free request and one with
-    sampled M(z), c(z) and f0.  At rtol 1e-10 (the gate) within 1e-8; at the
-    production rtol 1e-8 within 1e-8 or 4x the oracle's sensitivity, or 5 rtol
-    (the spread of accept/reject decisions between correct integrations)."""
+    sampled M(z), c(z) and f0, and one observed at z_obs > 0.  At rtol 1e-10
+    (the gate) within 1e-8, or 4x the oracle's sensitivity where the orbits make
+    that larger (the z_obs request: 1.6e-8 under a 1e-12 change of the mass); at
+    the production rtol 1e-8 within 1e-8 or 4x the oracle's sensitivity, or
+    5 rtol (the spread of accept/reject decisions between correct integrations)."""
     reqs = mixed_kinds(rtol)
     say(f"batch fp64 mixed kinds vs oracle, rtol {rtol}")
     profs, stats, rc = run_batch(ctx, reqs)
@@ -149,9 +152,12 @@ def test_mixed_geometry_kinds_vs_oracle(ctx, O, sensitivity, rtol):
     for i, r in enumerate(reqs):
         ref = O.solve(r)["n_over_nbar"]
         e = rel(profs[i], ref).max()
-        if rtol < 1e-9:
+        if rtol < 1e-9 and e <= 1e-8:
             print(f"request {i}: max rel {e:.2e}", flush=True)
-            assert e <= 1e-8, i
+        elif rtol < 1e-9:
+            sens = sensitivity(r, ref)
+            print(f"request {i}: max rel {e:.2e} (oracle sensitivity {sens:.2e})", flush=True)
+            assert e <= 4.0 * sens, i
         else:
             sens = sensitivity(r, ref)
             print(f"request {i}: max rel {e:.2e} (oracle sensitivity {sens:.2e})", flush=True)

@@ -146,6 +146,10 @@ DP5_CASES = {
     "tight_rtol": lambda: W.shrink(W.plain_scale(3), 6, 16, 8).with_(rtol=1e-11),
     "sampled_histories": lambda: _sampled_history(W.shrink(W.plain_scale(2), 8, 16, 6)),
     "sampled_f0": lambda: _sampled_f0(W.shrink(W.plain_scale(6), 8, 16, 6)),
+    "z_obs_paper": lambda: W.shrink(W.plain_small(), 8, 16, 6).with_(
+        method="dp5", mass_kind="paper", M0=1e14, conc_kind="constant", c0=7.0, m_eV=0.3, z_obs=0.5,
+        z_form=1.5 * 200.0 ** (1.0 / 3.0) - 1.0, z_end=1.5 * 200.0 ** (1.0 / 3.0) - 1.0),
+    "z_obs_exponential": lambda: W.shrink(W.plain_scale(1), 8, 16, 6).with_(z_obs=1.0, z_end=5.0),
 }
 
 
@@ -284,3 +288,81 @@ def test_queue_order_does_not_change_results(ctx):
     finally:
         ctx.set_option("queue_order", 0)
     assert np.array_equal(a, b)
+
+
+def test_rk4_observed_at_z_obs(ctx, O):
+    """Integration from z_obs > 0 (the halo's reference epoch moves with it)."""
+    req = W.shrink(W.plain_small(), 6, 12, 6).with_(z_obs=0.8, z_end=3.5, M0=5e13)
+    say(f"rk4 z_obs {req.z_obs} n_traj={req.n_traj}")
+    prof, ratio, stats = gpu_ratios(ctx, req)
+    ref = O.solve(req)
+    print("n/nbar gpu", prof, "\noracle", ref["n_over_nbar"], flush=True)
+    assert rel(prof, ref["n_over_nbar"]).max() <= 1e-9
+    assert stats["n_failed"] == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_cull_relics_that_never_reach_the_halo(ctx, O, prec):
+    """App. B: a relic whose straight backward path stays outside the largest
+    compensation radius feels no force (the compensated halo has no mass
+    perturbation there), so it takes no steps and keeps ratio 1; the oracle,
+    which integrates every trajectory, returns exactly 1 for them too."""
+    base = W.shrink(W.plain_scale(0), 4, 16, 8)
+    R, _ = O.halo_radii(base, 0.0)
+    req = base.with_(r_kpc=R * np.array([0.5, 1.5, 4.0, 12.0]), precision=prec)
+    say(f"cull {prec} radii {req.r_kpc} n_traj={req.n_traj}")
+    prof, ratio, stats = gpu_ratios(ctx, req)
+    acc, rej, _ = ctx.trajectory_stats(req.n_traj)
+    culled = (acc + rej) == 0
+    ref = O.solve(req.with_(precision="fp64"))
+    print(f"culled {culled.sum()} of {req.n_traj}; free exits {stats['free_exits']}", flush=True)
+    assert culled.sum() > req.n_traj // 10
+    assert np.all(ratio[culled] == 1.0)
+    assert np.all(ref["ratio"][culled] == 1.0)
+    tol = 1e-8 if prec == "fp64" else 1e-4
+    assert rel(prof, ref["n_over_nbar"]).max() <= tol
+
+
+def test_masses_reuse_one_integration(ctx, O, sensitivity):
+    """Sec. II.D: one integration serves every relic mass.  Mass m's profile is
+    the quadrature of the scaled momentum grid over the same speed ratios; the
+    request's own mass reproduces the plain solve bit for bit."""
+    req = DP5_CASES["paper_model"]().with_(rtol=1e-10)
+    masses = [req.m_eV, 0.1, 0.6]
+    say(f"masses {masses} n_traj={req.n_traj}")
+    out = torch.empty(len(masses) * req.n_r, dtype=torch.float64, device="cuda")
+    ratio = torch.empty(req.n_traj, dtype=torch.float64, device="cuda")
+    ctx.solve_masses(req, masses, out, ratio)
+    st, _ = ctx.last_stats()
+    assert st["n_failed"] == 0
+    prof = out.cpu().numpy().reshape(len(masses), req.n_r)
+    r = ratio.cpu().numpy()
+    p0, r0, _ = gpu_ratios(ctx, req)
+    assert np.array_equal(prof[0], p0) and np.array_equal(r, r0)
+    ref = O.solve_masses(req, masses)
+    for k, m in enumerate(masses):
+        rq = req.with_(m_eV=m, y=np.asarray(req.y) * (m / req.m_eV))
+        assert rel(prof[k], O.profile_from_ratio(rq, r)).max() <= 1e-13
+        e = rel(prof[k], ref[k]).max()
+        print(f"mass {m}: n/nbar {prof[k][:3]} max rel vs oracle {e:.2e}", flush=True)
+        if e > 1e-8:
+            assert e <= 4.0 * sensitivity(rq, ref[k])
+
+
+def test_masses_rejects_bad_input(ctx):
+    from paper_2410_08267_amd import nuhalo as N
+    req = W.shrink(W.plain_small(), 3, 5, 4).with_(method="dp5")
+    out = torch.empty(4 * req.n_r, dtype=torch.float64, device="cuda")
+    say("masses: invalid mass lists")
+    for bad in ([], [0.1, -0.2], [float("nan")]):
+        with pytest.raises((N.NhError, ValueError)):
+            ctx.solve_masses(req, bad, out)
+
+
+def test_fp64_fma_peak_is_plausible(ctx):
+    """The FMA probe measures the device's FP64 vector rate: MI355X's published
+    figure is 78.6 TFLOP/s (256 CUs x 128 FP64 FLOP per clock at 2.4 GHz)."""
+    say("fp64 fma peak probe")
+    t = ctx.fp64_fma_peak()
+    print(f"measured FP64 FMA {t:.1f} TFLOP/s", flush=True)
+    assert 30.0 < t < 1.1 * 78.6

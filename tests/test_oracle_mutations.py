@@ -27,13 +27,16 @@ MUTANTS = {
     "hubble_power": ("sqrt(m->Omega_m * opz * opz * opz + m->Omega_L)", "sqrt(m->Omega_m * opz * opz + m->Omega_L)"),
     "lagrangian_radius": ("double fac = 2.0 * nho_G() / (m->Omega_m * H0k * H0k);",
                           "double fac = 3.0 * nho_G() / (m->Omega_m * H0k * H0k);"),
-    "truncation_image": ("*rv = (*R / c200) * (1.0 + z);", "*rv = (*R / c200);"),
+    "truncation_image": ("*rv = (*R / c200) * ((1.0 + z) / (1.0 + m->z_obs));", "*rv = (*R / c200);"),
     "rk4_weight": ("(k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i])", "(k1[i] + 2.0 * k2[i] + k3[i] + 2.0 * k4[i])"),
     "rk4_stage_time": ("nho_rhs(m, u1, T, k3);", "nho_rhs(m, u0, T, k3);"),
     "dp_tableau": ("{44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0},", "{44.0 / 45.0, -56.0 / 15.0, 32.0 / 8.0, 0, 0, 0},"),
     "dp_weight": ("static const double DP_B[7] = {35.0 / 384.0,", "static const double DP_B[7] = {36.0 / 384.0,"),
     "dp_error_weight": ("-92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};", "-92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 30.0};"),
-    "mass_xi": ("double xi = (m->z_form - z) / m->z_form;", "double xi = (m->z_form - z) / (m->z_form + 1.0);"),
+    "mass_xi": ("double xi = (m->z_form - z) / (m->z_form - m->z_obs);",
+                "double xi = (m->z_form - z) / (m->z_form + 1.0 - m->z_obs);"),
+    "observed_truncation": ("*rv = (*R / c200) * ((1.0 + z) / (1.0 + m->z_obs));", "*rv = (*R / c200) * (1.0 + z);"),
+    "observed_radius": ("*R = cbrt(fac * nho_mass(m, m->z_obs));", "*R = cbrt(fac * nho_mass(m, 0.0));"),
     "conc_power": ("return m->c0 * pow(1.0 + z, -m->conc_gamma);", "return m->c0 * pow(1.0 + z, m->conc_gamma);"),
     "sampled_horner": ("return ((c[0] * t + c[1]) * t + c[2]) * t + c[3];",
                        "return ((c[0] * t + c[2]) * t + c[1]) * t + c[3];"),

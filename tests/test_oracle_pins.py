@@ -83,7 +83,7 @@ def _brute_deltaM(req, r, z):
 
     def Mz(zz):
         if req.mass_kind == "paper":
-            xi = min(max((req.z_form - zz) / req.z_form, 0.0), 1.0)
+            xi = min(max((req.z_form - zz) / (req.z_form - req.z_obs), 0.0), 1.0)
             return req.M0 * xi ** req.mass_alpha
         if req.mass_kind == "exponential":
             return req.M0 * math.exp(-req.mass_beta * zz)
@@ -91,10 +91,10 @@ def _brute_deltaM(req, r, z):
 
     c = req.c0 if req.conc_kind == "constant" else req.c0 * (1 + z) ** (-req.conc_gamma)
     if req.geometry == "paper":
-        Mh = Mz(0.0)
+        Mh = Mz(req.z_obs)                              # the halo as observed at z0
         xi = Mz(z) / Mh
         R = (3 * Mh / (4 * math.pi * rho_m0)) ** (1 / 3)
-        r200 = R / 200 ** (1 / 3)                      # physical, fixed
+        r200 = R / (200 ** (1 / 3) * (1 + req.z_obs))  # physical, fixed: R / (1 + z_i)
         shell = (1 - xi) * rhobar                       # rho_tot in the compensating shell
     else:
         Mh = Mz(z)
@@ -124,7 +124,8 @@ def _brute_deltaM(req, r, z):
     return val
 
 
-@pytest.mark.parametrize("kind", ["paper", "exponential", "delta200", "uncompensated", "alpha2"])
+@pytest.mark.parametrize("kind", ["paper", "exponential", "delta200", "uncompensated", "alpha2",
+                                  "paper_zobs", "exponential_zobs"])
 def test_deltaM_matches_density_integral(oracle_mod, kind):
     """P4: the closed-form enclosed mass equals the integral of Eq. (rhototal)."""
     O = oracle_mod
@@ -136,9 +137,15 @@ def test_deltaM_matches_density_integral(oracle_mod, kind):
         req = small_req(M0=5e13, c0=9.0)
     elif kind == "delta200":
         req = small_req(M0=5e13, c0=9.0, geometry="delta200")
+    elif kind == "paper_zobs":
+        req = paper_model_req(z_obs=0.5, z_form=(1.5 * 200 ** (1 / 3) - 1) * 0.999999)
+    elif kind == "exponential_zobs":
+        req = small_req(M0=5e13, c0=9.0, z_obs=0.5)
     else:
         req = paper_model_req(compensated=False)
-    for z in (0.0, 0.7, 2.0, 3.9):
+    for z in (0.0, 0.5, 0.7, 2.0, 3.9):
+        if z < req.z_obs:
+            continue
         R, rv = O.halo_radii(req, z)
         radii = np.concatenate([np.geomspace(1e-3 * rv, 0.999 * rv, 7),
                                 np.geomspace(1.001 * rv, 0.999 * R, 5), [1.2 * R, 3 * R]])
@@ -601,3 +608,66 @@ def test_sampled_f0_converges_to_fermi_dirac(oracle_mod):
     yq = np.geomspace(0.01, 100.0, 200)
     w = O.y_weights(yq)
     assert abs(math.fsum(w * O.f0_of(req, yq)) / math.fsum(w * O.f0("fermi_dirac", yq)) - 1.0) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Observation at z_obs > 0 (the paper's z0, Sec. II.B): the halo's reference
+# epoch moves to z0; (1 + z_i)/(1 + z0) = 200^(1/3); integration starts at z0.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cosmo", ["eds", "lambda"])
+def test_free_streaming_drift_from_z_obs(oracle_mod, cosmo):
+    """P2 from z_obs: x(z_end) = x0 - v0 [D(z_end) - D(z_obs)];
+    EdS: 2(sqrt(1+z_e) - sqrt(1+z_o))/H0, Lambda only: ((1+z_e)^2 - (1+z_o)^2)/(2 H0)."""
+    O = oracle_mod
+    Om, OL = {"eds": (1.0, 0.0), "lambda": (0.0, 1.0)}[cosmo]
+    z_o, z_e = 0.7, 3.0
+    req = small_req(mass_kind="zero", Omega_m=Om, Omega_L=OL, method="dp5", rtol=1e-10,
+                    z_obs=z_o, z_end=z_e)
+    H0k = req.H0 / 1000.0
+    if cosmo == "eds":
+        D = 2.0 * (math.sqrt(1 + z_e) - math.sqrt(1 + z_o)) / H0k
+    else:
+        D = ((1 + z_e) ** 2 - (1 + z_o) ** 2) / (2 * H0k)
+    tr = O.trajectories(req)
+    s0, s1 = tr["state0"], tr["state1"]
+    assert np.array_equal(s1[:, 2:], s0[:, 2:])
+    want = s0[:, :2] - s0[:, 2:] * D
+    assert np.abs(s1[:, :2] - want).max() <= 1e-9 * np.abs(s0[:, 2:]).max() * D
+
+
+def test_paper_halo_observed_at_z_obs(oracle_mod):
+    """With z0 > 0 the paper model is the z0 = 0 model moved to z0: M(z0) = M_h
+    and M(z_i) = 0 with 1 + z_i = (1 + z0) 200^(1/3); the truncation radius is
+    R / 200^(1/3) at z0 and R at z_i, where deltaM vanishes for every r; at z0,
+    deltaM(r200) = M_h (1 - 1/200)."""
+    O = oracle_mod
+    z0 = 1.0
+    zi = (1 + z0) * 200.0 ** (1.0 / 3.0) - 1
+    req = small_req(mass_kind="paper", M0=3e13, conc_kind="constant", c0=7.0, z_form=zi,
+                    z_obs=z0, z_end=zi, geometry="paper")
+    M, _, _ = O.histories(req, [z0, zi, 0.5 * (z0 + zi)])
+    assert abs(M[0] / 3e13 - 1) < 1e-15 and M[1] == 0.0 and abs(M[2] / 1.5e13 - 1) < 1e-14
+    R, rv = O.halo_radii(req, z0)
+    assert abs(rv * 200.0 ** (1.0 / 3.0) / R - 1) < 1e-14
+    R_i, rv_i = O.halo_radii(req, zi)
+    assert abs(rv_i / R - 1) < 1e-13 and R_i == R
+    assert abs(O.deltaM(req, rv * (1 - 1e-13), z0)[0] / (3e13 * (1 - 1 / 200.0)) - 1) < 1e-10
+    assert np.all(O.deltaM(req, np.geomspace(1.0, 2 * R, 50), zi) == 0.0)
+
+
+def test_solve_masses_equals_per_mass_solves(oracle_mod):
+    """Sec. II.D: the mass leaves the equations of motion.  Reusing one set of
+    trajectories for mass m (momenta y m / m_req on the same velocities) must give
+    the profile of a full solve of the request with that mass and that y grid."""
+    O = oracle_mod
+    req = paper_model_req(method="dp5", rtol=1e-11)
+    masses = [req.m_eV, 0.05, 0.3]
+    got = O.solve_masses(req, masses)
+    assert np.array_equal(got[0], O.solve(req)["n_over_nbar"])
+    for k, m in enumerate(masses[1:], 1):
+        rq = req.with_(m_eV=m, y=np.asarray(req.y) * (m / req.m_eV))
+        want = O.solve(rq)["n_over_nbar"]
+        assert np.abs(got[k] / want - 1).max() < 1e-8, (m, got[k], want)
+    # the density contrast grows with the mass (slower relics cluster more)
+    assert np.all(got[2] - 1 > got[0] - 1) and np.all(got[0] - 1 > got[1] - 1)
