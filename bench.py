@@ -37,12 +37,12 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # WRITE_SIZE (seeds 0 and 1), each scaled by what the counter reads for a plain
 # 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the sources and
 # build flags these hashes name; any change to them reports traffic as null.
-TRAFFIC_BYTES_PER_LAUNCH = 93592116
+TRAFFIC_BYTES_PER_LAUNCH = 93470389
 TRAFFIC_SOURCES = {
-    "kernels_f64.hip": "565d784da533bea0462efd53e0d7ee3a455e14e95a5c767f11420c8c75f2788d",
-    "nh_dp5.h": "25c2778fd6db8cf6f248f33be254c5f009357bb3983e01db98bc5782eb40254a",
-    "nh_device.h": "3323d5897aa888ad4f26bf235ed1e71a2deaa5501c63ec949c2f477631311a24",
-    "nh_internal.h": "0aca23be10b7948e506b6e674d212379305d975e194c13381940943b1beab691",
+    "kernels_f64.hip": "af43763ae35391a868b7cc936ee977ee02a769a9b79a6656f10ae1334e94fa0a",
+    "nh_dp5.h": "4e591e60107f94ed748b4dd2e65e970e1b58d70705a2a559ad9d4927ed021bce",
+    "nh_device.h": "c03f14d35678e60909a9122bea2fedb090e074094580d46608bd33fe64180ed7",
+    "nh_internal.h": "eddc42be0a7e6e00a95bb084416ea0a0c3d6b5765e61f0ac312d93c9ae534cf9",
     "../build.py": "02d0e50104314a81e52ea23b7739d80dc352af57069babf1308fd6cf5c118f35",
 }
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
