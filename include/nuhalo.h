@@ -248,18 +248,25 @@ enum {
                                   default [0]: 3073, or for the batched and serving forms as many
                                   as their LDS slots hold (a larger value is NH_EINVAL there) */
     NH_OPT_BLOCK_THREADS = 5,  /* Dormand-Prince threads per workgroup, a multiple of 64 in
-                                  [64, 1024], or 0 for the defaults [0]: 512 for nh_solve (one
-                                  table copy in LDS per workgroup; more lanes per profile
-                                  lengthen its tail) and for the FP32C kernels (their limit),
-                                  1024 for FP64 batches and serving (four waves per SIMD) */
+                                  [64, 1024], or 0 for the defaults [0]: what nh_autotune chose
+                                  for that form and precision, else 768 for FP64 nh_solve (three
+                                  waves per SIMD; more lanes per profile lengthen its tail),
+                                  512 for the FP32C kernels (their limit), 1024 for FP64
+                                  batches and serving (four waves per SIMD) */
     NH_OPT_BATCH_SLOTS   = 6,  /* batched and serving forms: request tables per workgroup in
-                                  LDS, 1 or 2, or 0 for the default [0]: 1 for FP64 (3073
+                                  LDS, 1 or 2, or 0 for the default [0]: what nh_autotune chose
+                                  for FP32C, else 2 for FP32C, and 1 for FP64 (3073
                                   nodes, the plain form's table; a workgroup drains before it
                                   changes request), 2 for FP32C (3073 FP32 nodes each; lanes
                                   keep integrating while the next table loads).  Two FP64
                                   tables hold at most 2044 (constant R) or 1703 nodes. */
-    NH_OPT_SLICE_US      = 7   /* serving: length of a time slice in microseconds, 200..1e6 [4000];
+    NH_OPT_SLICE_US      = 7,  /* serving: length of a time slice in microseconds, 200..1e6 [4000];
                                   requests are admitted and retired between slices */
+    NH_OPT_SERVE_GRAPH   = 8   /* serving: [1] run each slice (descriptor uploads, the slice
+                                  kernel, the read-back of its queue state) as a replay of a
+                                  HIP graph built once per session and table layout, with only
+                                  the kernel's arguments updated; 0 issues them one by one.
+                                  Taken when a serving session starts. */
 };
 int nh_set_option(nh_context *ctx, int option, double value);
 
@@ -347,6 +354,37 @@ int nh_poll(nh_context *ctx, uint64_t ticket, double *out, nh_stats *stats);
  * returns to the budget (once the next slice boundary has passed).  Polling it
  * afterwards returns NH_ECANCELED once.  NH_ENOTFOUND for an unknown ticket. */
 int nh_cancel(nh_context *ctx, uint64_t ticket);
+
+/* ---- autotuning -------------------------------------------------------- */
+
+/* Forms that nh_autotune tunes. */
+#define NH_FORM_PLAIN 0   /* nh_solve / nh_solve_async / nh_solve_masses (Dormand-Prince) */
+#define NH_FORM_BATCH 1   /* nh_solve_batch and the serving loop */
+
+typedef struct {
+    int    form;            /* NH_FORM_* */
+    int    precision;       /* NH_FP64 or NH_FP32C */
+    int    block_threads;   /* chosen threads per workgroup */
+    int    batch_slots;     /* chosen tables per workgroup (batched form), else 0 */
+    int    n_tried;         /* candidate configurations timed */
+    double best_ms;         /* trajectory-kernel time of the sample with the choice */
+    double default_ms;      /* the same with the built-in default */
+} nh_tune_result;
+
+/* Choose the launch configuration of one form and precision by timing it.
+ * Every candidate (workgroup sizes of one to four waves per SIMD; for FP32C
+ * batches also one or two tables per workgroup) solves the caller's sample
+ * after one untimed warm-up; the candidate with the least total trajectory-
+ * kernel time (best of two passes) becomes the context's default for that
+ * form and precision, used wherever NH_OPT_BLOCK_THREADS / NH_OPT_BATCH_SLOTS
+ * are 0.  Results never depend on the choice (every trajectory is integrated by
+ * the same arithmetic whichever lane runs it); only the time does.  The sample
+ * should resemble the later work but need not be part of it.
+ * reqs: host, n_req requests of one precision, all NH_DOPRI5; 1 <= n_req <= 65535
+ * (NH_FORM_PLAIN solves each one in turn, NH_FORM_BATCH them as one batch).
+ * result: may be NULL.  Waits for completion; the serving loop must be idle
+ * (NH_EBUSY otherwise).  Allocates device memory for the outputs while it runs. */
+int nh_autotune(nh_context *ctx, int form, int n_req, const nh_request *reqs, nh_tune_result *result);
 
 /* ---- host-side helpers (need no GPU) --------------------------------------- */
 

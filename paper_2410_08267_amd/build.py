@@ -23,6 +23,7 @@ SOURCES = [
     "host_api.cpp",
     "host_batch.cpp",
     "host_serve.cpp",
+    "host_tune.cpp",
     "kernels_f64.hip",
     "kernels_f32c.hip",
     "kernels_batch.hip",

@@ -247,7 +247,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
         const bool f32 = q->integ.precision == NH_FP32C;
         if (f32) P.h_fp64 = ctx->h_fp64;
         P.order = ctx->queue_order;
-        P.block = ctx->block_threads;
+        P.block = ctx->block_threads > 0 ? ctx->block_threads : ctx->tuned_plain_block[f32];
         if (f32) HIPCHK(launch_dp5_f32c(P, g, o, counter, ctx->n_cu, stream));
         else HIPCHK(launch_dp5_f64(P, g, o, counter, ctx->n_cu, stream));
     }
@@ -387,6 +387,10 @@ int nh_set_option(nh_context *ctx, int option, double value)
         if (value != 0.0 && value != 1.0 && value != 2.0)
             return set_err(ctx, NH_EINVAL, "batch slots is 0 (default), 1 or 2");
         ctx->batch_slots = (int)value;
+        return NH_OK;
+    case NH_OPT_SERVE_GRAPH:
+        if (value != 0.0 && value != 1.0) return set_err(ctx, NH_EINVAL, "serve graph is 0 or 1");
+        ctx->serve_graph = value != 0.0;
         return NH_OK;
     default:
         return set_err(ctx, NH_EINVAL, "unknown option %d", option);

@@ -27,12 +27,14 @@ int batch_block(const nh_context *ctx, bool f32c)
 {
     // FP64 slices fit four waves per SIMD (1024 threads); the FP32C lane state two
     const int cap = f32c ? 512 : 1024;
-    return ctx->block_threads > 0 ? std::min(ctx->block_threads, cap) : cap;
+    if (ctx->block_threads > 0) return std::min(ctx->block_threads, cap);
+    return ctx->tuned_batch_block[f32c] > 0 ? std::min(ctx->tuned_batch_block[f32c], cap) : cap;
 }
 
 int batch_slots(const nh_context *ctx, bool f32c)
 {
-    return ctx->batch_slots > 0 ? ctx->batch_slots : (f32c ? 2 : 1);
+    if (ctx->batch_slots > 0) return ctx->batch_slots;
+    return ctx->tuned_batch_slots[f32c] > 0 ? ctx->tuned_batch_slots[f32c] : (f32c ? 2 : 1);
 }
 
 int batch_table_nodes(nh_context *ctx, bool f32c, int nc, int slots, int *n_tab)

@@ -140,6 +140,8 @@ struct ServeState {
     WgSave *d_wg = nullptr;
     size_t lanes_cap = 0, wg_cap = 0;
     bool resume = false;
+    bool use_graph = true;            // slices as replays of a HIP graph (per table layout)
+    SliceGraph graph[2];              // [0] five columns, [1] six
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // pinned host mirrors; h_desc changes under `mu`, h_desc_up is the snapshot
@@ -218,6 +220,8 @@ int start_session(nh_context *ctx, ServeState &S, bool f32c)
     S.slice_ticks = (long long)((double)ctx->slice_us * rate_khz / 1000.0);
     S.resume = false;
     S.precision = f32c ? NH_FP32C : NH_FP64;
+    S.use_graph = ctx->serve_graph;
+    for (SliceGraph &G : S.graph) slice_graph_destroy(G);   // launch shape may have changed
     return NH_OK;
 }
 
@@ -298,11 +302,6 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
         S.h_order[i] = run[i]->slot;
         nc = std::max(nc, run[i]->desc.nc);
     }
-    WCHK(hipMemcpyAsync(S.d_desc, S.h_desc_up, SERVE_CAP * sizeof(BatchReq), hipMemcpyHostToDevice, s));
-    if (!run.empty())
-        WCHK(hipMemcpyAsync(S.d_order, S.h_order, run.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    WCHK(launch_fill_u64((unsigned long long *)S.d_inflight, SERVE_CAP / 2, 0ull, s));
-
     SliceArgs A{};
     A.reqs = S.d_desc;
     A.next = S.d_next;
@@ -316,12 +315,42 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
     A.lane_save = S.d_lanes;
     A.wg_save = S.d_wg;
     A.resume = S.resume ? 1 : 0;
-    WCHK(hipEventRecord(S.ev0, s));
-    WCHK(launch_slice(A, S.precision == NH_FP32C, nc, S.slots, S.grid, S.block, s));
-    WCHK(hipEventRecord(S.ev1, s));
+    const bool f32c = S.precision == NH_FP32C;
+    if (S.use_graph) {
+        // uploads, in-flight clear, slice kernel and read-backs as one graph launch
+        SliceGraph &G = S.graph[nc == NCOL ? 1 : 0];
+        if (!G.exec) {
+            SliceGraphBufs b{};
+            b.d_desc = S.d_desc;
+            b.d_order = S.d_order;
+            b.d_next = S.d_next;
+            b.d_inflight = S.d_inflight;
+            b.h_desc = S.h_desc_up;
+            b.h_order = S.h_order;
+            b.h_next = S.h_next;
+            b.h_inflight = S.h_inflight;
+            b.desc_bytes = SERVE_CAP * sizeof(BatchReq);
+            b.order_bytes = SERVE_CAP * sizeof(int);
+            b.next_bytes = SERVE_CAP * sizeof(unsigned long long);
+            b.inflight_bytes = SERVE_CAP * sizeof(unsigned int);
+            WCHK(slice_graph_build(G, b, A, f32c, nc, S.slots, S.grid, S.block));
+        }
+        WCHK(hipEventRecord(S.ev0, s));
+        WCHK(slice_graph_launch(G, A, s));
+        WCHK(hipEventRecord(S.ev1, s));
+    } else {
+        WCHK(hipMemcpyAsync(S.d_desc, S.h_desc_up, SERVE_CAP * sizeof(BatchReq), hipMemcpyHostToDevice, s));
+        if (!run.empty())
+            WCHK(hipMemcpyAsync(S.d_order, S.h_order, run.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        WCHK(launch_fill_u64((unsigned long long *)S.d_inflight, SERVE_CAP / 2, 0ull, s));
+        WCHK(hipEventRecord(S.ev0, s));
+        WCHK(launch_slice(A, f32c, nc, S.slots, S.grid, S.block, s));
+        WCHK(hipEventRecord(S.ev1, s));
+        WCHK(hipMemcpyAsync(S.h_next, S.d_next, SERVE_CAP * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        WCHK(hipMemcpyAsync(S.h_inflight, S.d_inflight, SERVE_CAP * sizeof(unsigned int), hipMemcpyDeviceToHost,
+                            s));
+    }
     S.resume = true;
-    WCHK(hipMemcpyAsync(S.h_next, S.d_next, SERVE_CAP * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    WCHK(hipMemcpyAsync(S.h_inflight, S.d_inflight, SERVE_CAP * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     WCHK(hipStreamSynchronize(s));
     float ms = 0.f;
     WCHK(hipEventElapsedTime(&ms, S.ev0, S.ev1));
@@ -425,6 +454,14 @@ ServeState *state_of(nh_context *ctx)
 
 }  // namespace
 
+bool serve_idle(nh_context *ctx)
+{
+    ServeState *S = ctx->serve;
+    if (!S) return true;
+    std::lock_guard<std::mutex> lk(S->mu);
+    return S->active.empty() && S->queued.empty();
+}
+
 void serve_shutdown(nh_context *ctx)
 {
     ServeState *S = ctx->serve;
@@ -436,6 +473,7 @@ void serve_shutdown(nh_context *ctx)
     S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();
     if (S->stream) (void)hipStreamSynchronize(S->stream);
+    for (SliceGraph &G : S->graph) slice_graph_destroy(G);
     for (void *p : {(void *)S->d_desc, (void *)S->d_next, (void *)S->d_inflight, (void *)S->d_stats,
                     (void *)S->d_order, (void *)S->d_list, (void *)S->d_rstart, (void *)S->d_lanes,
                     (void *)S->d_wg, (void *)S->arena_base})

@@ -9,6 +9,7 @@
 
 #include "nh_batch.h"
 #include "nh_dp5_f32.h"
+#include "nh_launch.h"
 #include "nh_reduce.h"
 
 namespace nh {
@@ -485,6 +486,79 @@ hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, int gr
     const size_t lds = slice_lds_bytes(f32c, nc, slots, A.n_tab);
     void *args[] = {(void *)&A};
     return hipLaunchKernel(slice_fn(f32c, nc, slots), dim3(grid), dim3(block), args, lds, s);
+}
+
+// One serving slice as a graph: upload the descriptors and the run order,
+// clear the in-flight counts (a kernel, not a memset node), run the slice
+// kernel, bring back the queue positions and in-flight counts.  The slice
+// kernel's arguments change every slice and are set on the instantiated graph
+// before each launch (slice_graph_launch).
+hipError_t slice_graph_build(SliceGraph &G, const SliceGraphBufs &b, const SliceArgs &A, bool f32c, int nc,
+                             int slots, int grid, int block)
+{
+    slice_graph_destroy(G);
+    hipError_t e = hipGraphCreate(&G.graph, 0);
+    if (e != hipSuccess) return e;
+    hipGraphNode_t up_desc, up_order, clear, back_next, back_inflight;
+    if ((e = hipGraphAddMemcpyNode1D(&up_desc, G.graph, nullptr, 0, b.d_desc, b.h_desc, b.desc_bytes,
+                                     hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if ((e = hipGraphAddMemcpyNode1D(&up_order, G.graph, nullptr, 0, b.d_order, b.h_order, b.order_bytes,
+                                     hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    unsigned long long *p = (unsigned long long *)b.d_inflight;
+    int n = (int)(b.inflight_bytes / sizeof(unsigned long long));
+    unsigned long long zero = 0ull;
+    void *fill_args[] = {(void *)&p, (void *)&n, (void *)&zero};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(fill_u64_kernel());
+    kp.gridDim = dim3((unsigned)((n + 255) / 256));
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = fill_args;
+    if ((e = hipGraphAddKernelNode(&clear, G.graph, nullptr, 0, &kp)) != hipSuccess) return e;
+    G.args = A;
+    G.params = hipKernelNodeParams{};
+    G.params.func = const_cast<void *>(slice_fn(f32c, nc, slots));
+    G.params.gridDim = dim3(grid);
+    G.params.blockDim = dim3(block);
+    G.params.sharedMemBytes = (unsigned)slice_lds_bytes(f32c, nc, slots, A.n_tab);
+    G.arg_ptr[0] = (void *)&G.args;
+    G.params.kernelParams = G.arg_ptr;
+    hipGraphNode_t deps[3] = {up_desc, up_order, clear};
+    if ((e = hipGraphAddKernelNode(&G.slice, G.graph, deps, 3, &G.params)) != hipSuccess) return e;
+    if ((e = hipGraphAddMemcpyNode1D(&back_next, G.graph, &G.slice, 1, b.h_next, b.d_next, b.next_bytes,
+                                     hipMemcpyDeviceToHost)) != hipSuccess)
+        return e;
+    if ((e = hipGraphAddMemcpyNode1D(&back_inflight, G.graph, &G.slice, 1, b.h_inflight, b.d_inflight,
+                                     b.inflight_bytes, hipMemcpyDeviceToHost)) != hipSuccess)
+        return e;
+    if ((e = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0)) != hipSuccess) return e;
+    G.f32c = f32c;
+    G.nc = nc;
+    G.slots = slots;
+    G.grid = grid;
+    G.block = block;
+    return hipSuccess;
+}
+
+hipError_t slice_graph_launch(SliceGraph &G, const SliceArgs &A, hipStream_t s)
+{
+    G.args = A;
+    G.params.kernelParams = G.arg_ptr;
+    hipError_t e = hipGraphExecKernelNodeSetParams(G.exec, G.slice, &G.params);
+    if (e != hipSuccess) return e;
+    return hipGraphLaunch(G.exec, s);
+}
+
+void slice_graph_destroy(SliceGraph &G)
+{
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    if (G.graph) (void)hipGraphDestroy(G.graph);
+    G.exec = nullptr;
+    G.graph = nullptr;
+    G.slice = nullptr;
+    G.nc = 0;
 }
 
 hipError_t launch_reduce_batch(const BatchReq *reqs, const int *list, const int *rstart, int n_list,

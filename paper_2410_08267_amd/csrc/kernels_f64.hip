@@ -104,11 +104,12 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
 
 // One block per CU: the table takes most of the LDS.  The kernel fits 128
 // VGPRs, so blocks of up to 1024 threads (four waves per SIMD) are possible;
-// 512 is the default: a single profile has ~1e6 trajectories, and more lanes
-// per profile lengthen the tail where the last long trajectories run alone.
+// 768 (three waves per SIMD) is the default: a single profile has ~1e6
+// trajectories, and more lanes per profile lengthen the tail where the last
+// long trajectories run alone.  The autotuner picks per workload.
 template <int NC>
 constexpr int dp5_block() { return 1024; }
-constexpr int DP5_DEFAULT_BLOCK = 512;
+constexpr int DP5_DEFAULT_BLOCK = 768;
 
 // CULL: some start radius lies beyond R_exit.  Without one no relic can be
 // culled, and the kernel leaves the test out: its branch alone costs the
@@ -214,6 +215,8 @@ __global__ __launch_bounds__(256) void k_reduce_stats(long long n, TrajOut o,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+const void *fill_u64_kernel() { return (const void *)k_fill_u64; }
 
 hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s)
 {

@@ -49,7 +49,12 @@ struct nh_context {
     int table_nodes = 0;                             // 0: default_table_nodes()
     int block_threads = 0;                           // Dormand-Prince workgroup size (0: default)
     int batch_slots = 0;                             // tables per workgroup, batched form (0: default)
+    // nh_autotune's choices per precision [FP64, FP32C] (0: built-in default)
+    int tuned_plain_block[2] = {0, 0};
+    int tuned_batch_block[2] = {0, 0};
+    int tuned_batch_slots[2] = {0, 0};
     double slice_us = 4000.0;                        // serving: time slice length
+    bool serve_graph = true;                         // serving: slices as HIP graph replays
     nh::ServeState *serve = nullptr;
 };
 
@@ -64,6 +69,7 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P,
 GridPtrs grid_ptrs(const Staged &s, const char *dev);
 size_t per_traj_bytes(const nh_request *q);
 void serve_shutdown(nh_context *ctx);
+bool serve_idle(nh_context *ctx);
 int wait_pending(nh_context *ctx);
 int request_columns(const nh_request *q);
 int batch_slots(const nh_context *ctx, bool f32c);

@@ -10,55 +10,26 @@
 namespace nh {
 
 // ---------------------------------------------------------------------------
-// FP64 elementary functions.  The hardware rcp/rsq give a ~26-bit first guess;
-// two Newton steps bring it to within an ulp or so.  No special-case handling:
+// FP64 elementary functions.  The hardware rcp/rsq give a first guess good to
+// ~2^-26; one third-order correction (the series of (1 - e)^-1 or
+// (1 - e)^-1/2 to e^2, error O(e^3) ~ 1e-23) brings it to within an ulp or so
+// with a dependency chain of three operations.  No special-case handling:
 // callers only pass positive finite arguments (r = 0 is masked by the caller).
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double rcp64(double a)
 {
-    double r = __builtin_amdgcn_rcp(a);
-    double e = fma(-a, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-a, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(a);
+    const double e = fma(-a, r, 1.0);             // 1/a = r / (1 - e)
+    return fma(r, fma(e, e, e), r);               // r (1 + e + e^2)
 }
 
 __device__ __forceinline__ double rsq64(double a)
 {
-    double y = __builtin_amdgcn_rsq(a);
-    double e = fma(-a * y, y, 1.0);     // 1 - a y^2
-    y = fma(0.5 * y, e, y);
-    e = fma(-a * y, y, 1.0);
-    return fma(0.5 * y, e, y);
-}
-
-// ln(w) for positive finite w: w = m 2^e with m in [sqrt(1/2), sqrt(2)), and
-// ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^21/21), s = (m-1)/(m+1), |s| <= 0.1716.
-__device__ __forceinline__ double log_pos(double w)
-{
-    int e = __builtin_amdgcn_frexp_exp(w);
-    double m = __builtin_amdgcn_frexp_mant(w);        // [0.5, 1)
-    if (m < 0.70710678118654752) {
-        m *= 2.0;
-        e -= 1;
-    }
-    const double s = (m - 1.0) * rcp64(m + 1.0);
-    const double s2 = s * s;
-    double p = 1.0 / 21.0;
-    p = fma(p, s2, 1.0 / 19.0);
-    p = fma(p, s2, 1.0 / 17.0);
-    p = fma(p, s2, 1.0 / 15.0);
-    p = fma(p, s2, 1.0 / 13.0);
-    p = fma(p, s2, 1.0 / 11.0);
-    p = fma(p, s2, 1.0 / 9.0);
-    p = fma(p, s2, 1.0 / 7.0);
-    p = fma(p, s2, 1.0 / 5.0);
-    p = fma(p, s2, 1.0 / 3.0);
-    const double ts = 2.0 * s;
-    const double lm = fma(ts * s2, p, ts);
-    const double de = (double)e;
-    return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, lm));
+    const double y = __builtin_amdgcn_rsq(a);
+    const double e = fma(-a * y, y, 1.0);         // a^-1/2 = y (1 - e)^-1/2
+    const double c = e * fma(e, 0.375, 0.5);      // e/2 + 3 e^2/8
+    return fma(y, c, y);
 }
 
 // NFW mass integral I(q) = ln(1+q) - q/(1+q) (Eq. nfw), branch-free for q >= 0.
@@ -81,47 +52,27 @@ __device__ __forceinline__ double nfw_I(double q)
     e = lowm ? e - 1 : e;
     const bool small = (e == 0);
     const double s = (small ? q : m - 1.0) * rcp64(small ? 2.0 + q : m + 1.0);
+    // 1/(1+s) = (2+q) / (2 (1+q)) when s = q/(2+q): both branches need only
+    // 1/(1+q), which does not wait for s
+    const double iw = rcp64(w0);
     const double s2 = s * s;
-    double p = 1.0 / 21.0;
-    p = fma(p, s2, 1.0 / 19.0);
-    p = fma(p, s2, 1.0 / 17.0);
-    p = fma(p, s2, 1.0 / 15.0);
-    p = fma(p, s2, 1.0 / 13.0);
-    p = fma(p, s2, 1.0 / 11.0);
-    p = fma(p, s2, 1.0 / 9.0);
-    p = fma(p, s2, 1.0 / 7.0);
-    p = fma(p, s2, 1.0 / 5.0);
-    p = fma(p, s2, 1.0 / 3.0);
+    // s^-3 (atanh(s) - s) = sum_{k=0..9} s2^k / (2k+3): even and odd powers
+    // of s2 as two interleaved Horner chains in s2^2
+    const double z2 = s2 * s2;
+    double pe = fma(z2, 1.0 / 19.0, 1.0 / 15.0), po = fma(z2, 1.0 / 21.0, 1.0 / 17.0);
+    pe = fma(z2, pe, 1.0 / 11.0);
+    po = fma(z2, po, 1.0 / 13.0);
+    pe = fma(z2, pe, 1.0 / 7.0);
+    po = fma(z2, po, 1.0 / 9.0);
+    pe = fma(z2, pe, 1.0 / 3.0);
+    po = fma(z2, po, 1.0 / 5.0);
+    const double p = fma(s2, po, pe);
     const double t3 = 2.0 * s * s2 * p;                  // 2 (atanh(s) - s)
-    const double inv = rcp64(small ? 1.0 + s : w0);
+    const double inv = small ? (0.5 * (2.0 + q)) * iw : iw;
     const double de = (double)e;
     const double big = fma(de, 6.93147180369123816490e-01,
                            fma(de, 1.90821492927058770002e-10, fma(-q, inv, 2.0 * s)));
     return (small ? 2.0 * s2 * inv : big) + t3;
-}
-
-// e^x for |x| < 700: x = k ln2 + r, |r| <= ln2/2, e^r by its Taylor series to r^13/13!
-// (next term < 4e-18), then scaled by 2^k.
-__device__ __forceinline__ double exp64(double x)
-{
-    const double k = rint(x * 1.4426950408889634);
-    double r = fma(-k, 6.93147180369123816490e-01, x);
-    r = fma(-k, 1.90821492927058770002e-10, r);
-    double p = 1.0 / 6227020800.0;                 // 1/13!
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    return __builtin_amdgcn_ldexp(p, (int)k);
 }
 
 // |v|^2 with a fixed operation order (the final and initial speeds must round
@@ -280,13 +231,23 @@ __device__ __forceinline__ long long wave_claim(bool need, unsigned long long *c
 }
 
 // Step-size factor of the controller, min(fmax, max(0.2, 0.9 err^(-1/5))),
-// from err^2 in FP64: adaptive step sequences are discontinuous in the
-// accept/reject decisions, so the factor is kept as exact as the rest.
+// from err^2, as exact as the rest of the FP64 step: adaptive step sequences
+// are discontinuous in the accept/reject decisions.  y = err2^(-1/10) starts
+// from the FP32 hardware log2/exp2 (relative error ~1e-6) and takes two Newton
+// steps y <- y + y (1 - err2 y^10) / 10 (each squares the error, times 5.5).
+// Outside [1e-8, 1e7] the clamps decide: 0.9 y > 5.6 below, < 0.18 above.
 __device__ __forceinline__ double step_factor(double err2, double fcap)
 {
-    if (err2 == 0.0) return fcap;
-    const double f = 0.9 * exp64(-0.1 * log_pos(err2));
-    return fmin(fcap, fmax(0.2, f));
+    if (err2 < 1.0e-8) return fcap;
+    if (err2 > 1.0e7) return 0.2;
+    const float l2 = __builtin_amdgcn_logf((float)err2);
+    double y = (double)__builtin_amdgcn_exp2f(-0.1f * l2);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double y2 = y * y, y4 = y2 * y2, y10 = y4 * y4 * y2;
+        y = fma(0.1 * y, fma(-err2, y10, 1.0), y);
+    }
+    return fmin(fcap, fmax(0.2, 0.9 * y));
 }
 
 }  // namespace nh

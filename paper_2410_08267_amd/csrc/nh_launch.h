@@ -31,6 +31,31 @@ size_t slice_lds_bytes(bool f32c, int nc, int slots, int n_tab);
 int slice_max_table_nodes(bool f32c, int nc, int slots);
 hipError_t slice_capacity(bool f32c, int nc, int slots, int n_tab, int block, int n_cu, int *grid);
 hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, int grid, int block, hipStream_t s);
+const void *fill_u64_kernel();
+
+// A serving slice captured as a HIP graph (descriptor and order uploads, the
+// in-flight clear, the slice kernel, the read-back of queue positions and
+// in-flight counts), re-launched every slice with new kernel arguments.
+struct SliceGraphBufs {
+    void *d_desc, *d_order, *d_next, *d_inflight;          // device
+    const void *h_desc, *h_order;                          // pinned host sources
+    void *h_next, *h_inflight;                             // pinned host destinations
+    size_t desc_bytes, order_bytes, next_bytes, inflight_bytes;
+};
+struct SliceGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t slice = nullptr;
+    hipKernelNodeParams params{};
+    SliceArgs args{};
+    void *arg_ptr[1] = {nullptr};
+    bool f32c = false;
+    int nc = 0, slots = 0, grid = 0, block = 0;
+};
+hipError_t slice_graph_build(SliceGraph &G, const SliceGraphBufs &b, const SliceArgs &A, bool f32c, int nc,
+                             int slots, int grid, int block);
+hipError_t slice_graph_launch(SliceGraph &G, const SliceArgs &A, hipStream_t s);
+void slice_graph_destroy(SliceGraph &G);
 // profiles of the listed requests (n_blocks = their total radii; rstart[i] = first
 // radius block of list[i]) and their statistics, 8 words per listed request
 hipError_t launch_reduce_batch(const BatchReq *reqs, const int *list, const int *rstart, int n_list,

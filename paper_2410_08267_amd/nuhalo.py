@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libnuhalo.so")
 NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ESTEPS = 0, -1, -2, -3, -4
 NH_ENONFINITE, NH_EBUSY, NH_ENOTREADY, NH_ENOTFOUND, NH_ECANCELED = -5, -6, -7, -8, -9
 OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4, "block_threads": 5,
-           "batch_slots": 6, "slice_us": 7}
+           "batch_slots": 6, "slice_us": 7, "serve_graph": 8}
 
 _MASS = {"zero": 0, "paper": 1, "exponential": 2, "table": 3}
 _CONC = {"constant": 0, "power": 1, "table": 2}
@@ -95,6 +95,18 @@ class nh_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+NH_FORM_PLAIN, NH_FORM_BATCH = 0, 1
+
+
+class nh_tune_result(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int), ("precision", ctypes.c_int), ("block_threads", ctypes.c_int),
+                ("batch_slots", ctypes.c_int), ("n_tried", ctypes.c_int), ("best_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # Every symbol the header declares, with its ctypes signature.
 _SIGNATURES = {
     "nh_context_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
@@ -117,6 +129,8 @@ _SIGNATURES = {
     "nh_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "nh_version": (ctypes.c_char_p, []),
     "nh_fp64_fma_peak": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "nh_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nh_request),
+                                   ctypes.POINTER(nh_tune_result)]),
     "nh_solve_masses": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_request), ctypes.c_int, _dp,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nh_gauss_legendre": (ctypes.c_int, [ctypes.c_int, _dp, _dp]),
@@ -365,6 +379,16 @@ class Context:
         t = ctypes.c_double()
         self._check(self._lib.nh_fp64_fma_peak(self.h, ctypes.byref(t)))
         return t.value
+
+    def autotune(self, reqs, form: str = "plain") -> dict:
+        """Time the launch configurations of one form on a sample of requests and
+        make the fastest the context's default (nh_autotune); returns the choice."""
+        ms = [marshal(r) for r in reqs]
+        arr = (nh_request * len(ms))(*[m.q for m in ms])
+        res = nh_tune_result()
+        f = {"plain": NH_FORM_PLAIN, "batch": NH_FORM_BATCH}[form]
+        self._check(self._lib.nh_autotune(self.h, f, len(ms), arr, ctypes.byref(res)))
+        return res.as_dict()
 
     def solve_batch(self, reqs, out: "torch.Tensor", stream=None):
         """Solve several requests in one persistent launch; out (float64 device tensor)

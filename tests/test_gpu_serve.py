@@ -52,12 +52,17 @@ def small(seed, n, prec="fp64"):
     return [W.shrink(r, 5 + i % 3, 10 + i % 5, 6 + i % 2) for i, r in enumerate(reqs)]
 
 
+@pytest.mark.parametrize("graph", [1, 0])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_served_equals_plain_bitwise_across_slices(ctx, prec):
-    """Short slices (200 us): most trajectories are saved and resumed many times."""
+def test_served_equals_plain_bitwise_across_slices(ctx, prec, graph):
+    """Short slices (200 us): most trajectories are saved and resumed many times,
+    each slice a replay of the session's HIP graph (graph=1, the default, with
+    the host's uploads and synchronisations between replays) or separate
+    launches (graph=0)."""
     reqs = small(41, 10, prec)
-    say(f"serve {prec} x{len(reqs)} slice 200 us")
+    say(f"serve {prec} x{len(reqs)} slice 200 us graph {graph}")
     ctx.set_option("slice_us", 200)
+    ctx.set_option("serve_graph", graph)
     tickets = [ctx.submit(r) for r in reqs]
     assert all(t is not None for t in tickets)
     res = [wait(ctx, t, r.n_r) for t, r in zip(tickets, reqs)]
