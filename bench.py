@@ -95,7 +95,7 @@ def cpu_baseline(budget_s: float):
     }
 
 
-def batched_leg(ctx, n_req: int):
+def batched_leg(ctx, n_req: int, tuned=None):
     """The batched workload (n_req heterogeneous requests, one persistent launch
     each) in FP64 and in the FP32-compensated form: profiles/s of whole batches."""
     import torch
@@ -104,6 +104,8 @@ def batched_leg(ctx, n_req: int):
            "workload": ("batched: M0 log-uniform 1e11-1e15 Msun, c0 U[4,15], m U[0.02,0.3] eV, "
                         "N_r U{16..128} x N_y U{32..256} x N_mu U{16..64}, Dormand-Prince rtol 1e-8, z 0->4")}
     for prec in ("fp64", "fp32c"):
+        if tuned is not None:
+            tuned[f"batch_{prec}"] = tune(ctx, "batch", W.batched(998, n_req=48, prec=prec))
         warm = W.batched(999, n_req=16, prec=prec)
         reqs = W.batched(0, n_req=n_req, prec=prec)
         n_traj = sum(r.n_traj for r in reqs)
@@ -181,10 +183,23 @@ def serving_leg(ctx, capacity: float, prec: str, n_req: int, loads=(0.5, 0.9), w
     return out
 
 
-def plain_leg(ctx, stream, reqs, warmup):
+def tune(ctx, form: str, reqs):
+    """nh_autotune on a sample disjoint from the timed work (untimed)."""
+    t0 = time.perf_counter()
+    res = ctx.autotune(reqs, form)
+    res["seconds"] = time.perf_counter() - t0
+    print(f"[bench] autotune {form} {'fp32c' if res['precision'] else 'fp64'}: block {res['block_threads']} "
+          f"slots {res['batch_slots']} ({res['best_ms']:.1f} ms vs default {res['default_ms']:.1f} ms)",
+          file=sys.stderr, flush=True)
+    return res
+
+
+def plain_leg(ctx, stream, reqs, warmup, tuned=None):
     """The headline: one FP64 profile of the plain-at-scale workload per step."""
     import torch
     from paper_2410_08267_amd import workloads as W
+    if tuned is not None:
+        tuned["plain_fp64"] = tune(ctx, "plain", [W.plain_scale(s) for s in (2000, 2001, 2002)])
     out = torch.empty(128, dtype=torch.float64, device="cuda")
     for i in range(warmup):
         ctx.solve_async(W.plain_scale(1000 + i), out, stream=stream)
@@ -224,7 +239,7 @@ def plain_leg(ctx, stream, reqs, warmup):
     }
 
 
-def fp32c_leg(ctx, stream, reqs):
+def fp32c_leg(ctx, stream, reqs, tuned=None):
     """The FP32-compensated form on the same halos: profiles/s and deviation from FP64."""
     import numpy as np
     import torch
@@ -236,20 +251,23 @@ def fp32c_leg(ctx, stream, reqs):
         ctx.last_stats()
         prof64.append(out[:r.n_r].cpu().numpy().copy())
     reqs32 = [r.with_(precision="fp32c") for r in reqs]
+    if tuned is not None:
+        tuned["plain_fp32c"] = tune(ctx, "plain", [W.plain_scale(s).with_(precision="fp32c")
+                                                   for s in (2000, 2001, 2002)])
+    outs = [torch.empty(r.n_r, dtype=torch.float64, device="cuda") for r in reqs32]
     ctx.solve_async(W.plain_scale(1000).with_(precision="fp32c"), out, stream=stream)
     ctx.last_stats()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     acc32 = f64 = 0
-    errs = []
-    for r, p64 in zip(reqs32, prof64):
-        ctx.solve_async(r, out, stream=stream)
+    for r, o in zip(reqs32, outs):
+        ctx.solve_async(r, o, stream=stream)
         st, _ = ctx.last_stats()
         acc32 += st["accepted_steps"]
         f64 += st["fp64_steps"]
-        errs.append(float(np.max(np.abs(out[:r.n_r].cpu().numpy() / p64 - 1.0))))
     torch.cuda.synchronize()
     dt32 = time.perf_counter() - t1
+    errs = [float(np.max(np.abs(o.cpu().numpy() / p64 - 1.0))) for o, p64 in zip(outs, prof64)]
     return {
         "trajectory_steps_per_s": acc32 / dt32,
         "profiles_per_s": len(reqs32) / dt32,
@@ -277,6 +295,8 @@ def main():
     ap.add_argument("--no-serving", dest="serving", action="store_false",
                     help="skip the serving leg (Poisson arrivals, p50/p99 latency)")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip nh_autotune (untimed, on samples disjoint from the timed work)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (counter calibration)")
     args = ap.parse_args()
@@ -333,15 +353,16 @@ def main():
             "precision": "fp64",
         },
     }
+    tuned = {} if args.tune else None
     if plain:
-        line.update(plain_leg(ctx, stream, reqs, args.warmup))
+        line.update(plain_leg(ctx, stream, reqs, args.warmup, tuned))
         measured = ctx.fp64_fma_peak()
         line["roofline"]["peak_measured"] = measured
         line["roofline"]["frac_of_measured_peak"] = line["roofline"]["achieved"] / measured
     if args.fp32c:
-        line["fp32c"] = fp32c_leg(ctx, stream, reqs)
+        line["fp32c"] = fp32c_leg(ctx, stream, reqs, tuned)
     if args.batched:
-        line["batched"] = batched_leg(ctx, args.batch_requests)
+        line["batched"] = batched_leg(ctx, args.batch_requests, tuned)
     if args.serving and args.batched:
         serving = {}
         for pr in ("fp32c", "fp64"):
@@ -349,6 +370,8 @@ def main():
             serving[pr] = serving_leg(ctx, cap, pr, args.serve_requests)
             serving[pr]["capacity_profiles_per_s"] = cap
         line["serving"] = serving
+    if tuned:
+        line["tuned"] = tuned
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     ctx.close()

@@ -33,28 +33,28 @@ __device__ __forceinline__ double rsq64(double a)
 }
 
 // NFW mass integral I(q) = ln(1+q) - q/(1+q) (Eq. nfw), branch-free for q >= 0.
-// ln(1+q) = e ln2 + 2 atanh(s) with 1+q = m 2^e, m in [sqrt(1/2), sqrt(2)),
-// s = (m-1)/(m+1).  When e = 0 (q < sqrt(2) - 1), s = q/(2+q) is formed from q
-// itself and q/(1+q) = 2s/(1+s), so
-//   I = 2 s^2/(1+s) + 2 (atanh(s) - s),                 (all terms positive)
+// 1+q = m 2^e with e = round(log2(1+q)) (the exponent of (1+q) sqrt(2), so m
+// lies in [sqrt(1/2), sqrt(2)) up to rounding), ln(1+q) = e ln2 + 2 atanh(s),
+// s = (m-1)/(m+1).  m - 1 is corrected by the exact rounding error of 1+q, so
+// that s = q/(2+q) when e = 0.  Then q/(1+q) = 2s/(1+s) and
+//   I = 2 s^2/(1+s) + 2 (atanh(s) - s)                  (e = 0, all terms positive)
 // otherwise
 //   I = e ln2 + 2s - q/(1+q) + 2 (atanh(s) - s),
-// with atanh(s) - s = s^3/3 + s^5/5 + ... + s^21/21 (|s| <= 0.1716).  Relative
-// error a few ulp for every q; the two forms differ only through selects, so a
-// wavefront whose lanes straddle the switch does not diverge.
+// with atanh(s) - s = s^3/3 + s^5/5 + ... + s^21/21 (|s| <= 0.1716).  One
+// reciprocal serves both divisions: 1/((m+1)(1+q)).  Relative error a few ulp
+// (up to ~20 near q = 0.5, where ln(1+q) and q/(1+q) cancel); the two forms
+// differ only through selects, so a wavefront whose lanes straddle the switch
+// does not diverge.
 __device__ __forceinline__ double nfw_I(double q)
 {
     const double w0 = 1.0 + q;
-    int e = __builtin_amdgcn_frexp_exp(w0);
-    double m = __builtin_amdgcn_frexp_mant(w0);        // [0.5, 1)
-    const bool lowm = m < 0.70710678118654752;
-    m = lowm ? 2.0 * m : m;
-    e = lowm ? e - 1 : e;
-    const bool small = (e == 0);
-    const double s = (small ? q : m - 1.0) * rcp64(small ? 2.0 + q : m + 1.0);
-    // 1/(1+s) = (2+q) / (2 (1+q)) when s = q/(2+q): both branches need only
-    // 1/(1+q), which does not wait for s
-    const double iw = rcp64(w0);
+    const int e = __builtin_amdgcn_frexp_exp(w0 * 1.4142135623730951) - 1;
+    const double m = __builtin_amdgcn_ldexp(w0, -e);
+    const double num = (m - 1.0) + __builtin_amdgcn_ldexp(q - (w0 - 1.0), -e);
+    const double den = m + 1.0;
+    const double rp = rcp64(den * w0);
+    const double s = num * (w0 * rp);                    // (m-1)/(m+1)
+    const double iw = den * rp;                          // 1/(1+q)
     const double s2 = s * s;
     // s^-3 (atanh(s) - s) = sum_{k=0..9} s2^k / (2k+3): even and odd powers
     // of s2 as two interleaved Horner chains in s2^2
@@ -68,7 +68,9 @@ __device__ __forceinline__ double nfw_I(double q)
     po = fma(z2, po, 1.0 / 5.0);
     const double p = fma(s2, po, pe);
     const double t3 = 2.0 * s * s2 * p;                  // 2 (atanh(s) - s)
-    const double inv = small ? (0.5 * (2.0 + q)) * iw : iw;
+    const bool small = (e == 0);
+    // e = 0: m = 1+q, so 1/(1+s) = (m+1)/(2m) = (1 + 1/(1+q))/2
+    const double inv = small ? fma(0.5, iw, 0.5) : iw;
     const double de = (double)e;
     const double big = fma(de, 6.93147180369123816490e-01,
                            fma(de, 1.90821492927058770002e-10, fma(-q, inv, 2.0 * s)));

@@ -128,7 +128,8 @@ __device__ __forceinline__ int dp5_attempt(Lane64 &L, const CF &cf, const DpCtl 
     // sc = atol + rtol max(|.|_n, |.|_{n+1}); max of the norms = sqrt of the max of the squares
     const double sx = ctl.atol_x + ctl.rtol * sqrt(fmax(x * x + y * y, x5 * x5 + y5 * y5));
     const double sv = ctl.atol_v + ctl.rtol * sqrt(fmax(vx * vx + vy * vy, vx5 * vx5 + vy5 * vy5));
-    const double isx = rcp64(sx), isv = rcp64(sv);
+    const double rp = rcp64(sx * sv);                   // one reciprocal for both scales
+    const double isx = sv * rp, isv = sx * rp;
     const double qx = ex * isx, qy = ey * isx, qu = eu * isv, qv = ev * isv;
     const double err2 = 0.25 * (qx * qx + qy * qy + qu * qu + qv * qv);   // err^2
     if (!(err2 <= 1.0e300)) return ST_NONFINITE;
