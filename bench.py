@@ -295,8 +295,9 @@ def main():
     ap.add_argument("--no-serving", dest="serving", action="store_false",
                     help="skip the serving leg (Poisson arrivals, p50/p99 latency)")
     ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--no-tune", dest="tune", action="store_false",
-                    help="skip nh_autotune (untimed, on samples disjoint from the timed work)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run nh_autotune first (untimed, on samples disjoint from the timed work); "
+                         "the built-in launch shapes are the ones it picked on MI355X")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (counter calibration)")
     args = ap.parse_args()

@@ -239,7 +239,10 @@ enum {
     NH_OPT_QUEUE_ORDER   = 1,  /* persistent-kernel work order: [0] index order (a wave's
                                   lanes share radius and momentum, so their u and table
                                   reads stay close), 1 lowest momenta first, 2 momentum
-                                  index fastest (lanes share radius and direction) */
+                                  index fastest (lanes share radius and direction), 3 index
+                                  order in 64-trajectory blocks with the blocks of each round
+                                  of claims spread over the workgroups (the costly small
+                                  radii then start on every CU rather than on a few) */
     NH_OPT_FREE_EXIT     = 2,  /* [1] stop a trajectory once it is beyond the compensation
                                   radius and receding (exact: the force is zero from then on);
                                   0 integrates every trajectory to z_end */
@@ -287,6 +290,18 @@ int nh_solve(nh_context *ctx, const nh_request *req, double *n_over_nbar, nh_sta
  * which first waits for this one.  nh_last_stats() waits and reports it. */
 int nh_solve_async(nh_context *ctx, const nh_request *req, double *d_out, double *d_ratio,
                    void *stream);
+
+/* The profile plus the relic distribution behind it (Sec. II.D, Fig. 3: the
+ * phase-space distribution at each radius, whose peaks are the phase-space
+ * shells of infall; the paper inspects it to choose the momentum grid).
+ * d_integrand: device, n_r * n_y doubles, radius-major:
+ *   d_integrand[k n_y + j] = sum_l w_mu,l f0(y_j P_i/P0 (k, j, l)),
+ * the distribution at radius k and momentum node y_j integrated over the
+ * direction (l in index order); far from the halo it is f0(y_j) sum_l w_mu,l.
+ * n/nbar_k = sum_j w_y,j d_integrand[k n_y + j] / sum_j w_y,j f0(y_j) sum_l w_mu,l.
+ * d_out, d_ratio, stream and statistics as for nh_solve_async. */
+int nh_solve_integrand(nh_context *ctx, const nh_request *req, double *d_out, double *d_integrand,
+                       double *d_ratio, void *stream);
 
 /* Several relic masses from one integration (Sec. II.D: the equations of
  * motion do not involve the mass).  The request fixes the velocities: its y

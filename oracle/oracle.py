@@ -398,6 +398,21 @@ def solve(req, threads: int | None = None):
     return tr
 
 
+def integrand_from_ratio(req, ratio: np.ndarray) -> np.ndarray:
+    """Direction-integrated distribution at each radius and momentum node
+    (Sec. II.D, Fig. 3): out[k, j] = sum_l w_mu,l f0(y_j P_i/P0), l in order."""
+    y = np.asarray(req.y, dtype=np.float64)
+    _, w_mu = mu_grid(req)
+    nr, ny, nm = len(req.r_kpc), y.size, w_mu.size
+    ratio = np.asarray(ratio, dtype=np.float64).reshape(nr, ny, nm)
+    out = np.empty((nr, ny))
+    for k in range(nr):
+        f = f0_of(req, y[:, None] * ratio[k])          # (j, l)
+        for j in range(ny):
+            out[k, j] = math.fsum((w_mu * f[j]).tolist())
+    return out
+
+
 def solve_masses(req, m_eV, threads: int | None = None):
     """Profiles for several relic masses from one set of trajectories (Sec. II.D:
     the equations of motion do not contain the mass).  The request's y grid at

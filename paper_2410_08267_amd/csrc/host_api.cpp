@@ -199,7 +199,7 @@ int wait_pending(nh_context *ctx)
 }
 
 int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d_ratio,
-                  hipStream_t stream, int n_mass, const double *m_eV)
+                  hipStream_t stream, int n_mass, const double *m_eV, double *d_integrand)
 {
     int rc = validate(q, ctx->err, sizeof(ctx->err));
     if (rc != NH_OK) return rc;
@@ -258,6 +258,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
                                     stream));
     else
         HIPCHK(launch_reduce_profile(P, g, d_ratio, d_out, stream));
+    if (d_integrand) HIPCHK(launch_reduce_integrand(P, g, d_ratio, d_integrand, stream));
     HIPCHK(launch_reduce_stats(n, o, stats, stream));
     HIPCHK(hipEventRecord(ctx->ev_done, stream));
     ctx->pending = true;
@@ -357,8 +358,8 @@ int nh_set_option(nh_context *ctx, int option, double value)
     if (!std::isfinite(value)) return set_err(ctx, NH_EINVAL, "option value must be finite");
     switch (option) {
     case NH_OPT_QUEUE_ORDER:
-        if (value != 0.0 && value != 1.0 && value != 2.0)
-            return set_err(ctx, NH_EINVAL, "queue order is 0, 1 or 2");
+        if (value != 0.0 && value != 1.0 && value != 2.0 && value != 3.0)
+            return set_err(ctx, NH_EINVAL, "queue order is 0, 1, 2 or 3");
         ctx->queue_order = (int)value;
         return NH_OK;
     case NH_OPT_FREE_EXIT:
@@ -465,6 +466,14 @@ int nh_solve_async(nh_context *ctx, const nh_request *req, double *d_out, double
     if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
     if (!d_out) return set_err(ctx, NH_EINVAL, "d_out is NULL");
     return solve_enqueue(ctx, req, d_out, d_ratio, (hipStream_t)stream, 0, nullptr);
+}
+
+int nh_solve_integrand(nh_context *ctx, const nh_request *req, double *d_out, double *d_integrand, double *d_ratio,
+                       void *stream)
+{
+    if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
+    if (!d_out || !d_integrand) return set_err(ctx, NH_EINVAL, "d_out and d_integrand are required");
+    return solve_enqueue(ctx, req, d_out, d_ratio, (hipStream_t)stream, 0, nullptr, d_integrand);
 }
 
 int nh_solve_masses(nh_context *ctx, const nh_request *req, int n_mass, const double *m_eV, double *d_out,

@@ -17,10 +17,6 @@
 
 namespace nh {
 
-int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d_ratio, hipStream_t stream,
-                  int n_mass, const double *m_eV);
-int collect_stats(nh_context *ctx, nh_stats *out);
-
 namespace {
 
 struct Cand {

@@ -188,6 +188,23 @@ __global__ __launch_bounds__(256) void k_reduce_profile(TrajParams P, GridPtrs g
     reduce_radius(P, g, ratio, blockIdx.x, out);
 }
 
+// Angle-integrated distribution at every radius and momentum node (the
+// integrand of Eq. localdensity before the momentum sum):
+//   out[k n_y + j] = sum_l w_mu,l f0(y_j ratio_kjl), l in index order.
+__global__ __launch_bounds__(256) void k_reduce_integrand(TrajParams P, GridPtrs g,
+                                                          const double *__restrict__ ratio,
+                                                          double *__restrict__ out)
+{
+    const long long kj = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (kj >= (long long)P.n_r * P.n_y) return;
+    const int j = (int)(kj % P.n_y);
+    const double yj = g.y[j];
+    const double *rk = ratio + kj * P.n_mu;
+    double acc = 0.0;
+    for (int l = 0; l < P.n_mu; ++l) acc += g.wmu[l] * f0_eval(g.f0, yj * rk[l]);
+    out[kj] = acc;
+}
+
 // Several masses from the same ratios: block (mass, radius) uses that mass's
 // momentum grid and weights.
 __global__ __launch_bounds__(256) void k_reduce_masses(TrajParams P, GridPtrs g,
@@ -274,6 +291,14 @@ hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const d
                                  double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reduce_profile, dim3(P.n_r), dim3(256), 0, s, P, g, ratio, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_integrand(const TrajParams &P, const GridPtrs &g, const double *ratio, double *out,
+                                   hipStream_t s)
+{
+    const long long n = (long long)P.n_r * P.n_y;
+    hipLaunchKernelGGL(k_reduce_integrand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, g, ratio, out);
     return hipGetLastError();
 }
 

@@ -71,6 +71,11 @@ size_t per_traj_bytes(const nh_request *q);
 void serve_shutdown(nh_context *ctx);
 bool serve_idle(nh_context *ctx);
 int wait_pending(nh_context *ctx);
+// Enqueue one plain solve: trajectories, then the profile (or one profile per
+// mass), and optionally the angle-integrated distribution per radius and momentum.
+int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d_ratio, hipStream_t stream,
+                  int n_mass, const double *m_eV, double *d_integrand = nullptr);
+int collect_stats(nh_context *ctx, nh_stats *out);
 int request_columns(const nh_request *q);
 int batch_slots(const nh_context *ctx, bool f32c);
 int batch_block(const nh_context *ctx, bool f32c);

@@ -207,6 +207,21 @@ __device__ __forceinline__ long long traj_of(long long p, const TrajParams &P)
         const long long j = q / P.n_r;
         return (k * P.n_y + j) * P.n_mu + l;
     }
+    if (P.order == ORDER_SPREAD) {
+        // full 64-trajectory blocks, in rounds of one block per wave of the
+        // grid; a round is a (waves per workgroup) x (workgroups) matrix read
+        // column-wise, so consecutive blocks - neighbouring radii and momenta,
+        // similar in cost - are claimed by different workgroups
+        const long long P_ = blockDim.x >> 6, Q_ = gridDim.x, W_ = P_ * Q_;
+        const long long nbf = P.n_traj >> 6, b = p >> 6;
+        const long long full_rounds = nbf / W_;
+        if (b < full_rounds * W_) {
+            const long long r = b / W_, i = b - r * W_;
+            const long long i_p = i / P_;
+            return ((r * W_ + (i - i_p * P_) * Q_ + i_p) << 6) + (p & 63);
+        }
+        return p;
+    }
     if (P.order == ORDER_Y_FASTEST) {
         const long long j = p % P.n_y;
         const long long q = p / P.n_y;

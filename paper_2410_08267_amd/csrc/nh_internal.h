@@ -32,6 +32,8 @@ enum : int {
     ORDER_NATURAL = 0,     // t = p
     ORDER_SLOW_FIRST = 1,  // p runs over (j, k, l) with l fastest: low-momentum relics first
     ORDER_Y_FASTEST = 2,   // p runs over (k, l, j) with j fastest: a wave shares radius and direction
+    ORDER_SPREAD = 3,      // index order in blocks of 64, the blocks of each round of claims
+                           // transposed so that neighbouring (costly) blocks go to different workgroups
 };
 
 // Everything a trajectory kernel needs about one request, passed by value.

@@ -19,6 +19,8 @@ hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const d
 hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long *stats,
                                hipStream_t s);
 // n_mass profiles from the same ratios: y and its weights per mass at ym, wm (mass-major)
+hipError_t launch_reduce_integrand(const TrajParams &P, const GridPtrs &g, const double *ratio, double *out,
+                                   hipStream_t s);
 hipError_t launch_reduce_masses(const TrajParams &P, const GridPtrs &g, const double *ratio, const double *ym,
                                 const double *wm, int n_mass, double *out, hipStream_t s);
 // FP64 FMA throughput probe: `blocks` workgroups of 1024 threads; *flop = work of one launch

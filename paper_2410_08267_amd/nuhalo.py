@@ -129,6 +129,8 @@ _SIGNATURES = {
     "nh_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "nh_version": (ctypes.c_char_p, []),
     "nh_fp64_fma_peak": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "nh_solve_integrand": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_request), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nh_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nh_request),
                                    ctypes.POINTER(nh_tune_result)]),
     "nh_solve_masses": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_request), ctypes.c_int, _dp,
@@ -373,6 +375,25 @@ class Context:
                                        ctypes.c_void_p(ratio.data_ptr()) if ratio is not None else None,
                                        ctypes.c_void_p(s.cuda_stream))
         self._check(rc)
+
+    def solve_integrand(self, req: Request, out: "torch.Tensor", integrand: "torch.Tensor",
+                        ratio: Optional["torch.Tensor"] = None, stream=None):
+        """Profile plus the direction-integrated distribution per (radius, momentum node):
+        integrand[k * n_y + j] = sum_l w_mu,l f0(y_j P_i/P0) (float64 device tensors)."""
+        for t in (out, integrand) + ((ratio,) if ratio is not None else ()):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+        m = marshal(req)
+        if out.numel() < m.r.size or integrand.numel() < req.n_r * req.n_y:
+            raise ValueError("out or integrand is too small")
+        if ratio is not None and ratio.numel() < req.n_traj:
+            raise ValueError("ratio is too small")
+        s = stream if stream is not None else torch.cuda.current_stream(out.device)
+        rc = self._lib.nh_solve_integrand(self.h, ctypes.byref(m.q), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(integrand.data_ptr()),
+                                          ctypes.c_void_p(ratio.data_ptr()) if ratio is not None else None,
+                                          ctypes.c_void_p(s.cuda_stream))
+        self._check(rc)
+        return m
 
     def fp64_fma_peak(self) -> float:
         """Measured FP64 vector FMA throughput of the device, TFLOP/s."""

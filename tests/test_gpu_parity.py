@@ -278,16 +278,25 @@ def test_step_counts_match_oracle_without_exit(ctx, O):
     assert stats["accepted_steps"] == int(acc.sum())
 
 
-def test_queue_order_does_not_change_results(ctx):
-    req = W.shrink(W.plain_scale(4), 8, 16, 8)
-    say("dp5 queue order 0 vs 1")
-    a = gpu_ratios(ctx, req)[1]
-    ctx.set_option("queue_order", 1)
+@pytest.mark.parametrize("block", [128, 0])
+def test_queue_order_does_not_change_results(ctx, block):
+    """Every queue order is a permutation of the trajectories: identical ratios.
+    With 128-thread workgroups the spread order (3) runs three full rounds of
+    claims plus a partial round and a ragged last block (100650 trajectories)."""
+    req = W.shrink(W.plain_scale(4), 25, 66, 61)
+    say(f"dp5 queue orders 0-3, block {block}, n_traj={req.n_traj}")
+    ctx.set_option("block_threads", block)
     try:
-        b = gpu_ratios(ctx, req)[1]
+        ref = gpu_ratios(ctx, req)
+        for order in (1, 2, 3):
+            ctx.set_option("queue_order", order)
+            got = gpu_ratios(ctx, req)
+            assert np.array_equal(ref[1], got[1]), order
+            assert np.array_equal(ref[0], got[0]), order
+            assert got[2]["accepted_steps"] == ref[2]["accepted_steps"]
     finally:
         ctx.set_option("queue_order", 0)
-    assert np.array_equal(a, b)
+        ctx.set_option("block_threads", 0)
 
 
 def test_rk4_observed_at_z_obs(ctx, O):
@@ -366,3 +375,34 @@ def test_fp64_fma_peak_is_plausible(ctx):
     t = ctx.fp64_fma_peak()
     print(f"measured FP64 FMA {t:.1f} TFLOP/s", flush=True)
     assert 30.0 < t < 1.1 * 78.6
+
+
+def test_integrand_output(ctx, O):
+    """nh_solve_integrand: the direction-integrated distribution per radius and
+    momentum node equals the oracle's quadrature of the GPU's own speed ratios,
+    sums (with the y weights) to the profile, and leaves profile and ratios
+    identical to nh_solve_async."""
+    req = DP5_CASES["paper_model"]()
+    say(f"integrand output n_traj={req.n_traj}")
+    out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+    F = torch.empty(req.n_r * req.n_y, dtype=torch.float64, device="cuda")
+    ratio = torch.empty(req.n_traj, dtype=torch.float64, device="cuda")
+    ctx.solve_integrand(req, out, F, ratio)
+    st, _ = ctx.last_stats()
+    assert st["n_failed"] == 0
+    prof, r, F = out.cpu().numpy(), ratio.cpu().numpy(), F.cpu().numpy().reshape(req.n_r, req.n_y)
+    p0, r0, _ = gpu_ratios(ctx, req)
+    assert np.array_equal(prof, p0) and np.array_equal(r, r0)
+    ref = O.integrand_from_ratio(req, r)
+    assert rel(F, ref).max() <= 1e-13
+    wy = O.y_weights(np.asarray(req.y))
+    _, w_mu = O.mu_grid(req)
+    den = (wy * O.f0_of(req, np.asarray(req.y))).sum() * w_mu.sum()
+    assert rel((F * wy[None, :]).sum(axis=1) / den, prof).max() <= 1e-12
+    # no halo: the initial distribution times the direction weights
+    z = req.with_(mass_kind="zero")
+    Fz = torch.empty(req.n_r * req.n_y, dtype=torch.float64, device="cuda")
+    ctx.solve_integrand(z, out, Fz)
+    ctx.last_stats()
+    want = O.f0_of(req, np.asarray(req.y)) * w_mu.sum()
+    assert rel(Fz.cpu().numpy().reshape(req.n_r, req.n_y), want[None, :]).max() <= 1e-14

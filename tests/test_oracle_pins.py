@@ -671,3 +671,30 @@ def test_solve_masses_equals_per_mass_solves(oracle_mod):
         assert np.abs(got[k] / want - 1).max() < 1e-8, (m, got[k], want)
     # the density contrast grows with the mass (slower relics cluster more)
     assert np.all(got[2] - 1 > got[0] - 1) and np.all(got[0] - 1 > got[1] - 1)
+
+
+def test_integrand_pins(oracle_mod):
+    """Sec. II.D / Fig. 3: far from the halo the distribution is the initial one
+    (ratio 1 exactly: f0(y_j) times the direction weights); its momentum sum with
+    the y weights reproduces n/nbar of Eq. (localdensity); and it is f0 itself
+    where no halo acts."""
+    O = oracle_mod
+    req = paper_model_req(method="dp5", rtol=1e-10)
+    tr = O.trajectories(req)
+    F = O.integrand_from_ratio(req, tr["ratio"])
+    y = np.asarray(req.y)
+    _, w_mu = O.mu_grid(req)
+    wy = O.y_weights(y)
+    f0 = O.f0_of(req, y)
+    # the momentum sum gives the profile
+    prof = O.profile_from_ratio(req, tr["ratio"])
+    num = (F * wy[None, :]).sum(axis=1)
+    den = (wy * f0).sum() * w_mu.sum()
+    assert np.allclose(num / den, prof, rtol=1e-13, atol=0)
+    # no halo: exactly the initial distribution times the direction weights
+    z = req.with_(mass_kind="zero")
+    Fz = O.integrand_from_ratio(z, O.trajectories(z)["ratio"])
+    assert np.array_equal(Fz, np.tile(np.array([math.fsum((w_mu * fj).tolist()) for fj in f0]), (req.n_r, 1)))
+    # at the smallest radius the halo has reshaped the distribution and the
+    # density is above the background (Sec. III)
+    assert num[0] / den > 1.0 and not np.allclose(F[0], Fz[0], rtol=1e-3)
