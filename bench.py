@@ -37,13 +37,13 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # WRITE_SIZE (seeds 0 and 1), each scaled by what the counter reads for a plain
 # 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the sources and
 # build flags these hashes name; any change to them reports traffic as null.
-TRAFFIC_BYTES_PER_LAUNCH = 93470389
+TRAFFIC_BYTES_PER_LAUNCH = 90663628
 TRAFFIC_SOURCES = {
-    "kernels_f64.hip": "af43763ae35391a868b7cc936ee977ee02a769a9b79a6656f10ae1334e94fa0a",
-    "nh_dp5.h": "4e591e60107f94ed748b4dd2e65e970e1b58d70705a2a559ad9d4927ed021bce",
-    "nh_device.h": "c03f14d35678e60909a9122bea2fedb090e074094580d46608bd33fe64180ed7",
-    "nh_internal.h": "eddc42be0a7e6e00a95bb084416ea0a0c3d6b5765e61f0ac312d93c9ae534cf9",
-    "../build.py": "02d0e50104314a81e52ea23b7739d80dc352af57069babf1308fd6cf5c118f35",
+    "kernels_f64.hip": "42c49200e24a6def2288cdd88edc81fc5c5a10f609e617b450fdab89622dcc7d",
+    "nh_dp5.h": "61e4b02899021b13740946767714dbac2260b5882e8c9205153578c966553ea5",
+    "nh_device.h": "35a3171b36b9587023d0eb933e6cc87fcd081fce49cb4d3f8acbdd69a6d6d075",
+    "nh_internal.h": "58dcc8b82d7bc503af626d767b60ab493992c20aa39974d433b28fbc746aafb5",
+    "../build.py": "d3c1c397d53ea82ca441cf34bd1c9ffeb38cae9062c9fad6166ddba8eb10aa87",
 }
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
 
@@ -217,6 +217,19 @@ def plain_leg(ctx, stream, reqs, warmup, tuned=None):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kern_s = sum(kernel_ms) / 1e3
+    # step-count structure of the last timed profile (outside the timed region)
+    r = reqs[-1]
+    acc_t, rej_t, _ = ctx.trajectory_stats(r.n_traj)
+    att = (acc_t.astype("int64") + rej_t).reshape(r.n_r, r.n_y, r.n_mu)
+    import numpy as np
+    blocks = lambda a, axis, n: [float(x.mean()) for x in np.array_split(np.moveaxis(a, axis, 0), n)]
+    steps_hist = {
+        "seed": len(reqs) - 1,
+        "attempts_percentiles": {q: float(np.percentile(att, float(q))) for q in ("50", "90", "99", "99.9", "100")},
+        "mean_attempts_by_radius_decile": blocks(att, 0, 10),
+        "mean_attempts_by_momentum_decile": blocks(att, 1, 10),
+        "mean_attempts_by_direction_decile": blocks(att, 2, 10),
+    }
     achieved = FLOP_PER_DP5_ATTEMPT * (acc + rej) / kern_s / 1e12
     return {
         "value": acc / dt,
@@ -225,6 +238,7 @@ def plain_leg(ctx, stream, reqs, warmup, tuned=None):
         "accepted_steps": acc,
         "rejected_steps": rej,
         "kernel_ms_avg": sum(kernel_ms) / len(kernel_ms),
+        "steps_per_trajectory": steps_hist,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
@@ -237,6 +251,36 @@ def plain_leg(ctx, stream, reqs, warmup, tuned=None):
             "flop_per_attempt": FLOP_PER_DP5_ATTEMPT,
         },
     }
+
+
+def small_leg(ctx, stream, with_oracle: bool):
+    """The small plain case (10 x 50 x 20 trajectories, RK4 with 1000 fixed steps):
+    157 waves for 1024 SIMDs, so latency-bound on the GPU; reported, not gated.
+    Beside it the oracle's time for the whole case on the host cores."""
+    import torch
+    from paper_2410_08267_amd import workloads as W
+    req = W.plain_small()
+    out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+    ctx.solve_async(req, out, stream=stream)
+    ctx.last_stats()
+    ms = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        ctx.solve_async(req, out, stream=stream)
+        st, _ = ctx.last_stats()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    res = {"workload": "plain_small: 10 r x 50 y x 20 mu, RK4 1000 steps, z 0->4",
+           "trajectories": req.n_traj, "steps": st["accepted_steps"],
+           "gpu_ms": min(ms), "gpu_kernel_ms": st["kernel_ms"],
+           "gpu_trajectory_steps_per_s": st["accepted_steps"] / (min(ms) / 1e3)}
+    if with_oracle:
+        from oracle import oracle as O
+        threads = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        O.solve(req, threads=threads)
+        res["oracle_s"] = time.perf_counter() - t0
+        res["oracle_cores"] = threads
+    return res
 
 
 def fp32c_leg(ctx, stream, reqs, tuned=None):
@@ -259,12 +303,15 @@ def fp32c_leg(ctx, stream, reqs, tuned=None):
     ctx.last_stats()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    acc32 = f64 = 0
+    acc32 = rej32 = f64 = 0
+    kms = 0.0
     for r, o in zip(reqs32, outs):
         ctx.solve_async(r, o, stream=stream)
         st, _ = ctx.last_stats()
         acc32 += st["accepted_steps"]
+        rej32 += st["rejected_steps"]
         f64 += st["fp64_steps"]
+        kms += st["kernel_ms"]
     torch.cuda.synchronize()
     dt32 = time.perf_counter() - t1
     errs = [float(np.max(np.abs(o.cpu().numpy() / p64 - 1.0))) for o, p64 in zip(outs, prof64)]
@@ -275,6 +322,12 @@ def fp32c_leg(ctx, stream, reqs, tuned=None):
         "fp64_attempts": f64,
         "max_rel_err_vs_fp64_path": max(errs),
         "rtol": 1e-6,
+        # the same algorithmic FLOP per attempted step, mostly in FP32; packed
+        # FP32 math (the datasheet's 157.3) is compiled out, so non-packed FP32
+        # issues at the FP64 rate, 78.6
+        "roofline": {"bound": "alu", "kernel": "k_dp5_f32c",
+                     "achieved": FLOP_PER_DP5_ATTEMPT * (acc32 + rej32) / (kms / 1e3) / 1e12,
+                     "peak": 157.3, "peak_unpacked": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"},
     }
 
 
@@ -360,6 +413,13 @@ def main():
         measured = ctx.fp64_fma_peak()
         line["roofline"]["peak_measured"] = measured
         line["roofline"]["frac_of_measured_peak"] = line["roofline"]["achieved"] / measured
+        # threads per workgroup of the plain FP64 kernel (one workgroup per CU):
+        # the built-in default, or the autotuner's choice
+        blk = tuned["plain_fp64"]["block_threads"] if tuned else 768
+        line["occupancy"] = {"threads_per_workgroup": blk, "waves_per_simd": blk / 256,
+                             "lds_table_bytes_per_cu": 3073 * 5 * 8}
+    if plain:
+        line["small"] = small_leg(ctx, stream, not args.no_cpu_baseline)
     if args.fp32c:
         line["fp32c"] = fp32c_leg(ctx, stream, reqs, tuned)
     if args.batched:
