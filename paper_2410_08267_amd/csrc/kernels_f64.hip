@@ -26,21 +26,32 @@ __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
 }
 
 // No halo: the force vanishes everywhere, so every velocity is unchanged.
+// Grid-stride: the grid is capped, n may exceed 2^32.
 __global__ void k_free_all(long long n, TrajOut o)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    o.ratio[t] = 1.0;
-    o.stat[t] = TrajStat{0, 0, ST_OK | ST_FREE_EXIT, 0};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        o.ratio[t] = 1.0;
+        o.stat[t] = TrajStat{0, 0, ST_OK | ST_FREE_EXIT, 0};
+    }
+}
+
+// Capped grids for the one-thread-per-item kernels (the dispatch size is 32-bit).
+constexpr long long MAX_BLOCKS = 1ll << 20;
+static unsigned capped_blocks(long long n, int block)
+{
+    long long b = (n + block - 1) / block;
+    if (b > MAX_BLOCKS) b = MAX_BLOCKS;
+    return (unsigned)(b < 1 ? 1 : b);
 }
 
 // ---------------------------------------------------------------------------
 // classical RK4, n_steps equal steps; all lanes share u
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajOut o)
+// One trajectory t (a lane past the end, t >= n_traj, only keeps its wave company).
+__device__ __forceinline__ void rk4_one(const TrajParams &P, const GridPtrs &g, const TrajOut &o, long long t)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = t < P.n_traj;
     double x = 0.0, y = 0.0, vx = 0.0, vy = 0.0, v0n = 1.0;
     if (valid) {
@@ -97,6 +108,15 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
         o.stat[t] = TrajStat{steps, 0, st | (freed ? ST_FREE_EXIT : 0), 0};
     }
 }
+
+__global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajOut o)
+{
+    // grid-stride over wave-aligned chunks (the grid is capped)
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < P.n_traj;
+         base += (long long)gridDim.x * blockDim.x)
+        rk4_one(P, g, o, base + threadIdx.x);
+}
+
 
 // ---------------------------------------------------------------------------
 // Dormand-Prince 5(4), adaptive; persistent waves refill lanes from a queue
@@ -195,14 +215,16 @@ __global__ __launch_bounds__(256) void k_reduce_integrand(TrajParams P, GridPtrs
                                                           const double *__restrict__ ratio,
                                                           double *__restrict__ out)
 {
-    const long long kj = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (kj >= (long long)P.n_r * P.n_y) return;
-    const int j = (int)(kj % P.n_y);
-    const double yj = g.y[j];
-    const double *rk = ratio + kj * P.n_mu;
-    double acc = 0.0;
-    for (int l = 0; l < P.n_mu; ++l) acc += g.wmu[l] * f0_eval(g.f0, yj * rk[l]);
-    out[kj] = acc;
+    const long long n = (long long)P.n_r * P.n_y;
+    for (long long kj = (long long)blockIdx.x * blockDim.x + threadIdx.x; kj < n;
+         kj += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(kj % P.n_y);
+        const double yj = g.y[j];
+        const double *rk = ratio + kj * P.n_mu;
+        double acc = 0.0;
+        for (int l = 0; l < P.n_mu; ++l) acc += g.wmu[l] * f0_eval(g.f0, yj * rk[l]);
+        out[kj] = acc;
+    }
 }
 
 // Several masses from the same ratios: block (mass, radius) uses that mass's
@@ -213,7 +235,7 @@ __global__ __launch_bounds__(256) void k_reduce_masses(TrajParams P, GridPtrs g,
                                                        const double *__restrict__ wm,
                                                        double *__restrict__ out)
 {
-    const int im = blockIdx.x / P.n_r, k = blockIdx.x - im * P.n_r;
+    const int im = blockIdx.y, k = blockIdx.x;
     GridPtrs gm = g;
     gm.y = ym + (size_t)im * P.n_y;
     gm.wy = wm + (size_t)im * P.n_y;
@@ -243,14 +265,13 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, h
 
 hipError_t launch_free_all(long long n, const TrajOut &o, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_free_all, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, o);
+    hipLaunchKernelGGL(k_free_all, dim3(capped_blocks(n, 256)), dim3(256), 0, s, n, o);
     return hipGetLastError();
 }
 
 hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, hipStream_t s)
 {
-    const long long blocks = (P.n_traj + 255) / 256;
-    hipLaunchKernelGGL(k_rk4_f64, dim3((unsigned)blocks), dim3(256), 0, s, P, g, o);
+    hipLaunchKernelGGL(k_rk4_f64, dim3(capped_blocks(P.n_traj, 256)), dim3(256), 0, s, P, g, o);
     return hipGetLastError();
 }
 
@@ -298,15 +319,15 @@ hipError_t launch_reduce_integrand(const TrajParams &P, const GridPtrs &g, const
                                    hipStream_t s)
 {
     const long long n = (long long)P.n_r * P.n_y;
-    hipLaunchKernelGGL(k_reduce_integrand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, g, ratio, out);
+    hipLaunchKernelGGL(k_reduce_integrand, dim3(capped_blocks(n, 256)), dim3(256), 0, s, P, g, ratio, out);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_masses(const TrajParams &P, const GridPtrs &g, const double *ratio, const double *ym,
                                 const double *wm, int n_mass, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_masses, dim3((unsigned)(P.n_r * n_mass)), dim3(256), 0, s, P, g, ratio, ym, wm,
-                       out);
+    hipLaunchKernelGGL(k_reduce_masses, dim3((unsigned)P.n_r, (unsigned)n_mass), dim3(256), 0, s, P, g, ratio, ym,
+                       wm, out);
     return hipGetLastError();
 }
 

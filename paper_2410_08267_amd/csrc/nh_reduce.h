@@ -14,12 +14,12 @@ __device__ __forceinline__ void reduce_radius(const TrajParams &P, const GridPtr
                                               const double *__restrict__ ratio, int k,
                                               double *__restrict__ out)
 {
-    const int ne = P.n_y * P.n_mu;
+    const long long ne = (long long)P.n_y * P.n_mu;
     double num = 0.0, den = 0.0;
     const double *rk = ratio + (size_t)k * ne;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-        const int j = e / P.n_mu;
-        const int l = e - j * P.n_mu;
+    for (long long e = threadIdx.x; e < ne; e += blockDim.x) {
+        const int j = (int)(e / P.n_mu);
+        const int l = (int)(e - (long long)j * P.n_mu);
         const double W = g.wy[j] * g.wmu[l];
         const double yj = g.y[j];
         num += W * f0_eval(g.f0, yj * rk[e]);

@@ -436,3 +436,20 @@ def test_integrand_output(ctx, O):
     ctx.last_stats()
     want = O.f0_of(req, np.asarray(req.y)) * w_mu.sum()
     assert rel(Fz.cpu().numpy().reshape(req.n_r, req.n_y), want[None, :]).max() <= 1e-14
+
+
+def test_more_than_2_32_trajectories(ctx):
+    """Maximum sizes: 65536 x 256 x 257 = 4.31e9 trajectories (more than 2^32,
+    103 GB of per-trajectory results) with no halo: every index is 64-bit and
+    every one-thread-per-item grid is capped and strided.  The profile is
+    exactly 1 at every radius and every trajectory is counted."""
+    req = W.plain_small().with_(mass_kind="zero", method="dp5", r_kpc=np.geomspace(10.0, 1000.0, 65536),
+                                y=np.geomspace(0.01, 100.0, 256), n_mu=257)
+    assert req.n_traj > 2 ** 32
+    say(f"zero halo at n_traj={req.n_traj}")
+    out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+    ctx.solve_async(req, out)
+    st, _ = ctx.last_stats()
+    assert st["n_traj"] == req.n_traj and st["free_exits"] == req.n_traj
+    assert st["accepted_steps"] == 0 and st["n_failed"] == 0
+    assert np.all(out.cpu().numpy() == 1.0)

@@ -180,3 +180,17 @@ def test_table_resolution(N, seed):
     interp = sum(wk[:, None] * T[i + o] for wk, o in zip(w, (-1, 0, 1, 2)))
     err = np.abs(interp - exact).max(axis=0) / np.abs(exact).max(axis=0)
     assert np.all(err < 5e-13), err
+
+
+def test_trajectory_count_bounds(N):
+    """Sizes: 2^40 trajectories is the largest request accepted (its footprint is
+    reported in 64 bits); one more radius beyond it is rejected."""
+    r = W.plain_small().with_(r_kpc=np.geomspace(10.0, 1000.0, 4096), y=np.geomspace(0.01, 100.0, 65536),
+                              n_mu=4096)
+    assert r.n_traj == 2 ** 40
+    fp = N.footprint_bytes(r)
+    assert fp > 24 * 2 ** 40
+    big = r.with_(r_kpc=np.geomspace(10.0, 1000.0, 4097))
+    with pytest.raises(N.NhError) as e:
+        N.footprint_bytes(big)
+    assert e.value.code == N.NH_EINVAL
