@@ -39,7 +39,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # build flags these hashes name; any change to them reports traffic as null.
 TRAFFIC_BYTES_PER_LAUNCH = 90663628
 TRAFFIC_SOURCES = {
-    "kernels_f64.hip": "42c49200e24a6def2288cdd88edc81fc5c5a10f609e617b450fdab89622dcc7d",
+    "kernels_f64.hip": "78b1b23620abf9c4de06b9f927a9148b448546ac8755d1ff108a7decf69ecb69",
     "nh_dp5.h": "61e4b02899021b13740946767714dbac2260b5882e8c9205153578c966553ea5",
     "nh_device.h": "35a3171b36b9587023d0eb933e6cc87fcd081fce49cb4d3f8acbdd69a6d6d075",
     "nh_internal.h": "58dcc8b82d7bc503af626d767b60ab493992c20aa39974d433b28fbc746aafb5",
