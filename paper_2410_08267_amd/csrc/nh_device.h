@@ -94,13 +94,17 @@ struct Stencil4 {
 };
 
 // Weights of nodes i-1..i+2 at fractional position p = s - i.
+// With a = p (p-1) and b = (p+1)(p-2) = a - 2:
+//   wa = -a (p-2)/6, wb = b (p-1)/2, wc = -b p/2, wd = a (p+1)/6.
 __device__ __forceinline__ void stencil_weights(double p, Stencil4 &w)
 {
-    const double pm = p + 1.0, p1 = p - 1.0, p2 = p - 2.0;
-    w.wa = -(p * p1 * p2) * (1.0 / 6.0);
-    w.wb = (pm * p1 * p2) * 0.5;
-    w.wc = -(pm * p * p2) * 0.5;
-    w.wd = (pm * p * p1) * (1.0 / 6.0);
+    const double a = fma(p, p, -p);
+    const double a6 = a * (1.0 / 6.0);
+    const double b2 = (a - 2.0) * 0.5;
+    w.wa = a6 * (2.0 - p);
+    w.wb = fma(b2, p, -b2);
+    w.wc = -(b2 * p);
+    w.wd = fma(a6, p, a6);
 }
 
 // Interval of grid coordinate s on n nodes, clamped to [1, n-3].
