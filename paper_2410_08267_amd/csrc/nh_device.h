@@ -32,6 +32,10 @@ __device__ __forceinline__ double rsq64(double a)
     return fma(y, c, y);
 }
 
+// sqrt(a) for positive finite a from the refined reciprocal square root, to
+// an ulp or two (the step controller's error scales need no more).
+__device__ __forceinline__ double sqrt_pos(double a) { return a * rsq64(a); }
+
 // NFW mass integral I(q) = ln(1+q) - q/(1+q) (Eq. nfw), branch-free for q >= 0.
 // 1+q = m 2^e with e = round(log2(1+q)) (the exponent of (1+q) sqrt(2), so m
 // lies in [sqrt(1/2), sqrt(2)) up to rounding), ln(1+q) = e ln2 + 2 atanh(s),
@@ -155,7 +159,8 @@ __device__ __forceinline__ void rhs(const double c[NCOL], double R, double x, do
     const double q = fmin(r * c[COL_INVS], c[COL_C]);
     const double I = nfw_I(q);
     double g = fma(c[COL_K] * I, ri * ri * ri, -c[COL_KC]);
-    g = (r2 > 0.0 && r < R) ? g : 0.0;
+    // r2 = 0 makes ri and r NaN, so r < R alone also zeroes the force there
+    g = (r < R) ? g : 0.0;
     dx = c[COL_A] * vx;
     dy = c[COL_A] * vy;
     dvx = -g * x;

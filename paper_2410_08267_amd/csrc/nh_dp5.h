@@ -126,8 +126,8 @@ __device__ __forceinline__ int dp5_attempt(Lane64 &L, const CF &cf, const DpCtl 
     const double eu = h * (e1 * k1u + e3 * k3u + e4 * k4u + e5 * k5u + e6 * k6u + e7 * k7u);
     const double ev = h * (e1 * k1v + e3 * k3v + e4 * k4v + e5 * k5v + e6 * k6v + e7 * k7v);
     // sc = atol + rtol max(|.|_n, |.|_{n+1}); max of the norms = sqrt of the max of the squares
-    const double sx = ctl.atol_x + ctl.rtol * sqrt(fmax(x * x + y * y, x5 * x5 + y5 * y5));
-    const double sv = ctl.atol_v + ctl.rtol * sqrt(fmax(vx * vx + vy * vy, vx5 * vx5 + vy5 * vy5));
+    const double sx = ctl.atol_x + ctl.rtol * sqrt_pos(fmax(x * x + y * y, x5 * x5 + y5 * y5));
+    const double sv = ctl.atol_v + ctl.rtol * sqrt_pos(fmax(vx * vx + vy * vy, vx5 * vx5 + vy5 * vy5));
     const double rp = rcp64(sx * sv);                   // one reciprocal for both scales
     const double isx = sv * rp, isv = sx * rp;
     const double qx = ex * isx, qy = ey * isx, qu = eu * isv, qv = ev * isv;
