@@ -60,25 +60,25 @@ __device__ __forceinline__ double nfw_I(double q)
     const double s = num * (w0 * rp);                    // (m-1)/(m+1)
     const double iw = den * rp;                          // 1/(1+q)
     const double s2 = s * s;
-    // s^-3 (atanh(s) - s) = sum_{k=0..9} s2^k / (2k+3): even and odd powers
-    // of s2 as two interleaved Horner chains in s2^2
+    // 2 s^-3 (atanh(s) - s) = sum_{k=0..9} 2 s2^k / (2k+3): even and odd
+    // powers of s2 as two interleaved Horner chains in s2^2
     const double z2 = s2 * s2;
-    double pe = fma(z2, 1.0 / 19.0, 1.0 / 15.0), po = fma(z2, 1.0 / 21.0, 1.0 / 17.0);
-    pe = fma(z2, pe, 1.0 / 11.0);
-    po = fma(z2, po, 1.0 / 13.0);
-    pe = fma(z2, pe, 1.0 / 7.0);
-    po = fma(z2, po, 1.0 / 9.0);
-    pe = fma(z2, pe, 1.0 / 3.0);
-    po = fma(z2, po, 1.0 / 5.0);
+    double pe = fma(z2, 2.0 / 19.0, 2.0 / 15.0), po = fma(z2, 2.0 / 21.0, 2.0 / 17.0);
+    pe = fma(z2, pe, 2.0 / 11.0);
+    po = fma(z2, po, 2.0 / 13.0);
+    pe = fma(z2, pe, 2.0 / 7.0);
+    po = fma(z2, po, 2.0 / 9.0);
+    pe = fma(z2, pe, 2.0 / 3.0);
+    po = fma(z2, po, 2.0 / 5.0);
     const double p = fma(s2, po, pe);
-    const double t3 = 2.0 * s * s2 * p;                  // 2 (atanh(s) - s)
+    const double t3 = s * s2 * p;                        // 2 (atanh(s) - s)
     const bool small = (e == 0);
-    // e = 0: m = 1+q, so 1/(1+s) = (m+1)/(2m) = (1 + 1/(1+q))/2
-    const double inv = small ? fma(0.5, iw, 0.5) : iw;
+    // e = 0: m = 1+q, so 2/(1+s) = (m+1)/m = 1 + 1/(1+q); otherwise 1/(1+q)
+    const double inv = small ? iw + 1.0 : iw;
     const double de = (double)e;
     const double big = fma(de, 6.93147180369123816490e-01,
-                           fma(de, 1.90821492927058770002e-10, fma(-q, inv, 2.0 * s)));
-    return (small ? 2.0 * s2 * inv : big) + t3;
+                           fma(de, 1.90821492927058770002e-10, fma(-q, inv, s + s)));
+    return (small ? s2 * inv : big) + t3;
 }
 
 // |v|^2 with a fixed operation order (the final and initial speeds must round
@@ -121,7 +121,7 @@ __device__ __forceinline__ int stencil_interval(int n, double s)
 // Stencil of the coefficient table (nodes u_i = u0 + i du) at u.
 __device__ __forceinline__ Stencil4 stencil_at(int n_tab, double u0, double inv_du, double u)
 {
-    const double s = (u - u0) * inv_du;
+    const double s = fma(u, inv_du, -(u0 * inv_du));
     const int i = stencil_interval(n_tab, s);
     Stencil4 w;
     w.row = i - 1;
