@@ -254,8 +254,9 @@ enum {
                                   [64, 1024], or 0 for the defaults [0]: what nh_autotune chose
                                   for that form and precision, else 768 for FP64 nh_solve (three
                                   waves per SIMD; more lanes per profile lengthen its tail),
-                                  512 for the FP32C kernels (their limit), 1024 for FP64
-                                  batches and serving (four waves per SIMD) */
+                                  512 for FP32C nh_solve, 768 for FP32C batches and serving
+                                  (three waves per SIMD, their limit), 1024 for FP64 batches
+                                  and serving (four waves per SIMD) */
     NH_OPT_BATCH_SLOTS   = 6,  /* batched and serving forms: request tables per workgroup in
                                   LDS, 1 or 2, or 0 for the default [0]: what nh_autotune chose
                                   for FP32C, else 2 for FP32C, and 1 for FP64 (3073

@@ -25,8 +25,9 @@ int request_columns(const nh_request *q)
 
 int batch_block(const nh_context *ctx, bool f32c)
 {
-    // FP64 slices fit four waves per SIMD (1024 threads); the FP32C lane state two
-    const int cap = f32c ? 512 : 1024;
+    // FP64 slices fit four waves per SIMD (1024 threads, 128 VGPRs); the FP32C
+    // lane state three (768 threads, 170 VGPRs)
+    const int cap = f32c ? 768 : 1024;
     if (ctx->block_threads > 0) return std::min(ctx->block_threads, cap);
     return ctx->tuned_batch_block[f32c] > 0 ? std::min(ctx->tuned_batch_block[f32c], cap) : cap;
 }

@@ -27,7 +27,7 @@ std::vector<Cand> candidates(int form, bool f32c)
 {
     std::vector<Cand> c;
     if (form == NH_FORM_PLAIN) {
-        const int fp64[] = {256, 384, 512, 640, 768, 1024}, fp32[] = {256, 384, 512};
+        const int fp64[] = {256, 384, 512, 640, 768, 1024}, fp32[] = {256, 384, 512, 640, 768};
         if (f32c)
             for (int b : fp32) c.push_back({b, 0});
         else
@@ -36,7 +36,7 @@ std::vector<Cand> candidates(int form, bool f32c)
         // two FP32 tables of 3073 nodes fit one workgroup's LDS; the results do
         // not depend on the slot count
         for (int s : {1, 2})
-            for (int b : {256, 384, 512}) c.push_back({b, s});
+            for (int b : {256, 384, 512, 768}) c.push_back({b, s});
     } else {
         // FP64 batches keep one 3073-node table per workgroup: the plain
         // form's table, so that a batched profile equals the plain one

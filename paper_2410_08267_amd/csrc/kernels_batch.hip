@@ -312,7 +312,7 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
 // ---------------------------------------------------------------------------
 
 template <int NC, int SLOTS>
-__global__ __launch_bounds__(512) void k_slice_f32c(SliceArgs A)
+__global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
 {
     extern __shared__ float lds32b[];
     __shared__ WgSched S;

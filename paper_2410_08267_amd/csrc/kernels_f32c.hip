@@ -19,7 +19,7 @@ namespace nh {
 // CULL: some start radius lies beyond R_exit (otherwise no relic can be culled
 // and the test is left out of the trajectory loop)
 template <int NC, bool CULL>
-__global__ __launch_bounds__(512) void k_dp5_f32c(TrajParams P, GridPtrs g, TrajOut o,
+__global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, TrajOut o,
                                                    unsigned long long *counter)
 {
     extern __shared__ float lds32[];
@@ -83,7 +83,9 @@ template <int NC, bool CULL>
 static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                  unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    const int B = P.block > 0 && P.block < 512 ? P.block : 512;   // launch bound of k_dp5_f32c
+    // default 512 (a single profile's tail grows with more lanes); at most the
+    // launch bound, 768 (the lane state fits 170 VGPRs: three waves per SIMD)
+    const int B = P.block > 0 ? (P.block < 768 ? P.block : 768) : 512;
     const size_t lds = (size_t)P.n_tab * NC * sizeof(float);
     hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f32c<NC, CULL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -38,7 +38,7 @@ def test_plain_autotune_changes_no_result(ctx, prec):
     before = plain(ctx, req)
     res = ctx.autotune(sample, "plain")
     print(res, flush=True)
-    allowed = {256, 384, 512} if prec == "fp32c" else {256, 384, 512, 640, 768, 1024}
+    allowed = {256, 384, 512, 640, 768} if prec == "fp32c" else {256, 384, 512, 640, 768, 1024}
     assert res["block_threads"] in allowed
     assert res["n_tried"] == len(allowed)
     assert res["batch_slots"] == 0
@@ -58,8 +58,8 @@ def test_batch_autotune_changes_no_result(ctx, prec):
     res = ctx.autotune(reqs, "batch")
     print(res, flush=True)
     if prec == "fp32c":
-        assert res["block_threads"] in {256, 384, 512} and res["batch_slots"] in {1, 2}
-        assert res["n_tried"] == 6
+        assert res["block_threads"] in {256, 384, 512, 768} and res["batch_slots"] in {1, 2}
+        assert res["n_tried"] == 8
     else:
         assert res["block_threads"] in {512, 768, 1024} and res["batch_slots"] == 1
         assert res["n_tried"] == 3
