@@ -37,11 +37,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # WRITE_SIZE (seeds 0 and 1), each scaled by what the counter reads for a plain
 # 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the sources and
 # build flags these hashes name; any change to them reports traffic as null.
-TRAFFIC_BYTES_PER_LAUNCH = 90663628
+TRAFFIC_BYTES_PER_LAUNCH = 90472069
 TRAFFIC_SOURCES = {
     "kernels_f64.hip": "78b1b23620abf9c4de06b9f927a9148b448546ac8755d1ff108a7decf69ecb69",
-    "nh_dp5.h": "61e4b02899021b13740946767714dbac2260b5882e8c9205153578c966553ea5",
-    "nh_device.h": "35a3171b36b9587023d0eb933e6cc87fcd081fce49cb4d3f8acbdd69a6d6d075",
+    "nh_dp5.h": "7fd3db224d31bc45c7734ec4a0e48cafdbc295bb5efcec005b9c9a5d57e1f44d",
+    "nh_device.h": "a0e25980b986ccb9fc7c0ffcd30c90002f7d4d8d4e95531b70c91d75e6b64c9c",
     "nh_internal.h": "58dcc8b82d7bc503af626d767b60ab493992c20aa39974d433b28fbc746aafb5",
     "../build.py": "d3c1c397d53ea82ca441cf34bd1c9ffeb38cae9062c9fad6166ddba8eb10aa87",
 }
