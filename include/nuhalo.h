@@ -265,7 +265,9 @@ enum {
                                   keep integrating while the next table loads).  Two FP64
                                   tables hold at most 2044 (constant R) or 1703 nodes. */
     NH_OPT_SLICE_US      = 7,  /* serving: length of a time slice in microseconds, 200..1e6 [4000];
-                                  requests are admitted and retired between slices */
+                                  requests are admitted and retired between slices.  While
+                                  the admitted, unclaimed work would take more than four
+                                  slices, a slice is stretched to a quarter of it, at most 8x */
     NH_OPT_SERVE_GRAPH   = 8   /* serving: [1] run each slice (descriptor uploads, the slice
                                   kernel, the read-back of its queue state) as a replay of a
                                   HIP graph built once per session and table layout, with only

@@ -120,7 +120,9 @@ struct ServeState {
     // session parameters, fixed while anything is admitted
     int precision = -1;
     int n_tab = 0, slots = 1, block = 512, grid = 0;
-    long long slice_ticks = 0;
+    long long slice_ticks = 0;        // NH_OPT_SLICE_US in device clock ticks
+    double ticks_per_ms = 100000.0;
+    double claim_rate = 0.0;          // trajectories claimed per ms of slice (running estimate)
     char *arena_base = nullptr;
     size_t arena_bytes = 0;
     Arena arena;
@@ -218,6 +220,7 @@ int start_session(nh_context *ctx, ServeState &S, bool f32c)
     HIPCHK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device));
     if (rate_khz <= 0) rate_khz = 100000;
     S.slice_ticks = (long long)((double)ctx->slice_us * rate_khz / 1000.0);
+    S.ticks_per_ms = (double)rate_khz;
     S.resume = false;
     S.precision = f32c ? NH_FP32C : NH_FP64;
     S.use_graph = ctx->serve_graph;
@@ -311,7 +314,26 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
     A.policy = POLICY_UNOPENED_FIRST;
     A.cursor = nullptr;
     A.n_tab = S.n_tab;
-    A.budget_ticks = S.slice_ticks;
+    // Slice length: NH_OPT_SLICE_US, stretched up to 8x while the admitted
+    // backlog would take more than four such slices to claim.  Every slice
+    // boundary costs ~0.6 ms of drain and restart plus a host round trip, so
+    // a loaded server runs longer slices (throughput), a light one short ones
+    // (latency); the backlog is re-read at every boundary.
+    long long unclaimed = 0;
+    for (Ticket *t : run) {
+        const long long left = t->n_traj - (long long)S.h_next[t->slot];
+        unclaimed += left > 0 ? left : 0;
+    }
+    long long ticks = S.slice_ticks;
+    if (S.claim_rate > 0.0) {
+        const double backlog_ms = (double)unclaimed / S.claim_rate;
+        const double want = 0.25 * backlog_ms * S.ticks_per_ms;
+        if (want > (double)ticks) ticks = (long long)std::min(want, 8.0 * (double)S.slice_ticks);
+    }
+    unsigned long long claimed_before = 0;
+    for (Ticket *t : run)
+        claimed_before += std::min<unsigned long long>(S.h_next[t->slot], (unsigned long long)t->n_traj);
+    A.budget_ticks = ticks;
     A.lane_save = S.d_lanes;
     A.wg_save = S.d_wg;
     A.resume = S.resume ? 1 : 0;
@@ -354,6 +376,16 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
     WCHK(hipStreamSynchronize(s));
     float ms = 0.f;
     WCHK(hipEventElapsedTime(&ms, S.ev0, S.ev1));
+    {
+        unsigned long long claimed_after = 0;
+        for (Ticket *t : run)
+            claimed_after += std::min<unsigned long long>(S.h_next[t->slot], (unsigned long long)t->n_traj);
+        const double got = (double)(claimed_after > claimed_before ? claimed_after - claimed_before : 0);
+        if (ms > 0.f && got > 0.0) {
+            const double r = got / ms;
+            S.claim_rate = S.claim_rate > 0.0 ? 0.7 * S.claim_rate + 0.3 * r : r;
+        }
+    }
 
     // finished requests: queue exhausted and nothing saved in flight
     std::vector<Ticket *> done;
