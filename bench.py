@@ -256,7 +256,8 @@ def plain_leg(ctx, stream, reqs, warmup, tuned=None):
 def small_leg(ctx, stream, with_oracle: bool):
     """The small plain case (10 x 50 x 20 trajectories, RK4 with 1000 fixed steps):
     157 waves for 1024 SIMDs, so latency-bound on the GPU; reported, not gated.
-    Beside it the oracle's time for the whole case on the host cores."""
+    Beside it the oracle's time for the whole case on the host cores, and both
+    again with Dormand-Prince at rtol 1e-10."""
     import torch
     from paper_2410_08267_amd import workloads as W
     req = W.plain_small()
@@ -273,12 +274,24 @@ def small_leg(ctx, stream, with_oracle: bool):
            "trajectories": req.n_traj, "steps": st["accepted_steps"],
            "gpu_ms": min(ms), "gpu_kernel_ms": st["kernel_ms"],
            "gpu_trajectory_steps_per_s": st["accepted_steps"] / (min(ms) / 1e3)}
+    # the same case with Dormand-Prince at rtol 1e-10 (the oracle's reference mode)
+    ref = req.with_(method="dp5", rtol=1e-10)
+    ctx.solve_async(ref, out, stream=stream)
+    ctx.last_stats()
+    t0 = time.perf_counter()
+    ctx.solve_async(ref, out, stream=stream)
+    st2, _ = ctx.last_stats()
+    res["gpu_dp5_rtol1e-10_ms"] = (time.perf_counter() - t0) * 1e3
+    res["dp5_rtol1e-10_steps"] = st2["accepted_steps"]
     if with_oracle:
         from oracle import oracle as O
         threads = len(os.sched_getaffinity(0))
         t0 = time.perf_counter()
         O.solve(req, threads=threads)
         res["oracle_s"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.solve(ref, threads=threads)
+        res["oracle_dp5_rtol1e-10_s"] = time.perf_counter() - t0
         res["oracle_cores"] = threads
     return res
 
