@@ -95,7 +95,8 @@ Staged stage_layout(const nh_request *q, int table_nodes, int n_mass)
     return s;
 }
 
-void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P, const double *m_eV)
+void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P, int table_threads,
+                const double *m_eV)
 {
     Physics ph(*q);
     const double u_end = -std::log1p(q->integ.z_end);
@@ -115,7 +116,7 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P,
         P.n_steps = q->integ.n_steps;
         P.rk_h = (u_end - u_start) / (double)q->integ.n_steps;
     } else {
-        build_interp_table(ph, u_end, s.n_tab, tab);
+        build_interp_table(ph, u_end, s.n_tab, tab, table_threads);
         P.n_tab = s.n_tab;
         P.tab_u0 = u_end;
         P.tab_inv_du = (double)(s.n_tab - 1) / (u_start - u_end);
@@ -214,7 +215,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
     const Staged s = stage_layout(q, ctx->table_nodes, n_mass);
     if ((rc = ensure_pinned(ctx, s.bytes)) != NH_OK) return rc;
     TrajParams P;
-    stage_fill(q, s, (char *)ctx->h_stage, P, m_eV);
+    stage_fill(q, s, (char *)ctx->h_stage, P, 4, m_eV);
     if (!ctx->free_exit && P.r_exit > 0.0) {
         P.r_exit = -1.0;
         P.cull_D = 0.0;

@@ -57,7 +57,7 @@ void describe(const nh_context *ctx, const nh_request *q, const Staged &s, char 
               double *ratio, TrajStat *stat, double *out, BatchReq &d)
 {
     std::memset(&d, 0, sizeof(d));
-    stage_fill(q, s, host_base, d.P);
+    stage_fill(q, s, host_base, d.P, 1);
     if (!ctx->free_exit && d.P.r_exit > 0.0) {
         d.P.r_exit = -1.0;
         d.P.cull_D = 0.0;

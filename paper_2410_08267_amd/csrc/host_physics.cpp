@@ -4,7 +4,9 @@
 // Halo model: Sec. II.B (Eqs. rhototal, nfw) with the enclosed mass of App. A
 // (attractive sign); background and EOM: Sec. II.A, Eq. (eoms), written in
 // u = ln a; growth variants and G(z): Sec. IV.A, IV.B.
+#include <algorithm>
 #include <cmath>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 
@@ -235,13 +237,29 @@ double Physics::drift(double u_end) const
 // relative for the columns of the benchmark halos (checked on the host).
 int default_table_nodes() { return 3073; }
 
-void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out)
+void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out, int threads)
 {
     const double du = (ph.u_start - u_end) / (double)(n_tab - 1);
-    for (int i = 0; i < n_tab; ++i) {
-        double u = (i == n_tab - 1) ? ph.u_start : u_end + (double)i * du;
-        ph.coef(u, out + (size_t)i * NCOL);
+    auto rows = [&](int i0, int i1) {
+        for (int i = i0; i < i1; ++i) {
+            double u = (i == n_tab - 1) ? ph.u_start : u_end + (double)i * du;
+            ph.coef(u, out + (size_t)i * NCOL);
+        }
+    };
+    // rows are independent: a few host threads may share a large table (the
+    // plain solve builds one per request while the device waits; batches
+    // already build their requests' tables in parallel)
+    const int nt = n_tab >= 1024 ? std::min(threads, (int)std::max(1u, std::thread::hardware_concurrency())) : 1;
+    if (nt <= 1) {
+        rows(0, n_tab);
+        return;
     }
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    const int chunk = (n_tab + nt - 1) / nt;
+    for (int w = 1; w < nt; ++w) th.emplace_back(rows, std::min(n_tab, w * chunk), std::min(n_tab, (w + 1) * chunk));
+    rows(0, std::min(n_tab, chunk));
+    for (auto &t : th) t.join();
 }
 
 void build_rk4_table(const Physics &ph, double u_end, int n_steps, double *out)

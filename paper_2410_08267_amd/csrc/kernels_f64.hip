@@ -335,7 +335,7 @@ hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long
                                hipStream_t s)
 {
     long long blocks = (n + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > 256) blocks = 256;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_reduce_stats, dim3((unsigned)blocks), dim3(256), 0, s, n, o, stats);
     return hipGetLastError();

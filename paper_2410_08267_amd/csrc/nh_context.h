@@ -64,7 +64,7 @@ int set_err(nh_context *ctx, int code, const char *fmt, ...);
 int ensure_dev(nh_context *ctx, DevBuf &b, size_t bytes);
 int ensure_pinned(nh_context *ctx, size_t bytes);
 Staged stage_layout(const nh_request *q, int table_nodes, int n_mass = 0);
-void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P,
+void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P, int table_threads,
                 const double *m_eV = nullptr);
 GridPtrs grid_ptrs(const Staged &s, const char *dev);
 size_t per_traj_bytes(const nh_request *q);

@@ -198,7 +198,7 @@ long long n_traj_of(const nh_request *q);
 
 // Table builders (host, FP64).
 int default_table_nodes();
-void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out);   // nodes on [u_end, u_start]
+void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out, int threads = 1);   // nodes on [u_end, u_start]
 void build_rk4_table(const Physics &ph, double u_end, int n_steps, double *out);
 
 }  // namespace nh

@@ -42,6 +42,7 @@ __device__ __forceinline__ void reduce_radius(const TrajParams &P, const GridPtr
 // Integer statistics of trajectories t = first, first + step, ... < n (exact
 // under any summation order), added into
 // stats = [accepted, rejected, max(acc+rej), failed, fp64 attempts, free exits].
+// Called by every thread of a block of at most 1024 threads.
 __device__ __forceinline__ void reduce_stats_range(const TrajStat *__restrict__ stat, long long first,
                                                    long long n, long long step, unsigned long long *stats)
 {
@@ -65,13 +66,25 @@ __device__ __forceinline__ void reduce_stats_range(const TrajStat *__restrict__ 
         f64 += __shfl_down(f64, off);
         fre += __shfl_down(fre, off);
     }
+    // then across the block's waves in LDS, so that one set of atomics per
+    // block (not per wave) meets the same six counters
+    __shared__ unsigned long long part[16][6];
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     if (__lane_id() == 0) {
-        atomicAdd(stats + 0, acc);
-        atomicAdd(stats + 1, rej);
-        atomicMax(stats + 2, mx);
-        atomicAdd(stats + 3, fail);
-        atomicAdd(stats + 4, f64);
-        atomicAdd(stats + 5, fre);
+        part[w][0] = acc;
+        part[w][1] = rej;
+        part[w][2] = mx;
+        part[w][3] = fail;
+        part[w][4] = f64;
+        part[w][5] = fre;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int c = threadIdx.x;
+        unsigned long long v = part[0][c];
+        for (int i = 1; i < nw; ++i) v = (c == 2) ? (part[i][c] > v ? part[i][c] : v) : v + part[i][c];
+        if (c == 2) atomicMax(stats + c, v);
+        else atomicAdd(stats + c, v);
     }
 }
 
