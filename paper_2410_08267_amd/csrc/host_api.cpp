@@ -261,6 +261,9 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
         HIPCHK(launch_reduce_profile(P, g, d_ratio, d_out, stream));
     if (d_integrand) HIPCHK(launch_reduce_integrand(P, g, d_ratio, d_integrand, stream));
     HIPCHK(launch_reduce_stats(n, o, stats, stream));
+    // the statistics come back with the solve itself, so reading them later
+    // does not wait for whatever the caller enqueued on the stream since
+    HIPCHK(hipMemcpyAsync(ctx->h_stats, stats, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipEventRecord(ctx->ev_done, stream));
     ctx->pending = true;
     ctx->last_n_traj = n;
@@ -273,7 +276,7 @@ int collect_stats(nh_context *ctx, nh_stats *out)
     if (!ctx->pending && ctx->last_n_traj < 0) return set_err(ctx, NH_EINVAL, "no solve to report");
     HIPCHK(hipEventSynchronize(ctx->ev_done));
     unsigned long long h[8] = {0};
-    HIPCHK(hipMemcpy(h, (unsigned long long *)ctx->small.p + 8, sizeof(h), hipMemcpyDeviceToHost));
+    std::memcpy(h, ctx->h_stats, sizeof(h));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
     nh_stats st{};
@@ -431,7 +434,8 @@ int nh_context_create(int device, nh_context **out)
     if (hipSetDevice(device) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&ctx->ev_done) != hipSuccess || hipEventCreate(&ctx->ev_t0) != hipSuccess ||
-        hipEventCreate(&ctx->ev_t1) != hipSuccess) {
+        hipEventCreate(&ctx->ev_t1) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_stats, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
         set_err(nullptr, NH_EDEVICE, "stream/event creation failed");
         nh_context_destroy(ctx);
         return NH_EDEVICE;
@@ -453,6 +457,7 @@ int nh_context_destroy(nh_context *ctx)
     for (DevBuf *b : {&ctx->blob, &ctx->ratio, &ctx->stat, &ctx->small, &ctx->out, &ctx->bctr})
         if (b->p) (void)hipFree(b->p);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    if (ctx->h_stats) (void)hipHostFree(ctx->h_stats);
     if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
     if (ctx->ev_t0) (void)hipEventDestroy(ctx->ev_t0);
     if (ctx->ev_t1) (void)hipEventDestroy(ctx->ev_t1);

@@ -471,10 +471,8 @@ hipError_t slice_capacity(bool f32c, int nc, int slots, int n_tab, int block, in
 {
     const void *fn = slice_fn(f32c, nc, slots);
     const size_t lds = slice_lds_bytes(f32c, nc, slots, n_tab);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds);
+    const hipError_t e = occupancy_cached(fn, block, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     *grid = n_cu * per_cu;

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "nh_dp5_f32.h"
+#include "nh_launch.h"
 
 namespace nh {
 
@@ -87,11 +88,8 @@ static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const T
     // launch bound, 768 (the lane state fits 170 VGPRs: three waves per SIMD)
     const int B = P.block > 0 ? (P.block < 768 ? P.block : 768) : 512;
     const size_t lds = (size_t)P.n_tab * NC * sizeof(float);
-    hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f32c<NC, CULL>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dp5_f32c<NC, CULL>, B, lds);
+    const hipError_t e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL>, B, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long long grid = (long long)n_cu * per_cu;

@@ -8,6 +8,10 @@
 // from an LDS copy of the FP64 table (Dormand-Prince: every lane has its own u).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
 #include "nh_dp5.h"
 #include "nh_reduce.h"
 
@@ -275,17 +279,46 @@ hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut 
     return hipGetLastError();
 }
 
+// The LDS attribute and the occupancy query cost host time at every launch;
+// their answer depends only on the kernel, the block size and the LDS bytes,
+// so it is kept per (kernel, block, bytes).
+hipError_t occupancy_cached(const void *fn, int block, size_t lds, int *per_cu)
+{
+    struct Entry {
+        const void *fn;
+        int block;
+        size_t lds;
+        int per_cu;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const Entry &e : cache)
+        if (e.fn == fn && e.block == block && e.lds == lds) {
+            *per_cu = e.per_cu;
+            return hipSuccess;
+        }
+    // the attribute is a per-kernel upper bound: never lower it below a size
+    // an earlier (cached) launch of the same kernel relies on
+    size_t attr = lds;
+    for (const Entry &e : cache)
+        if (e.fn == fn) attr = std::max(attr, e.lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)attr);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, block, lds);
+    if (e != hipSuccess) return e;
+    cache.push_back(Entry{fn, block, lds, *per_cu});
+    return hipSuccess;
+}
+
 template <int NC, bool CULL>
 static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                 unsigned long long *counter, int n_cu, hipStream_t s)
 {
     const int B = P.block > 0 ? P.block : DP5_DEFAULT_BLOCK;
     const size_t lds = (size_t)P.n_tab * NC * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void *)k_dp5_f64<NC, CULL>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dp5_f64<NC, CULL>, B, lds);
+    const hipError_t e = occupancy_cached((const void *)k_dp5_f64<NC, CULL>, B, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long long grid = (long long)n_cu * per_cu;

@@ -38,6 +38,7 @@ struct nh_context {
     nh::DevBuf blob, ratio, stat, small, out;
     nh::DevBuf bctr;                                 // batched form: counters and statistics
     void *h_stage = nullptr;                         // pinned staging for the inputs
+    unsigned long long *h_stats = nullptr;           // pinned copy of the last solve's statistics
     size_t h_stage_cap = 0;
     hipEvent_t ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
     bool pending = false;

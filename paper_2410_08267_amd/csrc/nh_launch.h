@@ -34,6 +34,8 @@ int slice_max_table_nodes(bool f32c, int nc, int slots);
 hipError_t slice_capacity(bool f32c, int nc, int slots, int n_tab, int block, int n_cu, int *grid);
 hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, int grid, int block, hipStream_t s);
 const void *fill_u64_kernel();
+// hipFuncSetAttribute (dynamic LDS) and the occupancy query, kept per (kernel, block, bytes)
+hipError_t occupancy_cached(const void *fn, int block, size_t lds, int *per_cu);
 
 // A serving slice captured as a HIP graph (descriptor and order uploads, the
 // in-flight clear, the slice kernel, the read-back of queue positions and
