@@ -37,12 +37,12 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # WRITE_SIZE (seeds 0 and 1), each scaled by what the counter reads for a plain
 # 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the sources and
 # build flags these hashes name; any change to them reports traffic as null.
-TRAFFIC_BYTES_PER_LAUNCH = 90472069
+TRAFFIC_BYTES_PER_LAUNCH = 90209138
 TRAFFIC_SOURCES = {
-    "kernels_f64.hip": "78b1b23620abf9c4de06b9f927a9148b448546ac8755d1ff108a7decf69ecb69",
+    "kernels_f64.hip": "caa3ddb5c6c103f24b9a083eb879f5ec8c9738bff3a4c42a6ef1c0eb25bf02fc",
     "nh_dp5.h": "7fd3db224d31bc45c7734ec4a0e48cafdbc295bb5efcec005b9c9a5d57e1f44d",
     "nh_device.h": "a0e25980b986ccb9fc7c0ffcd30c90002f7d4d8d4e95531b70c91d75e6b64c9c",
-    "nh_internal.h": "58dcc8b82d7bc503af626d767b60ab493992c20aa39974d433b28fbc746aafb5",
+    "nh_internal.h": "5c6d5b9ab8d55a6f927702964b4f78ebd00b42aa6e6a9f1610aee0615039d9c9",
     "../build.py": "d3c1c397d53ea82ca441cf34bd1c9ffeb38cae9062c9fad6166ddba8eb10aa87",
 }
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
