@@ -268,11 +268,19 @@ enum {
                                   requests are admitted and retired between slices.  While
                                   the admitted, unclaimed work would take more than four
                                   slices, a slice is stretched to a quarter of it, at most 8x */
-    NH_OPT_SERVE_GRAPH   = 8   /* serving: [1] run each slice (descriptor uploads, the slice
+    NH_OPT_SERVE_GRAPH   = 8,  /* serving: [1] run each slice (descriptor uploads, the slice
                                   kernel, the read-back of its queue state) as a replay of a
                                   HIP graph built once per session and table layout, with only
                                   the kernel's arguments updated; 0 issues them one by one.
                                   Taken when a serving session starts. */
+    NH_OPT_WORKGROUPS    = 9   /* nh_solve, nh_solve_async, nh_solve_masses, nh_solve_integrand
+                                  with Dormand-Prince: at most this many workgroups per launch,
+                                  1..65536, or 0 for the default [0]: as many as the device holds
+                                  at once (one per CU).  Solves from several contexts on
+                                  separate streams, each capped to its share of the CUs, run
+                                  side by side; a profile's tail (its few longest
+                                  trajectories) then idles only its own share.  Results do not
+                                  depend on it. */
 };
 int nh_set_option(nh_context *ctx, int option, double value);
 

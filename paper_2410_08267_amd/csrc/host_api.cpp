@@ -249,6 +249,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
         if (f32) P.h_fp64 = ctx->h_fp64;
         P.order = ctx->queue_order;
         P.block = ctx->block_threads > 0 ? ctx->block_threads : ctx->tuned_plain_block[f32];
+        P.max_wg = ctx->max_workgroups;
         if (f32) HIPCHK(launch_dp5_f32c(P, g, o, counter, ctx->n_cu, stream));
         else HIPCHK(launch_dp5_f64(P, g, o, counter, ctx->n_cu, stream));
     }
@@ -396,6 +397,11 @@ int nh_set_option(nh_context *ctx, int option, double value)
     case NH_OPT_SERVE_GRAPH:
         if (value != 0.0 && value != 1.0) return set_err(ctx, NH_EINVAL, "serve graph is 0 or 1");
         ctx->serve_graph = value != 0.0;
+        return NH_OK;
+    case NH_OPT_WORKGROUPS:
+        if (value != 0.0 && (value < 1 || value > 65536 || value != (double)(int)value))
+            return set_err(ctx, NH_EINVAL, "workgroups must be 0 (default) or an integer in [1, 65536]");
+        ctx->max_workgroups = (int)value;
         return NH_OK;
     default:
         return set_err(ctx, NH_EINVAL, "unknown option %d", option);

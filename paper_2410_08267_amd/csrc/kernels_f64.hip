@@ -322,6 +322,7 @@ static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const Tr
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long long grid = (long long)n_cu * per_cu;
+    if (P.max_wg > 0 && grid > P.max_wg) grid = P.max_wg;
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;

@@ -56,6 +56,7 @@ struct nh_context {
     int tuned_batch_slots[2] = {0, 0};
     double slice_us = 4000.0;                        // serving: time slice length
     bool serve_graph = true;                         // serving: slices as HIP graph replays
+    int max_workgroups = 0;                          // plain Dormand-Prince launches (0: one per CU)
     nh::ServeState *serve = nullptr;
 };
 

@@ -62,6 +62,7 @@ struct TrajParams {
     double R_const;         // > 0: the compensation radius is this constant (no R column)
     int order;              // ORDER_*
     int block;              // workgroup size of the persistent kernels
+    int max_wg;             // > 0: at most this many workgroups (plain Dormand-Prince launches)
     // FP32-compensated form: steps with |h| below this run in FP64
     double h_fp64;
 };

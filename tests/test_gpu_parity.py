@@ -38,6 +38,7 @@ import numpy as np
 import pytest
 import torch
 
+from paper_2410_08267_amd import nuhalo as N
 from paper_2410_08267_amd import workloads as W
 from paper_2410_08267_amd.request import Z_FORM_PAPER
 
@@ -326,6 +327,50 @@ def test_queue_order_does_not_change_results(ctx, block):
             assert got[2]["accepted_steps"] == ref[2]["accepted_steps"]
     finally:
         ctx.set_option("queue_order", 0)
+        ctx.set_option("block_threads", 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_workgroup_cap_does_not_change_results(ctx, prec):
+    """Capping a launch's workgroups (so that solves on several streams run side
+    by side) changes only which lanes take which trajectories: identical ratios.
+    Three 1024-thread workgroups (FP32C: its 768-thread limit) leave a ragged
+    last round of claims on 100650 trajectories; two solves on two streams at
+    once give the same bits again."""
+    req = W.shrink(W.plain_scale(4), 25, 66, 61).with_(precision=prec)
+    say(f"{prec} workgroup cap 3 and two streams, n_traj={req.n_traj}")
+    ref = gpu_ratios(ctx, req)
+    ctx.set_option("workgroups", 3)
+    ctx.set_option("block_threads", 1024)
+    try:
+        got = gpu_ratios(ctx, req)
+        assert np.array_equal(ref[1], got[1])
+        assert np.array_equal(ref[0], got[0])
+        assert got[2]["accepted_steps"] == ref[2]["accepted_steps"]
+        with pytest.raises(N.NhError):
+            ctx.set_option("workgroups", 0.5)
+        with pytest.raises(N.NhError):
+            ctx.set_option("workgroups", 70000)
+        # two contexts, half the device each, on two streams at once
+        ctx.set_option("workgroups", 128)
+        other = N.Context(0)
+        try:
+            other.set_option("workgroups", 128)
+            s2 = torch.cuda.Stream()
+            outs = [torch.empty(req.n_r, dtype=torch.float64, device="cuda") for _ in range(2)]
+            ratios = [torch.empty(req.n_traj, dtype=torch.float64, device="cuda") for _ in range(2)]
+            ctx.solve_async(req, outs[0], ratio=ratios[0])
+            other.solve_async(req, outs[1], ratio=ratios[1], stream=s2)
+            ctx.last_stats()
+            other.last_stats()
+            torch.cuda.synchronize()
+            for o, r in zip(outs, ratios):
+                assert np.array_equal(o.cpu().numpy(), ref[0])
+                assert np.array_equal(r.cpu().numpy(), ref[1])
+        finally:
+            other.close()
+    finally:
+        ctx.set_option("workgroups", 0)
         ctx.set_option("block_threads", 0)
 
 
