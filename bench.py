@@ -33,11 +33,11 @@ sys.path.insert(0, ROOT)
 FLOP_PER_DP5_ATTEMPT = 6 * 84 + 5 * 55 + 184 + 182
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
-# HBM bytes per k_dp5_f64 launch on this workload (1024 threads, 128 workgroups),
+# HBM bytes per k_dp5_f64 launch on this workload (1024 threads, 64 workgroups),
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (seeds 0 and 1), each scaled by what
 # the counter reads for a plain 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the sources and
 # build flags these hashes name; any change to them reports traffic as null.
-TRAFFIC_BYTES_PER_LAUNCH = 93281581
+TRAFFIC_BYTES_PER_LAUNCH = 94783239
 TRAFFIC_SOURCES = {
     "kernels_f64.hip": "d065db7771698004f0767fd903a37d9fc2e31d2085710e1dba8aba635957f22f",
     "nh_dp5.h": "7fd3db224d31bc45c7734ec4a0e48cafdbc295bb5efcec005b9c9a5d57e1f44d",
@@ -197,12 +197,13 @@ def tune(ctx, form: str, reqs):
 # Consecutive profiles run side by side on PIPE_DEPTH contexts, each on its own
 # stream and its share of the CUs, so that one profile's tail (its few longest
 # trajectories) idles only that share.  Each step is still one whole profile.
-# Two: more streams than that shared hardware queues here and serialised.
-PIPE_DEPTH = 2
+# Four: one hardware queue each (four per process here); streams beyond that
+# share queues and serialise.
+PIPE_DEPTH = 4
 PLAIN_FP64_BLOCK = 1024   # four waves per SIMD pay once tails no longer idle the device
 
 
-def overlapped(reqs, outs, stream, block, warm_req):
+def overlapped(reqs, outs, block, warm_req):
     """Solve reqs[i] into outs[i] on PIPE_DEPTH contexts, each on its own stream
     and capped to its share of the CUs; a context takes the next profile as soon
     as its previous one is done.
@@ -214,7 +215,7 @@ def overlapped(reqs, outs, stream, block, warm_req):
     from paper_2410_08267_amd import nuhalo as N
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     ctxs = [N.Context(0) for _ in range(PIPE_DEPTH)]
-    streams = [stream] + [torch.cuda.Stream() for _ in range(PIPE_DEPTH - 1)]
+    streams = [torch.cuda.Stream() for _ in range(PIPE_DEPTH)]
     warm_out = torch.empty(warm_req.n_r, dtype=torch.float64, device="cuda")
     for c, s in zip(ctxs, streams):
         if block:
@@ -275,7 +276,7 @@ def plain_leg(ctx, stream, reqs, warmup, tuned=None):
         ctx.solve_async(W.plain_scale(1000 + i), out, stream=stream)
         ctx.last_stats()
     outs = [torch.empty(r.n_r, dtype=torch.float64, device="cuda") for r in reqs]
-    dt, tot, kernel_ms, span_ms, last, ctxs = overlapped(reqs, outs, stream, block, W.plain_scale(1000))
+    dt, tot, kernel_ms, span_ms, last, ctxs = overlapped(reqs, outs, block, W.plain_scale(1000))
     acc, rej = tot["accepted_steps"], tot["rejected_steps"]
     # step-count structure of the last timed profile (outside the timed region)
     r = reqs[-1]
@@ -382,7 +383,7 @@ def fp32c_leg(ctx, stream, reqs, tuned=None):
                                                    for s in (2000, 2001, 2002)])
     outs = [torch.empty(r.n_r, dtype=torch.float64, device="cuda") for r in reqs32]
     block = tuned["plain_fp32c"]["block_threads"] if tuned else 0
-    dt32, tot, _, span_ms, _, ctxs = overlapped(reqs32, outs, stream, block,
+    dt32, tot, _, span_ms, _, ctxs = overlapped(reqs32, outs, block,
                                                 W.plain_scale(1000).with_(precision="fp32c"))
     for c in ctxs:
         c.close()
