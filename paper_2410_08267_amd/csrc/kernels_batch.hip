@@ -28,6 +28,9 @@ struct TabCoefB {
         coef_interp<NC, STRIDE>(tab, n_tab, u0, inv_du, u, c);
         R = (NC == NCOL && nc == NCOL) ? c[COL_R] : R_const;
     }
+    // four rows per stage: the shared window of stages 2 and 3 costs registers
+    // this kernel does not have (the values are the same either way)
+    static constexpr bool paired = false;
 };
 
 // The same from an FP32 table slot (rows of NC floats).

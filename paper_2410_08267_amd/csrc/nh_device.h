@@ -130,9 +130,11 @@ __device__ __forceinline__ Stencil4 stencil_at(int n_tab, double u0, double inv_
 }
 
 // Column k of the interpolated coefficients from rows of `stride` doubles.
+// The sum runs node by node as one FMA chain, so that the five-node form
+// below reproduces it bit for bit.
 __device__ __forceinline__ double stencil_col(const Stencil4 &w, const double *row, int stride, int k)
 {
-    return w.wa * row[k] + w.wb * row[stride + k] + w.wc * row[2 * stride + k] + w.wd * row[3 * stride + k];
+    return fma(w.wd, row[3 * stride + k], fma(w.wc, row[2 * stride + k], fma(w.wb, row[stride + k], w.wa * row[k])));
 }
 
 // Coefficients at u from the uniform table, rows of STRIDE doubles of which
@@ -146,6 +148,39 @@ __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int 
     const double *row = tab + w.row * STRIDE;
 #pragma unroll
     for (int k = 0; k < NC; ++k) c[k] = stencil_col(w, row, STRIDE, k);
+}
+
+// Coefficients at two abscissae a fraction of a step apart (uQ at or below
+// uP).  When their stencils start on the same or adjacent nodes, the five
+// rows from Q's first node serve both, P's weights shifted by the difference
+// (a zero weight on the unused end row); lanes whose stencils lie further
+// apart read P's own four rows.  Either way the values equal those of two
+// coef_interp calls bit for bit: an FMA with a zero weight adds an exact zero.
+// The fifth row index is clamped to the table, where its weight is always zero.
+template <int NC, int STRIDE = NC>
+__device__ __forceinline__ void coef_interp2(const double *__restrict__ tab, int n_tab, double u0,
+                                             double inv_du, double uP, double uQ, double cP[NCOL],
+                                             double cQ[NCOL])
+{
+    const Stencil4 wQ = stencil_at(n_tab, u0, inv_du, uQ);
+    const Stencil4 wP = stencil_at(n_tab, u0, inv_du, uP);
+    const double *row = tab + wQ.row * STRIDE;
+    const double *row4 = tab + min(wQ.row + 4, n_tab - 1) * STRIDE;
+    const int d = wP.row - wQ.row;
+    const bool s = d == 1;
+    const double v0 = s ? 0.0 : wP.wa, v1 = s ? wP.wa : wP.wb, v2 = s ? wP.wb : wP.wc;
+    const double v3 = s ? wP.wc : wP.wd, v4 = s ? wP.wd : 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const double r0 = row[k], r1 = row[STRIDE + k], r2 = row[2 * STRIDE + k], r3 = row[3 * STRIDE + k];
+        cQ[k] = fma(wQ.wd, r3, fma(wQ.wc, r2, fma(wQ.wb, r1, wQ.wa * r0)));
+        cP[k] = fma(v4, row4[k], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
+    }
+    if ((unsigned)d > 1u) {
+        const double *rp = tab + wP.row * STRIDE;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) cP[k] = stencil_col(wP, rp, STRIDE, k);
+    }
 }
 
 // dY/du for Y = (x, y, vx, vy): dx/du = A v, dv/du = -g x with

@@ -40,6 +40,16 @@ struct TabCoef {
         coef_interp<NC, STRIDE>(tab, n_tab, u0, inv_du, u, c);
         R = (NC == NCOL) ? c[COL_R] : R_const;
     }
+    // coefficients at uP and at uQ <= uP, a fraction of a step apart, from one
+    // five-row window where they share it
+    static constexpr bool paired = true;
+    __device__ __forceinline__ void at2(double uP, double uQ, double cP[NCOL], double &RP, double cQ[NCOL],
+                                        double &RQ) const
+    {
+        coef_interp2<NC, STRIDE>(tab, n_tab, u0, inv_du, uP, uQ, cP, cQ);
+        RP = (NC == NCOL) ? cP[COL_R] : R_const;
+        RQ = (NC == NCOL) ? cQ[COL_R] : R_const;
+    }
 };
 
 struct DpCtl {
@@ -91,15 +101,21 @@ __device__ __forceinline__ int dp5_attempt(Lane64 &L, const CF &cf, const DpCtl 
     }
     const double x = L.x, y = L.y, vx = L.vx, vy = L.vy, u = L.u;
     const double k1x = L.k1x, k1y = L.k1y, k1u = L.k1u, k1v = L.k1v;
-    double c[NCOL], R;
+    double c[NCOL], R, cb[NCOL], Rb;
     double k2x, k2y, k2u, k2v, k3x, k3y, k3u, k3v, k4x, k4y, k4u, k4v;
     double k5x, k5y, k5u, k5v, k6x, k6y, k6u, k6v, k7x, k7y, k7u, k7v;
 
-    cf.at(u + c2 * h, c, R);
+    // stages 2 and 3 lie a tenth of a step apart: one table window for both
+    // where the source has one (h < 0, so stage 3 sits at or below stage 2)
+    if constexpr (CF::paired) {
+        cf.at2(u + c2 * h, u + c3 * h, c, R, cb, Rb);
+    } else {
+        cf.at(u + c2 * h, c, R);
+    }
     rhs(c, R, x + h * (a21 * k1x), y + h * (a21 * k1y), vx + h * (a21 * k1u), vy + h * (a21 * k1v),
         k2x, k2y, k2u, k2v);
-    cf.at(u + c3 * h, c, R);
-    rhs(c, R, x + h * (a31 * k1x + a32 * k2x), y + h * (a31 * k1y + a32 * k2y),
+    if constexpr (!CF::paired) cf.at(u + c3 * h, cb, Rb);
+    rhs(cb, Rb, x + h * (a31 * k1x + a32 * k2x), y + h * (a31 * k1y + a32 * k2y),
         vx + h * (a31 * k1u + a32 * k2u), vy + h * (a31 * k1v + a32 * k2v), k3x, k3y, k3u, k3v);
     cf.at(u + c4 * h, c, R);
     rhs(c, R, x + h * (a41 * k1x + a42 * k2x + a43 * k3x), y + h * (a41 * k1y + a42 * k2y + a43 * k3y),
