@@ -37,11 +37,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (seeds 0 and 1), each scaled by what
 # the counter reads for a plain 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the sources and
 # build flags these hashes name; any change to them reports traffic as null.
-TRAFFIC_BYTES_PER_LAUNCH = 94783239
+TRAFFIC_BYTES_PER_LAUNCH = 95092911
 TRAFFIC_SOURCES = {
     "kernels_f64.hip": "d065db7771698004f0767fd903a37d9fc2e31d2085710e1dba8aba635957f22f",
-    "nh_dp5.h": "7fd3db224d31bc45c7734ec4a0e48cafdbc295bb5efcec005b9c9a5d57e1f44d",
-    "nh_device.h": "a0e25980b986ccb9fc7c0ffcd30c90002f7d4d8d4e95531b70c91d75e6b64c9c",
+    "nh_dp5.h": "c9a09aa826db44ed57190ecea29756224b6bed2220cca89efc3195073061ed3a",
+    "nh_device.h": "8116fd1511b47db24c57e787620b7a5ffcc31c7e63a968b5e300c21a28d8c5fa",
     "nh_internal.h": "423e35d973ade1aed18f5b891a95f413abbb973fe70b762c40a6eb4438732d31",
     "../build.py": "d3c1c397d53ea82ca441cf34bd1c9ffeb38cae9062c9fad6166ddba8eb10aa87",
 }
