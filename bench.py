@@ -201,6 +201,7 @@ def tune(ctx, form: str, reqs):
 # share queues and serialise.
 PIPE_DEPTH = 4
 PLAIN_FP64_BLOCK = 1024   # four waves per SIMD pay once tails no longer idle the device
+PLAIN_FP32C_BLOCK = 768   # three waves per SIMD, the FP32C kernel's limit
 
 
 def overlapped(reqs, outs, block, warm_req):
@@ -382,7 +383,7 @@ def fp32c_leg(ctx, stream, reqs, tuned=None):
         tuned["plain_fp32c"] = tune(ctx, "plain", [W.plain_scale(s).with_(precision="fp32c")
                                                    for s in (2000, 2001, 2002)])
     outs = [torch.empty(r.n_r, dtype=torch.float64, device="cuda") for r in reqs32]
-    block = tuned["plain_fp32c"]["block_threads"] if tuned else 0
+    block = tuned["plain_fp32c"]["block_threads"] if tuned else PLAIN_FP32C_BLOCK
     dt32, tot, _, span_ms, _, ctxs = overlapped(reqs32, outs, block,
                                                 W.plain_scale(1000).with_(precision="fp32c"))
     for c in ctxs:
