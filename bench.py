@@ -489,10 +489,13 @@ def main():
         measured = ctx.fp64_fma_peak()
         line["roofline"]["peak_measured"] = measured
         line["roofline"]["frac_of_measured_peak"] = line["roofline"]["achieved"] / measured
-        # threads per workgroup of the plain FP64 kernel (one workgroup per CU):
-        # the built-in default, or the autotuner's choice
+        # threads per workgroup of the plain FP64 kernel (one workgroup per CU,
+        # a quarter of the CUs per profile): the bench's choice or the autotuner's
         blk = tuned["plain_fp64"]["block_threads"] if tuned else PLAIN_FP64_BLOCK
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
         line["occupancy"] = {"threads_per_workgroup": blk, "waves_per_simd": blk / 256,
+                             "workgroups_per_launch": max(1, n_cu // PIPE_DEPTH),
+                             "concurrent_profiles": PIPE_DEPTH,
                              "lds_table_bytes_per_cu": 3073 * 5 * 8}
     if plain:
         line["small"] = small_leg(ctx, stream, not args.no_cpu_baseline)
