@@ -202,6 +202,7 @@ def tune(ctx, form: str, reqs):
 PIPE_DEPTH = 4
 PLAIN_FP64_BLOCK = 1024   # four waves per SIMD pay once tails no longer idle the device
 PLAIN_FP32C_BLOCK = 768   # three waves per SIMD, the FP32C kernel's limit
+CU_SHARE = 1.0            # workgroups per launch: this many CUs' worth over the profiles in flight
 
 
 def overlapped(reqs, outs, block, warm_req):
@@ -241,6 +242,8 @@ def overlapped(reqs, outs, block, warm_req):
         while free and todo:
             k = free.pop(0)
             r, o = todo.pop(0)
+            # the last profiles may spread over the CUs the others free as they end
+            ctxs[k].set_option("workgroups", max(1, int(CU_SHARE * n_cu) // max(1, min(PIPE_DEPTH, len(todo) + 1))))
             ctxs[k].solve_async(r, o, stream=streams[k])
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(streams[k])
