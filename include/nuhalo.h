@@ -439,7 +439,7 @@ const char *nh_version(void);
 /* Measured FP64 vector FMA throughput of the context's device (TFLOP/s, FMA =
  * 2 FLOP): a kernel of independent v_fma_f64 chains in every lane of every CU,
  * best of three launches.  The datasheet peak of an MI355X is 78.6 TFLOP/s;
- * this is the ceiling the trajectory kernels are judged against as well. */
+ * this is the ceiling the trajectory kernels are measured against as well. */
 int nh_fp64_fma_peak(nh_context *ctx, double *tflops);
 
 #ifdef __cplusplus
