@@ -194,3 +194,11 @@ def test_trajectory_count_bounds(N):
     with pytest.raises(N.NhError) as e:
         N.footprint_bytes(big)
     assert e.value.code == N.NH_EINVAL
+
+
+def test_binding_options_match_header(N):
+    """The binding's option names and numbers are the header's NH_OPT_* enum."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    declared = {name.lower(): int(v) for name, v in re.findall(r"\bNH_OPT_([A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    assert declared == N.OPTIONS
+    assert declared["workgroups"] == 9
