@@ -247,13 +247,23 @@ def test_dp5_matches_oracle_at_tight_rtol(ctx, O, sensitivity, name):
 
 
 def test_dp5_full_size_sampled(ctx, O):
-    """Full 100 x 200 x 64 grid in the benchmark's launch; 400 sampled trajectories
-    integrated one by one on the oracle, plus the quadrature re-done on the CPU
-    from the GPU's own ratios."""
+    """Full 100 x 200 x 64 grid in the benchmark's launch shape (1024-thread
+    workgroups, at most 64 of them, as when four profiles run side by side);
+    400 sampled trajectories integrated one by one on the oracle, plus the
+    quadrature re-done on the CPU from the GPU's own ratios.  The default
+    launch (768 threads on every CU) gives the same bits."""
     req = W.plain_scale(4)
-    say(f"dp5 full size seed 4 n_traj={req.n_traj}")
-    prof, ratio, stats = gpu_ratios(ctx, req)
+    say(f"dp5 full size seed 4 n_traj={req.n_traj}, 1024 threads x 64 workgroups")
+    ctx.set_option("block_threads", 1024)
+    ctx.set_option("workgroups", 64)
+    try:
+        prof, ratio, stats = gpu_ratios(ctx, req)
+    finally:
+        ctx.set_option("block_threads", 0)
+        ctx.set_option("workgroups", 0)
     assert stats["n_failed"] == 0
+    prof0, ratio0, _ = gpu_ratios(ctx, req)
+    assert np.array_equal(ratio0, ratio) and np.array_equal(prof0, prof)
     rng = np.random.default_rng(11)
     idx = np.sort(rng.choice(req.n_traj, 400, replace=False))
     tr = O.trajectories(req, index=idx)
