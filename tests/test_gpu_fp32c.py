@@ -66,11 +66,20 @@ def test_fp32c_within_1e4_of_oracle(ctx, O, name, h_fp64):
 
 
 def test_fp32c_full_size(ctx, O):
-    """Full 1.28 M-trajectory profile; compared on radii re-computed by the oracle
-    on a subsample of (y, mu) through the GPU's FP64 profile at rtol 1e-10."""
+    """Full 1.28 M-trajectory profile in the benchmark's launch shape (768-thread
+    workgroups, at most 64 of them); compared with the GPU's FP64 profile at
+    rtol 1e-10.  The default launch gives the same bits."""
     req = W.precision(4)
-    say(f"fp32c full size seed 4 n_traj={req.n_traj}")
-    got, stats, _ = ctx.solve(req)
+    say(f"fp32c full size seed 4 n_traj={req.n_traj}, 768 threads x 64 workgroups")
+    ctx.set_option("block_threads", 768)
+    ctx.set_option("workgroups", 64)
+    try:
+        got, stats, _ = ctx.solve(req)
+    finally:
+        ctx.set_option("block_threads", 0)
+        ctx.set_option("workgroups", 0)
+    got0, _, _ = ctx.solve(req)
+    assert np.array_equal(got0, got)
     ref, _, _ = ctx.solve(req.with_(precision="fp64", rtol=1e-10))
     e = np.abs(got / ref - 1)
     print(f"fp32c vs fp64(rtol 1e-10) full profile: max rel err {e.max():.2e}; "
