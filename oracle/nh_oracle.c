@@ -86,6 +86,13 @@ typedef struct {
     double    atol_v;          /* km/s */
     double    h0;              /* first trial step in u (negative) */
     long long max_steps;       /* attempted-step budget per trajectory */
+    /* Step-control settings for the tests (0 = the defaults of the reading the
+       library implements): the largest step growth after an accepted step
+       (default 5), and per-component error scales atol + rtol max(|y_i|,
+       |y_i'|) instead of the position / velocity pair norms (a library
+       integrator's convention, so the controller can be checked against it). */
+    double    fmax;
+    int       component_scales;
 } nho_integ;
 
 enum { NHO_OK = 0, NHO_MAXSTEPS = 1, NHO_UNDERFLOW = 2, NHO_NONFINITE = 3 };
@@ -327,16 +334,17 @@ static const double DP_BS[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 /
  *   err = sqrt( mean_i (E_i / sc_i)^2 ),  E = h sum_j (b_j - b*_j) k_j
  *   sc  = atol + rtol * max(|.|_n, |.|_{n+1}), with |.| the Euclidean norm of
  *         the position pair for the x, y components and of the velocity pair
- *         for the vx, vy components;
+ *         for the vx, vy components (it->component_scales: |y_i| itself);
  *   accept when err <= 1;
- *   h_new = h * min(fmax, max(0.2, 0.9 err^(-1/5))), fmax = 5, and fmax = 1
- *         for the step right after a rejection;
+ *   h_new = h * min(fmax, max(0.2, 0.9 err^(-1/5))), fmax = 5 (it->fmax when
+ *         set), and fmax = 1 for the step right after a rejection;
  *   the last step is cut to land on u_end. */
 static int integrate_dp5(const nho_model *m, const nho_integ *it, double *Y,
                          long long *acc_out, long long *rej_out)
 {
     const double u_end = it->u_end;
     const double dir = (u_end >= it->u_start) ? 1.0 : -1.0;
+    const double fmax = it->fmax > 0.0 ? it->fmax : 5.0;
     double u = it->u_start;
     double h = dir * fabs(it->h0);
     if (fabs(h) > fabs(u_end - u)) h = u_end - u;
@@ -366,23 +374,32 @@ static int integrate_dp5(const nho_model *m, const nho_integ *it, double *Y,
             for (int j = 0; j < 7; ++j) sum += (DP_B[j] - DP_BS[j]) * K[j][i];
             E[i] = h * sum;
         }
-        double rx0 = sqrt(Y[0] * Y[0] + Y[1] * Y[1]);
-        double rx1 = sqrt(Y5[0] * Y5[0] + Y5[1] * Y5[1]);
-        double rv0 = sqrt(Y[2] * Y[2] + Y[3] * Y[3]);
-        double rv1 = sqrt(Y5[2] * Y5[2] + Y5[3] * Y5[3]);
-        double sx = it->atol_x + it->rtol * (rx0 > rx1 ? rx0 : rx1);
-        double sv = it->atol_v + it->rtol * (rv0 > rv1 ? rv0 : rv1);
-        double e0 = E[0] / sx, e1 = E[1] / sx, e2 = E[2] / sv, e3 = E[3] / sv;
-        double err = sqrt((e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3) / 4.0);
+        double sc[4];
+        if (it->component_scales) {
+            for (int i = 0; i < 4; ++i) {
+                double a0 = fabs(Y[i]), a1 = fabs(Y5[i]);
+                sc[i] = (i < 2 ? it->atol_x : it->atol_v) + it->rtol * (a0 > a1 ? a0 : a1);
+            }
+        } else {
+            double rx0 = sqrt(Y[0] * Y[0] + Y[1] * Y[1]);
+            double rx1 = sqrt(Y5[0] * Y5[0] + Y5[1] * Y5[1]);
+            double rv0 = sqrt(Y[2] * Y[2] + Y[3] * Y[3]);
+            double rv1 = sqrt(Y5[2] * Y5[2] + Y5[3] * Y5[3]);
+            sc[0] = sc[1] = it->atol_x + it->rtol * (rx0 > rx1 ? rx0 : rx1);
+            sc[2] = sc[3] = it->atol_v + it->rtol * (rv0 > rv1 ? rv0 : rv1);
+        }
+        double sum = 0.0;
+        for (int i = 0; i < 4; ++i) { double e = E[i] / sc[i]; sum += e * e; }
+        double err = sqrt(sum / 4.0);
         if (!isfinite(err)) { status = NHO_NONFINITE; break; }
         if (err <= 1.0) {
             ++acc;
             u = last ? u_end : u + h;
             for (int i = 0; i < 4; ++i) { Y[i] = Y5[i]; K[0][i] = K[6][i]; }
             if (last) break;
-            double fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, -0.2);
+            double fac = (err == 0.0) ? fmax : 0.9 * pow(err, -0.2);
             if (fac < 0.2) fac = 0.2;
-            if (fac > 5.0) fac = 5.0;
+            if (fac > fmax) fac = fmax;
             if (rejected_prev && fac > 1.0) fac = 1.0;
             h *= fac;
             rejected_prev = 0;

@@ -37,7 +37,7 @@ _SRC = os.path.join(_HERE, "nh_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libnh_oracle.so")
 
 # Constants (the paper gives only T_nu0 = 1.95 K, Sec. II.C)
-K_B_EV_PER_K = 8.617333262e-5      # CODATA 2018, exact in SI
+K_B_EV_PER_K = 1.380649e-23 / 1.602176634e-19   # k_B / e: both exact in SI since 2019
 C_KM_S = 299792.458                 # exact
 T_NU0_K = 1.95
 
@@ -89,6 +89,8 @@ class _Integ(ctypes.Structure):
         ("atol_v", ctypes.c_double),
         ("h0", ctypes.c_double),
         ("max_steps", ctypes.c_longlong),
+        ("fmax", ctypes.c_double),
+        ("component_scales", ctypes.c_int),
     ]
 
 

@@ -1,11 +1,15 @@
 """The oracle's pins must catch plausible mistakes.
 
-Each case plants one mistake in a copy of nh_oracle.c (a dropped term, a wrong
-sign, a wrong power, a transposed operand, a wrong tableau entry), builds it
-into a temporary library on the CPU, and runs the pin suite against it through
-NH_ORACLE_LIB.  The suite must fail for every mutant.
+Each case plants one mistake in a copy of the oracle (a dropped term, a wrong
+sign, a wrong power, a transposed operand, a wrong tableau entry, a wrong
+step-control constant or norm, a wrong unit factor), builds it on the CPU, and
+runs the pin suite against it: mistakes in nh_oracle.c through NH_ORACLE_LIB
+(a mutated build of the C file), mistakes in oracle.py through NH_ORACLE_ROOT
+(a directory holding a mutated copy of the oracle package, imported first).
+The suite must fail for every mutant.
 """
 import os
+import shutil
 import subprocess
 import sys
 
@@ -13,6 +17,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "nh_oracle.c")
+PY_SRC = os.path.join(ROOT, "oracle", "oracle.py")
 
 MUTANTS = {
     "force_sign": ("dY[2] = -g * x;", "dY[2] = g * x;"),
@@ -45,7 +50,33 @@ MUTANTS = {
     "sampled_time_sign": ("double u = -log1p(z);\n    double du", "double u = log1p(z);\n    double du"),
     "sampled_spacing": ("double du = (0.0 - m->hist_u_min) / (double)(m->hist_n - 1);",
                         "double du = (0.0 - m->hist_u_min) / (double)m->hist_n;"),
+    # step control (Hairer, Norsett & Wanner, Sec. II.4, as read for the paper's unstated integrator)
+    "dp_no_cap_after_rejection": ("            if (rejected_prev && fac > 1.0) fac = 1.0;\n", ""),
+    "dp_max_norm": ("for (int i = 0; i < 4; ++i) { double e = E[i] / sc[i]; sum += e * e; }",
+                    "for (int i = 0; i < 4; ++i) { double e = E[i] / sc[i]; if (4.0 * e * e > sum) sum = 4.0 * e * e; }"),
+    "dp_fmax_10": ("const double fmax = it->fmax > 0.0 ? it->fmax : 5.0;",
+                   "const double fmax = it->fmax > 0.0 ? it->fmax : 10.0;"),
+    "dp_safety_accept": ("double fac = (err == 0.0) ? fmax : 0.9 * pow(err, -0.2);",
+                         "double fac = (err == 0.0) ? fmax : 0.8 * pow(err, -0.2);"),
+    "dp_position_scale_max_component": (
+        "sc[0] = sc[1] = it->atol_x + it->rtol * (rx0 > rx1 ? rx0 : rx1);",
+        "sc[0] = sc[1] = it->atol_x + it->rtol * (fabs(Y[0]) > fabs(Y5[0]) ? fabs(Y[0]) : fabs(Y5[0]));"),
 }
+
+# Mistakes in the Python half of the oracle (initial conditions, quadrature).
+PY_MUTANTS = {
+    "velocity_scale": ("    return K_B_EV_PER_K * T_K * C_KM_S / m_eV",
+                       "    return 1.5 * K_B_EV_PER_K * T_K * C_KM_S / m_eV"),
+    "velocity_temperature": ("    return K_B_EV_PER_K * T_K * C_KM_S / m_eV",
+                             "    return K_B_EV_PER_K * C_KM_S / m_eV"),
+    "trapezoid_end_weight": ("        d[0] = 0.5 * (ly[1] - ly[0])", "        d[0] = (ly[1] - ly[0])"),
+}
+
+
+def _run_pins(env):
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                          env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -58,8 +89,38 @@ def test_pins_catch_mutant(name, tmp_path):
     so = tmp_path / "mut.so"
     subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
                     "-o", str(so), str(mut), "-lm"], check=True)
-    env = dict(os.environ, NH_ORACLE_LIB=str(so))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
-                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    r = _run_pins(dict(os.environ, NH_ORACLE_LIB=str(so)))
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_pins_catch_python_mutant(name, tmp_path):
+    old, new = PY_MUTANTS[name]
+    src = open(PY_SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    (pkg / "oracle.py").write_text(src.replace(old, new))
+    shutil.copy(SRC, pkg / "nh_oracle.c")
+    env = dict(os.environ, NH_ORACLE_ROOT=str(tmp_path))
+    env.pop("NH_ORACLE_LIB", None)
+    r = _run_pins(env)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+def test_unmutated_copies_pass(tmp_path):
+    """Control: both routes, given the oracle unchanged, pass the pins (so a
+    mutant fails because of its mistake, not because of the route)."""
+    so = tmp_path / "same.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-o", str(so), SRC, "-lm"], check=True)
+    r = _run_pins(dict(os.environ, NH_ORACLE_LIB=str(so)))
+    assert r.returncode == 0, r.stdout[-2000:]
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    shutil.copy(PY_SRC, pkg / "oracle.py")
+    shutil.copy(SRC, pkg / "nh_oracle.c")
+    env = dict(os.environ, NH_ORACLE_ROOT=str(tmp_path))
+    env.pop("NH_ORACLE_LIB", None)
+    r = _run_pins(env)
+    assert r.returncode == 0, r.stdout[-2000:]
