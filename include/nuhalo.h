@@ -275,6 +275,11 @@ enum {
                                   HIP graph built once per session and table layout, with only
                                   the kernel's arguments updated; 0 issues them one by one.
                                   Taken when a serving session starts. */
+    NH_OPT_FP32C_RTOL    = 10, /* NH_FP32C: tolerance floor of the FP32 attempts, in [1e-9, 1e-3]
+                                  [1e-7]: they integrate at max(rtol, this).  At 1e-6 the
+                                  discretisation error alone reaches 1e-4 of n/nbar for some
+                                  halos; at 1e-7 the form stays within ~2e-5 of the FP64
+                                  reference integration */
     NH_OPT_WORKGROUPS    = 9   /* nh_solve, nh_solve_async, nh_solve_masses, nh_solve_integrand
                                   with Dormand-Prince: at most this many workgroups per launch,
                                   1..65536, or 0 for the default [0]: as many as the device holds

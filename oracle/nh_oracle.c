@@ -72,6 +72,11 @@ typedef struct {
     const double *hist_M;
     const double *hist_c;
     const double *hist_kappa;
+    /* test only: a sampled factor multiplying H(z) in the equations of motion
+       (pieces as above, NULL for none): a ripple of the expansion rate, which
+       scales both the drift and the kick, probes how the step control responds
+       to perturbations the size of a tabulated coefficient's error */
+    const double *hist_hmod;
 } nho_model;
 
 typedef struct {
@@ -256,6 +261,7 @@ void nho_rhs(const nho_model *m, double u, const double *Y, double *dY)
         double opz = exp(-u);
         z = expm1(-u);
         double H = nho_hubble(m, z);
+        if (m->hist_hmod) H *= nho_sampled(m, m->hist_hmod, z);
         A = opz * opz / H;
         B = nho_kappa(m, z) * nho_G() * opz / H;
     }

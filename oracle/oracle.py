@@ -75,6 +75,7 @@ class _Model(ctypes.Structure):
         ("hist_M", ctypes.POINTER(ctypes.c_double)),
         ("hist_c", ctypes.POINTER(ctypes.c_double)),
         ("hist_kappa", ctypes.POINTER(ctypes.c_double)),
+        ("hist_hmod", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -175,12 +176,14 @@ def model_of(req, static_background: bool = False) -> _Model:
     # u = ln a (scipy's CubicSpline), handed to the C side as its polynomial
     # pieces; the model keeps the coefficient arrays alive
     m._keep = []
-    arrays = [getattr(req, "hist_" + k, None) for k in ("M", "c", "kappa")]
+    # hist_hmod: test-only sampled factor of H(z) (see nh_oracle.c); requests
+    # carry it only as a probe attribute set by the tests
+    arrays = [getattr(req, "hist_" + k, None) for k in ("M", "c", "kappa", "hmod")]
     if any(a is not None for a in arrays):
         from scipy.interpolate import CubicSpline
         u_min = -math.log1p(float(req.hist_z_max))
         m.hist_u_min = u_min
-        for name, a in zip(("hist_M", "hist_c", "hist_kappa"), arrays):
+        for name, a in zip(("hist_M", "hist_c", "hist_kappa", "hist_hmod"), arrays):
             if a is None:
                 continue
             a = np.asarray(a, dtype=np.float64)

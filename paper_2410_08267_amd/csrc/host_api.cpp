@@ -74,7 +74,8 @@ Staged stage_layout(const nh_request *q, int table_nodes, int n_mass)
 {
     Staged s{};
     const bool rk4 = q->integ.method == NH_RK4;
-    s.n_tab = rk4 ? 2 * q->integ.n_steps + 1 : (table_nodes > 0 ? table_nodes : default_table_nodes());
+    s.n_tab = rk4 ? 2 * q->integ.n_steps + 1
+                  : (table_nodes > 0 ? table_nodes : default_table_nodes(q->integ.precision == NH_FP32C));
     size_t off = 0;
     s.off_tab = off;  off = align_up(off + (size_t)s.n_tab * NCOL * sizeof(double));
     s.off_r = off;    off = align_up(off + (size_t)q->grid.n_r * sizeof(double));
@@ -116,10 +117,13 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P,
         P.n_steps = q->integ.n_steps;
         P.rk_h = (u_end - u_start) / (double)q->integ.n_steps;
     } else {
-        build_interp_table(ph, u_end, s.n_tab, tab, table_threads);
-        P.n_tab = s.n_tab;
-        P.tab_u0 = u_end;
-        P.tab_inv_du = (double)(s.n_tab - 1) / (u_start - u_end);
+        const TableGrid tg = table_grid(ph, u_end, s.n_tab);
+        build_interp_table(ph, tg, tab, table_threads);
+        P.n_tab = tg.n;
+        P.tab_u0 = tg.u0;
+        P.tab_inv_du = ph.sampled() ? 1.0 / tg.du : (double)(tg.n - 1) / (u_start - u_end);
+        P.kn.m = tg.m;
+        P.kn.inv_m = 1.0 / (double)tg.m;
     }
     const double rt = q->integ.rtol;
     P.rtol = rt;
@@ -143,6 +147,13 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P,
         P.R_const = q->halo.compensated ? ph.R_fixed : 1.0e300;
     P.order = ORDER_SLOW_FIRST;
     P.h_fp64 = 0.0;
+    // Dormand-Prince tables leave the power-law factors of K and Kc to the
+    // kernels and keep stencils inside spline pieces; RK4 rows are exact
+    // coefficients at the stage abscissae
+    if (q->integ.method != NH_RK4) {
+        P.pw = ph.pw;
+        P.hist = (ph.pw.on_mass || ph.pw.on_kappa || ph.sampled()) ? 1 : 0;
+    }
 
     std::memcpy(base + s.off_r, q->grid.r_kpc, sizeof(double) * q->grid.n_r);
     std::memcpy(base + s.off_y, q->grid.y, sizeof(double) * q->grid.n_y);
@@ -213,6 +224,9 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
     ctx->pending = false;
 
     const Staged s = stage_layout(q, ctx->table_nodes, n_mass);
+    if (!sampled_table_fits(q, s.n_tab))
+        return set_err(ctx, NH_EINVAL, "%d history samples need at least 3 of the %d table nodes per sample interval",
+                       q->halo.history.n, s.n_tab);
     if ((rc = ensure_pinned(ctx, s.bytes)) != NH_OK) return rc;
     TrajParams P;
     stage_fill(q, s, (char *)ctx->h_stage, P, 4, m_eV);
@@ -246,7 +260,10 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
         HIPCHK(launch_rk4_f64(P, g, o, stream));
     } else {
         const bool f32 = q->integ.precision == NH_FP32C;
-        if (f32) P.h_fp64 = ctx->h_fp64;
+        if (f32) {
+            P.h_fp64 = ctx->h_fp64;
+            P.rtol32 = ctx->rtol32;
+        }
         P.order = ctx->queue_order;
         P.block = ctx->block_threads > 0 ? ctx->block_threads : ctx->tuned_plain_block[f32];
         P.max_wg = ctx->max_workgroups;
@@ -374,6 +391,11 @@ int nh_set_option(nh_context *ctx, int option, double value)
     case NH_OPT_FP64_BELOW_H:
         if (value < 0.0) return set_err(ctx, NH_EINVAL, "threshold must be >= 0");
         ctx->h_fp64 = value;
+        return NH_OK;
+    case NH_OPT_FP32C_RTOL:
+        if (value < 1.0e-9 || value > 1.0e-3)
+            return set_err(ctx, NH_EINVAL, "FP32C tolerance floor must be in [1e-9, 1e-3]");
+        ctx->rtol32 = value;
         return NH_OK;
     case NH_OPT_BLOCK_THREADS:
         if (value != 0.0 && (value < 64 || value > 1024 || value != (double)(64 * (int)(value / 64))))

@@ -40,7 +40,7 @@ int batch_slots(const nh_context *ctx, bool f32c)
 
 int batch_table_nodes(nh_context *ctx, bool f32c, int nc, int slots, int *n_tab)
 {
-    const int cap = std::min(slice_max_table_nodes(f32c, nc, slots), 3073);
+    const int cap = std::min(slice_max_table_nodes(f32c, nc, slots), default_table_nodes(f32c));
     if (ctx->table_nodes > 0) {
         if (ctx->table_nodes > cap)
             return set_err(ctx, NH_EINVAL,
@@ -64,6 +64,7 @@ void describe(const nh_context *ctx, const nh_request *q, const Staged &s, char 
     }
     d.P.order = ctx->queue_order;
     d.P.h_fp64 = q->integ.precision == NH_FP32C ? ctx->h_fp64 : 0.0;
+    d.P.rtol32 = ctx->rtol32;
     d.g = grid_ptrs(s, dev_base);
     d.o.ratio = ratio;
     d.o.stat = stat;
@@ -152,6 +153,9 @@ int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d
     long long rtot = 0;
     for (int i = 0; i < n_req; ++i) {
         st[i] = stage_layout(&reqs[i], n_tab);
+        if (!sampled_table_fits(&reqs[i], n_tab))
+            return set_err(ctx, NH_EINVAL, "request %d: %d history samples need at least 3 of the %d table nodes "
+                           "per sample interval", i, reqs[i].halo.history.n, n_tab);
         off[i] = bytes;
         bytes += align_up(st[i].bytes);
         const long long n = n_traj_of(&reqs[i]);
@@ -211,13 +215,15 @@ int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d
     A.lane_save = nullptr;
     A.wg_save = nullptr;
     A.resume = 0;
+    bool pow = false;
+    for (int i = 0; i < n_req; ++i) pow = pow || hdesc[i].P.hist;
     int grid = 0;
-    HIPCHK(slice_capacity(f32c, nc, slots, n_tab, block, ctx->n_cu, &grid));
+    HIPCHK(slice_capacity(f32c, nc, slots, pow, n_tab, block, ctx->n_cu, &grid));
     const long long need = (ntot + block - 1) / block;
     if (grid > need) grid = (int)std::max(1ll, need);
 
     HIPCHK(hipEventRecord(ctx->ev_t0, s));
-    HIPCHK(launch_slice(A, f32c, nc, slots, grid, block, s));
+    HIPCHK(launch_slice(A, f32c, nc, slots, pow, grid, block, s));
     HIPCHK(hipEventRecord(ctx->ev_t1, s));
     const int chunks = (int)std::min(256ll, std::max(1ll, (nmax + 256 * 64 - 1) / (256 * 64)));
     HIPCHK(launch_reduce_batch(A.reqs, A.order, (const int *)(dev + off_rstart), n_req, (int)rtot, d_stats,

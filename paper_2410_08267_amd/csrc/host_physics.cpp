@@ -123,6 +123,29 @@ Physics::Physics(const nh_request &q)
     }
     // M(z_obs) = (4 pi/3) R^3 rhobar_m0, rhobar_m0 = 3 Om H0^2 / (8 pi G)  =>  R^3 = 2 G M / (Om H0^2)
     R_fixed = std::cbrt(2.0 * G * mass(z_obs) / (Om * H0k * H0k));
+    // power-law factors the tables leave out (see PowFactor): xi^alpha unless it
+    // is linear in e^{-u} over the whole interval (alpha = 1 with xi > 0 up to
+    // z_end) or constant (alpha = 0); kappa = 1 + a [z/(1+z)]^b always
+    const double z_end = q.integ.z_end;
+    pw.on_mass = mass_kind == NH_MASS_PAPER && alpha > 0.0 && (alpha != 1.0 || z_form < z_end);
+    pw.on_kappa = kappa_kind == NH_KAPPA_PAPER;
+    pw.zf1 = 1.0 + z_form;
+    pw.inv_dz = 1.0 / (z_form - z_obs);
+    pw.alpha = alpha;
+    pw.ka = ka;
+    pw.kb = kb;
+}
+
+double Physics::pow_factor(double u) const
+{
+    double f = 1.0;
+    if (pw.on_mass) {
+        double xi = (pw.zf1 - std::exp(-u)) * pw.inv_dz;
+        xi = xi < 0.0 ? 0.0 : (xi > 1.0 ? 1.0 : xi);
+        f = std::pow(xi, pw.alpha);
+    }
+    if (pw.on_kappa) f *= 1.0 + pw.ka * std::pow(-std::expm1(u), pw.kb);
+    return f;
 }
 
 double Physics::mass(double z) const
@@ -165,13 +188,17 @@ double Physics::hubble(double z) const
     return H0k * std::sqrt(Om * opz * opz * opz + OL);
 }
 
-void Physics::coef(double u, double out[NCOL]) const
+void Physics::coef(double u, double out[NCOL], bool factored) const
 {
     const double opz = std::exp(-u);
     const double z = std::expm1(-u);
     const double H = H0k * std::sqrt(Om * opz * opz * opz + OL);
     out[COL_A] = opz * opz / H;
     const double M = mass(z);
+    // the mass and G(z) that K and Kc carry: without the power-law factors
+    // when the kernels apply those (M = M0 xi^alpha, kappa = 1 + a s^b)
+    const double MK = (factored && pw.on_mass) ? M0 : M;
+    const double kK = (factored && pw.on_kappa) ? 1.0 : kappa(z);
     const double c = conc(z);
     out[COL_C] = c;
     if (M == 0.0 && geometry == NH_GEOM_DELTA200) {
@@ -191,9 +218,9 @@ void Physics::coef(double u, double out[NCOL]) const
         R = R_fixed;
         rv = (R_fixed / kCbrt200) * (opz / (1.0 + z_obs));   // fixed physical r200, comoving image
     }
-    const double B = kappa(z) * G * opz / H;
-    out[COL_K] = B * M / nfw_I_host(c);
-    out[COL_KC] = compensated ? B * M / (R * R * R) : 0.0;
+    const double B = kK * G * opz / H;
+    out[COL_K] = B * MK / nfw_I_host(c);
+    out[COL_KC] = compensated ? B * MK / (R * R * R) : 0.0;
     out[COL_INVS] = c / rv;
     out[COL_R] = compensated ? R : 1.0e300;
 }
@@ -233,17 +260,53 @@ double Physics::drift(double u_end) const
     return s * h / 3.0;
 }
 
-// 3073 nodes over u in [-ln 5, 0]: cubic interpolation error below ~2e-13
-// relative for the columns of the benchmark halos (checked on the host).
-int default_table_nodes() { return 3073; }
+// FP64: 3073 nodes over u in [-ln 5, 0], cubic interpolation error below
+// ~2e-13 relative for the columns of the benchmark halos (checked on the host).
+// FP32C: 2049 nodes (~1e-12, far below FP32 rounding), so that two tables of
+// the precision form's layout fit one workgroup's LDS in the batched form.
+int default_table_nodes(bool f32c) { return f32c ? 2049 : 3073; }
 
-void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out, int threads)
+TableGrid table_grid(const Physics &ph, double u_end, int n_max)
 {
-    const double du = (ph.u_start - u_end) / (double)(n_tab - 1);
+    TableGrid g;
+    if (!ph.sampled()) {
+        g.n = n_max;
+        g.u0 = u_end;
+        g.du = (ph.u_start - u_end) / (double)(n_max - 1);
+        g.m = n_max - 1;
+        return g;
+    }
+    const double dh = (0.0 - ph.hist_u_min) / (double)(ph.hist_n - 1);
+    int k0 = (int)std::floor((u_end - ph.hist_u_min) / dh);
+    int k1 = (int)std::ceil((ph.u_start - ph.hist_u_min) / dh);
+    k0 = std::max(0, std::min(k0, ph.hist_n - 2));
+    k1 = std::max(k0 + 1, std::min(k1, ph.hist_n - 1));
+    const int pieces = k1 - k0;
+    g.m = (n_max - 1) / pieces;
+    g.n = pieces * g.m + 1;
+    g.u0 = ph.hist_u_min + (double)k0 * dh;
+    g.du = dh / (double)g.m;
+    return g;
+}
+
+bool sampled_table_fits(const nh_request *q, int n_max)
+{
+    const nh_history &h = q->halo.history;
+    const bool sampled = q->halo.mass_kind == NH_MASS_TABLE || q->halo.conc_kind == NH_CONC_TABLE ||
+                         q->halo.kappa_kind == NH_KAPPA_TABLE;
+    if (!sampled || q->integ.method == NH_RK4) return true;
+    // at most every sample interval can hold a piece of [u_end, u_start]
+    return (n_max - 1) / (h.n - 1) >= 3;
+}
+
+void build_interp_table(const Physics &ph, const TableGrid &tg, double *out, int threads)
+{
+    const int n_tab = tg.n;
     auto rows = [&](int i0, int i1) {
         for (int i = i0; i < i1; ++i) {
-            double u = (i == n_tab - 1) ? ph.u_start : u_end + (double)i * du;
-            ph.coef(u, out + (size_t)i * NCOL);
+            // smooth histories end exactly on u_start; sampled ones on a knot
+            double u = (i == n_tab - 1 && !ph.sampled()) ? ph.u_start : tg.u0 + (double)i * tg.du;
+            ph.coef(u, out + (size_t)i * NCOL, true);
         }
     };
     // rows are independent: a few host threads may share a large table (the

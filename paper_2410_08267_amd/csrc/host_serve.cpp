@@ -143,7 +143,7 @@ struct ServeState {
     size_t lanes_cap = 0, wg_cap = 0;
     bool resume = false;
     bool use_graph = true;            // slices as replays of a HIP graph (per table layout)
-    SliceGraph graph[2];              // [0] five columns, [1] six
+    SliceGraph graph[4];              // [five | six columns] + 2 [with power-law factors]
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // pinned host mirrors; h_desc changes under `mu`, h_desc_up is the snapshot
@@ -199,10 +199,13 @@ int start_session(nh_context *ctx, ServeState &S, bool f32c)
     if (rc != NH_OK) return rc;
     HIPCHK(hipSetDevice(ctx->device));
     // one grid for every slice (saved lanes are indexed by it): what fits for both layouts
-    int g5 = 0, g6 = 0;
-    HIPCHK(slice_capacity(f32c, NCOL - 1, S.slots, S.n_tab, S.block, ctx->n_cu, &g5));
-    HIPCHK(slice_capacity(f32c, NCOL, S.slots, S.n_tab, S.block, ctx->n_cu, &g6));
-    S.grid = std::min(g5, g6);
+    S.grid = 1 << 30;
+    for (int nc : {(int)NCOL - 1, (int)NCOL})
+        for (bool pow : {false, true}) {
+            int g = 0;
+            HIPCHK(slice_capacity(f32c, nc, S.slots, pow, S.n_tab, S.block, ctx->n_cu, &g));
+            S.grid = std::min(S.grid, g);
+        }
     const size_t lanes = (size_t)S.grid * S.block;
     if (lanes > S.lanes_cap) {
         if (S.d_lanes) HIPCHK(hipFree(S.d_lanes));
@@ -301,9 +304,11 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
                             hipMemcpyHostToDevice, s));
     }
     int nc = NCOL - 1;
+    bool pow = false;
     for (size_t i = 0; i < run.size(); ++i) {
         S.h_order[i] = run[i]->slot;
         nc = std::max(nc, run[i]->desc.nc);
+        pow = pow || run[i]->desc.P.hist;
     }
     SliceArgs A{};
     A.reqs = S.d_desc;
@@ -340,7 +345,7 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
     const bool f32c = S.precision == NH_FP32C;
     if (S.use_graph) {
         // uploads, in-flight clear, slice kernel and read-backs as one graph launch
-        SliceGraph &G = S.graph[nc == NCOL ? 1 : 0];
+        SliceGraph &G = S.graph[(nc == NCOL ? 1 : 0) + (pow ? 2 : 0)];
         if (!G.exec) {
             SliceGraphBufs b{};
             b.d_desc = S.d_desc;
@@ -355,7 +360,7 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
             b.order_bytes = SERVE_CAP * sizeof(int);
             b.next_bytes = SERVE_CAP * sizeof(unsigned long long);
             b.inflight_bytes = SERVE_CAP * sizeof(unsigned int);
-            WCHK(slice_graph_build(G, b, A, f32c, nc, S.slots, S.grid, S.block));
+            WCHK(slice_graph_build(G, b, A, f32c, nc, S.slots, pow, S.grid, S.block));
         }
         WCHK(hipEventRecord(S.ev0, s));
         WCHK(slice_graph_launch(G, A, s));
@@ -366,7 +371,7 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
             WCHK(hipMemcpyAsync(S.d_order, S.h_order, run.size() * sizeof(int), hipMemcpyHostToDevice, s));
         WCHK(launch_fill_u64((unsigned long long *)S.d_inflight, SERVE_CAP / 2, 0ull, s));
         WCHK(hipEventRecord(S.ev0, s));
-        WCHK(launch_slice(A, f32c, nc, S.slots, S.grid, S.block, s));
+        WCHK(launch_slice(A, f32c, nc, S.slots, pow, S.grid, S.block, s));
         WCHK(hipEventRecord(S.ev1, s));
         WCHK(hipMemcpyAsync(S.h_next, S.d_next, SERVE_CAP * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         WCHK(hipMemcpyAsync(S.h_inflight, S.d_inflight, SERVE_CAP * sizeof(unsigned int), hipMemcpyDeviceToHost,
@@ -567,6 +572,11 @@ int nh_submit(nh_context *ctx, const nh_request *req, uint64_t *ticket)
     }
     if (S->free_slots.empty()) return set_err(ctx, NH_EBUSY, "%d requests are admitted already", SERVE_CAP);
     const Staged lay = stage_layout(req, S->n_tab);
+    if (!sampled_table_fits(req, S->n_tab)) {
+        if (S->active.empty() && S->queued.empty()) S->precision = -1;
+        return set_err(ctx, NH_EINVAL, "%d history samples need at least 3 of the %d table nodes per sample interval",
+                       req->halo.history.n, S->n_tab);
+    }
     const long long n_traj = n_traj_of(req);
     const size_t bytes = ticket_bytes(lay, n_traj, req->grid.n_r);
     size_t off = 0;

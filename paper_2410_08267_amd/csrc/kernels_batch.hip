@@ -17,50 +17,52 @@ namespace nh {
 // FP64 coefficients from rows of STRIDE doubles of which the first NC columns
 // are interpolated; R comes from its column for requests with a moving
 // compensation radius (nc == NCOL, possible only when NC == NCOL), else it is
-// the request's constant.
-template <int NC, int STRIDE = NC>
+// the request's constant.  HIST: launches holding requests with non-smooth
+// histories keep each request's stencils inside its spline pieces (Knots) and
+// apply its power-law factor of K and Kc (PowFactor); for smooth requests both
+// leave the values unchanged bit for bit (one piece, factor exactly 1).
+template <int NC, int STRIDE = NC, bool HIST = false>
 struct TabCoefB {
     const double *tab;
     int nc, n_tab;
     double u0, inv_du, R_const;
+    PowFactor pw;
+    Knots kn;
     __device__ __forceinline__ void at(double u, double c[NCOL], double &R) const
     {
-        coef_interp<NC, STRIDE>(tab, n_tab, u0, inv_du, u, c);
+        coef_interp<NC, STRIDE, HIST>(tab, n_tab, u0, inv_du, kn, u, c);
         R = (NC == NCOL && nc == NCOL) ? c[COL_R] : R_const;
+        if constexpr (HIST) {
+            const double f = pow_factor(pw, u);
+            c[COL_K] *= f;
+            c[COL_KC] *= f;
+        }
     }
     // four rows per stage: the shared window of stages 2 and 3 costs registers
     // this kernel does not have (the values are the same either way)
     static constexpr bool paired = false;
 };
 
-// The same from an FP32 table slot (rows of NC floats).
+// Copy request q's table into a slot: FP64 rows of NC doubles (NC of the
+// staged NCOL columns), or the FP32C layout (stage_f32c_table), by the threads
+// first, first + step, ...
 template <int NC>
-struct TabCoef32B {
-    const float *tab;
-    int nc, n_tab;
-    double u0, inv_du;
-    float R_const;
-    __device__ __forceinline__ void at(double u, float c[NCOL], float &R) const
-    {
-        const Stencil4f w = stencil32_at(n_tab, u0, inv_du, u);
-        const float *row = tab + w.row * NC;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) c[k] = stencil32_col(w, row, NC, k);
-        R = (NC == NCOL && nc == NCOL) ? c[COL_R] : R_const;
-    }
-};
-
-// Copy the first NC columns of request q's table rows into a slot (rows of
-// NC), by the threads first, first + step, ...
-template <int NC, class T>
-__device__ __forceinline__ void copy_table(T *dst, const BatchReq &q, int first, int step)
+__device__ __forceinline__ void copy_table(double *dst, const BatchReq &q, int first, int step)
 {
     const int n = q.P.n_tab * NC;
     const double *src = q.g.tab;
     for (int i = first; i < n; i += step) {
         const int node = i / NC, col = i - node * NC;
-        dst[i] = (T)src[node * NCOL + col];
+        dst[i] = src[node * NCOL + col];
     }
+}
+
+// Bytes of one FP32C table slot (kept a multiple of 16 so the next slot's
+// FP64 rows stay aligned).
+template <int NC>
+__host__ __device__ constexpr size_t f32c_slot_bytes(int n_tab)
+{
+    return (f32c_table_bytes<NC>(n_tab) + 15) & ~(size_t)15;
 }
 
 // Initial position and velocity of trajectory t = (k n_y + j) n_mu + l.
@@ -171,16 +173,16 @@ __device__ __forceinline__ void unpack32(const LaneSave &s, Lane32 &L, double &v
 }
 
 // Per-lane parameters of a trajectory of request q whose table sits in `slot`.
-template <int NC>
+template <int NC, bool HIST>
 struct Lane64Params {
-    TabCoefB<NC> cf;
+    TabCoefB<NC, NC, HIST> cf;
     DpCtl ctl;
 };
-template <int NC>
-__device__ __forceinline__ void setup64(const BatchReq &q, const double *slot, Lane64Params<NC> &p)
+template <int NC, bool HIST>
+__device__ __forceinline__ void setup64(const BatchReq &q, const double *slot, Lane64Params<NC, HIST> &p)
 {
     const TrajParams &P = q.P;
-    p.cf = TabCoefB<NC>{slot, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
+    p.cf = TabCoefB<NC, NC, HIST>{slot, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     p.ctl.u_end = P.u_end;
     p.ctl.rtol = P.rtol;
     p.ctl.atol_x = P.atol_x;
@@ -189,20 +191,22 @@ __device__ __forceinline__ void setup64(const BatchReq &q, const double *slot, L
     p.ctl.max_steps = (int)P.max_steps;
 }
 
-template <int NC>
+template <int NC, bool HIST>
 struct Lane32Params {
-    TabCoef32B<NC> cf;
-    TabCoefB<NC, NCOL> cf64;    // the promoted FP64 attempts read the FP64 table from HBM
+    TabCoef32<NC, HIST> cf;
+    TabCoefB<NC, NCOL, HIST> cf64;    // the promoted FP64 attempts read the FP64 table from HBM
     DpCtl32 ctl;
     DpCtl ctl64;
     double h_fp64;
 };
-template <int NC>
-__device__ __forceinline__ void setup32(const BatchReq &q, const float *slot, Lane32Params<NC> &p)
+template <int NC, bool HIST>
+__device__ __forceinline__ void setup32(const BatchReq &q, const char *slot, Lane32Params<NC, HIST> &p)
 {
     const TrajParams &P = q.P;
-    p.cf = TabCoef32B<NC>{slot, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30)};
-    p.cf64 = TabCoefB<NC, NCOL>{q.g.tab, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
+    const double *t64 = (const double *)slot;
+    p.cf = TabCoef32<NC, HIST>{t64, (const float *)(t64 + (size_t)P.n_tab * F32C_T64), q.nc, P.n_tab,
+                              P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30), P.pw, P.kn};
+    p.cf64 = TabCoefB<NC, NCOL, HIST>{q.g.tab, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     f32c_controls(P, p.ctl, p.ctl64);
     p.h_fp64 = P.h_fp64;
 }
@@ -213,7 +217,7 @@ __device__ __forceinline__ void setup32(const BatchReq &q, const float *slot, La
 
 // FP64 slices run up to 1024 threads per workgroup (four waves per SIMD); the
 // FP32-compensated lane state needs more than the 128 VGPRs that allows.
-template <int NC, int SLOTS>
+template <int NC, int SLOTS, bool HIST>
 __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
 {
     extern __shared__ double lds64[];
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
     int rq = 0, sl = 0;
     double v0n = 1.0;
     Lane64 L{};
-    Lane64Params<NC> lp{};
+    Lane64Params<NC, HIST> lp{};
     LaneSave *const my = A.lane_save ? A.lane_save + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) : nullptr;
     if (A.resume && my) {
         const LaneSave sv = *my;
@@ -314,22 +318,25 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
 // FP32-compensated slice kernel
 // ---------------------------------------------------------------------------
 
-template <int NC, int SLOTS>
+template <int NC, int SLOTS, bool HIST>
 __global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
 {
-    extern __shared__ float lds32b[];
+    extern __shared__ double lds32b[];
     __shared__ WgSched S;
-    const int slot_n = A.n_tab * NC;
+    char *const slots = (char *)lds32b;
+    const size_t slot_n = f32c_slot_bytes<NC>(A.n_tab);
     if (threadIdx.x == 0) sched_init(S, A);
     __syncthreads();
     for (int s = 0; s < SLOTS; ++s)
-        if (S.slot_req[s] >= 0) copy_table<NC>(lds32b + s * slot_n, A.reqs[S.slot_req[s]], threadIdx.x, blockDim.x);
+        if (S.slot_req[s] >= 0)
+            stage_f32c_table<NC>(slots + s * slot_n, A.reqs[S.slot_req[s]].g.tab, A.reqs[S.slot_req[s]].P.n_tab,
+                                 threadIdx.x, blockDim.x);
 
     long long t = -1;
     int rq = 0, sl = 0;
     double v0n = 1.0;
     Lane32 L{};
-    Lane32Params<NC> lp{};
+    Lane32Params<NC, HIST> lp{};
     LaneSave *const my = A.lane_save ? A.lane_save + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) : nullptr;
     if (A.resume && my) {
         const LaneSave sv = *my;
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
             rq = sv.req;
             sl = sv.slot;
             unpack32(sv, L, v0n);
-            setup32(A.reqs[rq], lds32b + sl * slot_n, lp);
+            setup32(A.reqs[rq], slots + sl * slot_n, lp);
             __hip_atomic_fetch_add(&S.active[sl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
@@ -353,7 +360,8 @@ __global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
             int r, s;
             long long p;
             wave_acquire<SLOTS>(S, A, mask, r, p, s, [&](int slot, int req) {
-                copy_table<NC>(lds32b + slot * slot_n, A.reqs[req], (int)__lane_id(), 64);
+                stage_f32c_table<NC>(slots + slot * slot_n, A.reqs[req].g.tab, A.reqs[req].P.n_tab, (int)__lane_id(),
+                                     64);
             });
             if (r >= 0) {
                 const BatchReq &q = A.reqs[r];
@@ -365,7 +373,7 @@ __global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
                     slot_release(S, s);
                     t = -1;
                 } else {
-                    setup32(q, lds32b + s * slot_n, lp);
+                    setup32(q, slots + s * slot_n, lp);
                     double x0, vx0, vy0;
                     initial_state(q, t, x0, vx0, vy0);
                     v0n = sqrt(norm2(vx0, vy0));
@@ -448,31 +456,41 @@ __global__ __launch_bounds__(256) void k_reduce_stats_batch(const BatchReq *__re
 
 size_t slice_lds_bytes(bool f32c, int nc, int slots, int n_tab)
 {
-    return (size_t)slots * n_tab * nc * (f32c ? sizeof(float) : sizeof(double));
+    if (f32c)
+        return (size_t)slots * (nc == NCOL ? f32c_slot_bytes<NCOL>(n_tab) : f32c_slot_bytes<NCOL - 1>(n_tab));
+    return (size_t)slots * n_tab * nc * sizeof(double);
 }
 
 int slice_max_table_nodes(bool f32c, int nc, int slots)
 {
     const size_t avail = 160 * 1024 - sizeof(WgSched) - 256;
-    return (int)(avail / ((size_t)slots * nc * (f32c ? sizeof(float) : sizeof(double))));
+    const size_t per_node = f32c ? F32C_T64 * sizeof(double) + (nc - F32C_T64) * sizeof(float) : nc * sizeof(double);
+    // one node of slack per slot for the alignment of the next slot
+    return (int)(avail / ((size_t)slots * per_node)) - 1;
 }
 
-template <int NC, int SLOTS>
+template <int NC, int SLOTS, bool HIST>
 static const void *slice_fn(bool f32c)
 {
-    return f32c ? (const void *)k_slice_f32c<NC, SLOTS> : (const void *)k_slice_f64<NC, SLOTS>;
+    return f32c ? (const void *)k_slice_f32c<NC, SLOTS, HIST> : (const void *)k_slice_f64<NC, SLOTS, HIST>;
 }
 
-static const void *slice_fn(bool f32c, int nc, int slots)
+template <bool HIST>
+static const void *slice_fn_hist(bool f32c, int nc, int slots)
 {
-    if (nc == NCOL) return slots == 2 ? slice_fn<NCOL, 2>(f32c) : slice_fn<NCOL, 1>(f32c);
-    return slots == 2 ? slice_fn<NCOL - 1, 2>(f32c) : slice_fn<NCOL - 1, 1>(f32c);
+    if (nc == NCOL) return slots == 2 ? slice_fn<NCOL, 2, HIST>(f32c) : slice_fn<NCOL, 1, HIST>(f32c);
+    return slots == 2 ? slice_fn<NCOL - 1, 2, HIST>(f32c) : slice_fn<NCOL - 1, 1, HIST>(f32c);
+}
+
+static const void *slice_fn(bool f32c, int nc, int slots, bool pow)
+{
+    return pow ? slice_fn_hist<true>(f32c, nc, slots) : slice_fn_hist<false>(f32c, nc, slots);
 }
 
 // Workgroups that fit the device at once for this slice configuration.
-hipError_t slice_capacity(bool f32c, int nc, int slots, int n_tab, int block, int n_cu, int *grid)
+hipError_t slice_capacity(bool f32c, int nc, int slots, bool pow, int n_tab, int block, int n_cu, int *grid)
 {
-    const void *fn = slice_fn(f32c, nc, slots);
+    const void *fn = slice_fn(f32c, nc, slots, pow);
     const size_t lds = slice_lds_bytes(f32c, nc, slots, n_tab);
     int per_cu = 0;
     const hipError_t e = occupancy_cached(fn, block, lds, &per_cu);
@@ -482,11 +500,12 @@ hipError_t slice_capacity(bool f32c, int nc, int slots, int n_tab, int block, in
     return hipSuccess;
 }
 
-hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, int grid, int block, hipStream_t s)
+hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, bool pow, int grid, int block,
+                        hipStream_t s)
 {
     const size_t lds = slice_lds_bytes(f32c, nc, slots, A.n_tab);
     void *args[] = {(void *)&A};
-    return hipLaunchKernel(slice_fn(f32c, nc, slots), dim3(grid), dim3(block), args, lds, s);
+    return hipLaunchKernel(slice_fn(f32c, nc, slots, pow), dim3(grid), dim3(block), args, lds, s);
 }
 
 // One serving slice as a graph: upload the descriptors and the run order,
@@ -495,7 +514,7 @@ hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, int gr
 // kernel's arguments change every slice and are set on the instantiated graph
 // before each launch (slice_graph_launch).
 hipError_t slice_graph_build(SliceGraph &G, const SliceGraphBufs &b, const SliceArgs &A, bool f32c, int nc,
-                             int slots, int grid, int block)
+                             int slots, bool pow, int grid, int block)
 {
     slice_graph_destroy(G);
     hipError_t e = hipGraphCreate(&G.graph, 0);
@@ -520,7 +539,7 @@ hipError_t slice_graph_build(SliceGraph &G, const SliceGraphBufs &b, const Slice
     if ((e = hipGraphAddKernelNode(&clear, G.graph, nullptr, 0, &kp)) != hipSuccess) return e;
     G.args = A;
     G.params = hipKernelNodeParams{};
-    G.params.func = const_cast<void *>(slice_fn(f32c, nc, slots));
+    G.params.func = const_cast<void *>(slice_fn(f32c, nc, slots, pow));
     G.params.gridDim = dim3(grid);
     G.params.blockDim = dim3(block);
     G.params.sharedMemBytes = (unsigned)slice_lds_bytes(f32c, nc, slots, A.n_tab);
@@ -538,6 +557,7 @@ hipError_t slice_graph_build(SliceGraph &G, const SliceGraphBufs &b, const Slice
     G.f32c = f32c;
     G.nc = nc;
     G.slots = slots;
+    G.pow = pow;
     G.grid = grid;
     G.block = block;
     return hipSuccess;

@@ -3,13 +3,15 @@
 // State: positions in FP32 with a Kahan compensation term each (the carried
 // rounding error of the accumulated position), velocities in FP32, time u and
 // step h in FP64 (u also indexes the coefficient table).  Right-hand sides,
-// stage sums, error norm and step control run in FP32 on an FP32 copy of the
-// FP64 coefficient table held in LDS.  An attempt whose |h| is below a
-// threshold (the short steps the controller takes near pericentre) runs the
-// FP64 step instead, on the FP64 table, after re-evaluating the first stage in
-// FP64.  The speed ratio and the quadrature downstream stay FP64.  The choice
-// is per lane, so a trajectory's result does not depend on which trajectories
-// share its wavefront.
+// stage sums, error norm and step control run in FP32.  The coefficient table
+// stays FP64 for the H(z)-derived drift and kick columns (interpolated in FP64,
+// rounded to FP32 afterwards); the halo's radii and concentration are an FP32
+// copy; both sit in LDS.  An attempt whose |h| is below a threshold (the short
+// steps the controller takes near pericentre) runs the FP64 step instead, on
+// the FP64 table, after re-evaluating the first stage in FP64.  The speed ratio
+// and the quadrature downstream stay FP64.  The choice is per lane, so a
+// trajectory's result does not depend on which trajectories share its
+// wavefront.
 #include <hip/hip_runtime.h>
 
 #include "nh_dp5_f32.h"
@@ -19,20 +21,18 @@ namespace nh {
 
 // CULL: some start radius lies beyond R_exit (otherwise no relic can be culled
 // and the test is left out of the trajectory loop)
-template <int NC, bool CULL>
+template <int NC, bool CULL, bool HIST>
 __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, TrajOut o,
                                                    unsigned long long *counter)
 {
-    extern __shared__ float lds32[];
-    for (int i = threadIdx.x; i < P.n_tab * NC; i += blockDim.x) {
-        const int node = i / NC, col = i - node * NC;
-        lds32[i] = (float)g.tab[node * NCOL + col];
-    }
+    extern __shared__ double lds_mix[];
+    stage_f32c_table<NC>(lds_mix, g.tab, P.n_tab, threadIdx.x, blockDim.x);
     __syncthreads();
 
-    const TabCoef32<NC> cf{lds32, P.n_tab, P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30)};
+    const TabCoef32<NC, HIST> cf{lds_mix, (const float *)(lds_mix + (size_t)P.n_tab * F32C_T64), NC, P.n_tab,
+                                P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30), P.pw, P.kn};
     // the promoted FP64 steps read the FP64 table from global memory (rows of NCOL)
-    const TabCoef<NC, NCOL> cf64{g.tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
+    const TabCoef<NC, NCOL, HIST> cf64{g.tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     DpCtl32 ctl;
     DpCtl ctl64;
     f32c_controls(P, ctl, ctl64);
@@ -80,16 +80,16 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
     }
 }
 
-template <int NC, bool CULL>
+template <int NC, bool CULL, bool HIST>
 static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                  unsigned long long *counter, int n_cu, hipStream_t s)
 {
     // default 512 (a single profile's tail grows with more lanes); at most the
     // launch bound, 768 (the lane state fits 170 VGPRs: three waves per SIMD)
     const int B = P.block > 0 ? (P.block < 768 ? P.block : 768) : 512;
-    const size_t lds = (size_t)P.n_tab * NC * sizeof(float);
+    const size_t lds = f32c_table_bytes<NC>(P.n_tab);
     int per_cu = 0;
-    const hipError_t e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL>, B, lds, &per_cu);
+    const hipError_t e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL, HIST>, B, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long long grid = (long long)n_cu * per_cu;
@@ -97,20 +97,28 @@ static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const T
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
-    auto *kern = k_dp5_f32c<NC, CULL>;
+    auto *kern = k_dp5_f32c<NC, CULL, HIST>;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
     return hipGetLastError();
+}
+
+template <bool HIST>
+static hipError_t launch_f32c_hist(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                                  unsigned long long *counter, int n_cu, hipStream_t s)
+{
+    const bool cull = P.cull_D > 0.0;
+    if (P.R_const > 0.0)
+        return cull ? launch_f32c_nc<NCOL - 1, true, HIST>(P, g, o, counter, n_cu, s)
+                    : launch_f32c_nc<NCOL - 1, false, HIST>(P, g, o, counter, n_cu, s);
+    return cull ? launch_f32c_nc<NCOL, true, HIST>(P, g, o, counter, n_cu, s)
+                : launch_f32c_nc<NCOL, false, HIST>(P, g, o, counter, n_cu, s);
 }
 
 hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                            unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    const bool cull = P.cull_D > 0.0;
-    if (P.R_const > 0.0)
-        return cull ? launch_f32c_nc<NCOL - 1, true>(P, g, o, counter, n_cu, s)
-                    : launch_f32c_nc<NCOL - 1, false>(P, g, o, counter, n_cu, s);
-    return cull ? launch_f32c_nc<NCOL, true>(P, g, o, counter, n_cu, s)
-                : launch_f32c_nc<NCOL, false>(P, g, o, counter, n_cu, s);
+    return P.hist ? launch_f32c_hist<true>(P, g, o, counter, n_cu, s)
+                  : launch_f32c_hist<false>(P, g, o, counter, n_cu, s);
 }
 
 }  // namespace nh

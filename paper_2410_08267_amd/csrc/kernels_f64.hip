@@ -138,7 +138,7 @@ constexpr int DP5_DEFAULT_BLOCK = 768;
 // CULL: some start radius lies beyond R_exit.  Without one no relic can be
 // culled, and the kernel leaves the test out: its branch alone costs the
 // trajectory loop a few percent in register moves.
-template <int NC, bool CULL>
+template <int NC, bool CULL, bool HIST>
 __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
                                                              unsigned long long *counter)
 {
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridP
     }
     __syncthreads();
 
-    const TabCoef<NC> cf{lds_tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const};
+    const TabCoef<NC, NC, HIST> cf{lds_tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     DpCtl ctl;
     ctl.u_end = P.u_end;
     ctl.rtol = P.rtol;
@@ -311,14 +311,14 @@ hipError_t occupancy_cached(const void *fn, int block, size_t lds, int *per_cu)
     return hipSuccess;
 }
 
-template <int NC, bool CULL>
+template <int NC, bool CULL, bool HIST>
 static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                 unsigned long long *counter, int n_cu, hipStream_t s)
 {
     const int B = P.block > 0 ? P.block : DP5_DEFAULT_BLOCK;
     const size_t lds = (size_t)P.n_tab * NC * sizeof(double);
     int per_cu = 0;
-    const hipError_t e = occupancy_cached((const void *)k_dp5_f64<NC, CULL>, B, lds, &per_cu);
+    const hipError_t e = occupancy_cached((const void *)k_dp5_f64<NC, CULL, HIST>, B, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long long grid = (long long)n_cu * per_cu;
@@ -326,20 +326,28 @@ static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const Tr
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
-    auto *kern = k_dp5_f64<NC, CULL>;
+    auto *kern = k_dp5_f64<NC, CULL, HIST>;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
     return hipGetLastError();
+}
+
+template <bool HIST>
+static hipError_t launch_dp5_hist(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                                 unsigned long long *counter, int n_cu, hipStream_t s)
+{
+    const bool cull = P.cull_D > 0.0;
+    if (P.R_const > 0.0)
+        return cull ? launch_dp5_nc<NCOL - 1, true, HIST>(P, g, o, counter, n_cu, s)
+                    : launch_dp5_nc<NCOL - 1, false, HIST>(P, g, o, counter, n_cu, s);
+    return cull ? launch_dp5_nc<NCOL, true, HIST>(P, g, o, counter, n_cu, s)
+                : launch_dp5_nc<NCOL, false, HIST>(P, g, o, counter, n_cu, s);
 }
 
 hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                           unsigned long long *counter, int n_cu, hipStream_t s)
 {
-    const bool cull = P.cull_D > 0.0;
-    if (P.R_const > 0.0)
-        return cull ? launch_dp5_nc<NCOL - 1, true>(P, g, o, counter, n_cu, s)
-                    : launch_dp5_nc<NCOL - 1, false>(P, g, o, counter, n_cu, s);
-    return cull ? launch_dp5_nc<NCOL, true>(P, g, o, counter, n_cu, s)
-                : launch_dp5_nc<NCOL, false>(P, g, o, counter, n_cu, s);
+    return P.hist ? launch_dp5_hist<true>(P, g, o, counter, n_cu, s)
+                  : launch_dp5_hist<false>(P, g, o, counter, n_cu, s);
 }
 
 hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,

@@ -47,6 +47,7 @@ struct nh_context {
     int queue_order = nh::ORDER_NATURAL;
     bool free_exit = true;
     double h_fp64 = 1.0e-5;                          // FP32C: |h| below this runs in FP64
+    double rtol32 = 1.0e-7;                          // FP32C: tolerance floor of the FP32 attempts
     int table_nodes = 0;                             // 0: default_table_nodes()
     int block_threads = 0;                           // Dormand-Prince workgroup size (0: default)
     int batch_slots = 0;                             // tables per workgroup, batched form (0: default)

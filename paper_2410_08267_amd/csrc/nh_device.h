@@ -129,6 +129,30 @@ __device__ __forceinline__ Stencil4 stencil_at(int n_tab, double u0, double inv_
     return w;
 }
 
+// The same restricted to the piece of a sampled history that holds u (Knots):
+// the stencil's first node is kept within [k m, (k+1) m - 3] for the piece
+// [k m, (k+1) m] of table nodes.  With one piece (m = n_tab - 1) this is
+// stencil_at, bit for bit.
+__device__ __forceinline__ Stencil4 stencil_at_knots(int n_tab, double u0, double inv_du, const Knots &kn, double u)
+{
+    const double s = fma(u, inv_du, -(u0 * inv_du));
+    const int i = (int)s;
+    const int lo = (int)(s * kn.inv_m) * kn.m;
+    const int hi = min(lo + kn.m - 3, n_tab - 4);
+    const int row = min(max(i - 1, lo), hi);
+    Stencil4 w;
+    w.row = row;
+    stencil_weights(s - (double)(row + 1), w);
+    return w;
+}
+
+template <bool HIST>
+__device__ __forceinline__ Stencil4 table_stencil(int n_tab, double u0, double inv_du, const Knots &kn, double u)
+{
+    if constexpr (HIST) return stencil_at_knots(n_tab, u0, inv_du, kn, u);
+    else return stencil_at(n_tab, u0, inv_du, u);
+}
+
 // Column k of the interpolated coefficients from rows of `stride` doubles.
 // The sum runs node by node as one FMA chain, so that the five-node form
 // below reproduces it bit for bit.
@@ -140,11 +164,11 @@ __device__ __forceinline__ double stencil_col(const Stencil4 &w, const double *r
 // Coefficients at u from the uniform table, rows of STRIDE doubles of which
 // the first NC columns are used (NC = NCOL - 1 when the compensation radius R
 // is constant and passed separately).
-template <int NC, int STRIDE = NC>
+template <int NC, int STRIDE = NC, bool HIST = false>
 __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int n_tab, double u0,
-                                            double inv_du, double u, double c[NCOL])
+                                            double inv_du, const Knots &kn, double u, double c[NCOL])
 {
-    const Stencil4 w = stencil_at(n_tab, u0, inv_du, u);
+    const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
     const double *row = tab + w.row * STRIDE;
 #pragma unroll
     for (int k = 0; k < NC; ++k) c[k] = stencil_col(w, row, STRIDE, k);
@@ -157,13 +181,13 @@ __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int 
 // apart read P's own four rows.  Either way the values equal those of two
 // coef_interp calls bit for bit: an FMA with a zero weight adds an exact zero.
 // The fifth row index is clamped to the table, where its weight is always zero.
-template <int NC, int STRIDE = NC>
+template <int NC, int STRIDE = NC, bool HIST = false>
 __device__ __forceinline__ void coef_interp2(const double *__restrict__ tab, int n_tab, double u0,
-                                             double inv_du, double uP, double uQ, double cP[NCOL],
-                                             double cQ[NCOL])
+                                             double inv_du, const Knots &kn, double uP, double uQ,
+                                             double cP[NCOL], double cQ[NCOL])
 {
-    const Stencil4 wQ = stencil_at(n_tab, u0, inv_du, uQ);
-    const Stencil4 wP = stencil_at(n_tab, u0, inv_du, uP);
+    const Stencil4 wQ = table_stencil<HIST>(n_tab, u0, inv_du, kn, uQ);
+    const Stencil4 wP = table_stencil<HIST>(n_tab, u0, inv_du, kn, uP);
     const double *row = tab + wQ.row * STRIDE;
     const double *row4 = tab + min(wQ.row + 4, n_tab - 1) * STRIDE;
     const int d = wP.row - wQ.row;
@@ -181,6 +205,23 @@ __device__ __forceinline__ void coef_interp2(const double *__restrict__ tab, int
 #pragma unroll
         for (int k = 0; k < NC; ++k) cP[k] = stencil_col(wP, rp, STRIDE, k);
     }
+}
+
+// The power-law factor of K and Kc at u (PowFactor): xi^alpha of the paper's
+// growth model and kappa = 1 + a [z/(1+z)]^b, from the library's FP64 exp,
+// expm1 and log (a few ulp); 0^alpha = 0 (alpha > 0 wherever it applies).
+__device__ __noinline__ double pow_factor(const PowFactor &f, double u)
+{
+    double s = 1.0;
+    if (f.on_mass) {
+        const double xi = fmin(fmax((f.zf1 - exp(-u)) * f.inv_dz, 0.0), 1.0);
+        s = xi > 0.0 ? exp(f.alpha * log(xi)) : 0.0;
+    }
+    if (f.on_kappa) {
+        const double zr = -expm1(u);   // z / (1+z)
+        s *= 1.0 + (zr > 0.0 ? f.ka * exp(f.kb * log(zr)) : 0.0);
+    }
+    return s;
 }
 
 // dY/du for Y = (x, y, vx, vy): dx/du = A v, dv/du = -g x with

@@ -29,16 +29,25 @@ constexpr double e7 = 0.0 - 1.0 / 40.0;
 }  // namespace dp
 
 // Coefficient source: an FP64 table (LDS rows of NC doubles, or the staged
-// global copy with rows of NCOL).  NC = 5 when R is constant.
-template <int NC, int STRIDE = NC>
+// global copy with rows of NCOL).  NC = 5 when R is constant.  HIST: the
+// request's history is not smooth: stencils stay inside spline pieces (Knots)
+// and K and Kc take their power-law factor (PowFactor) here.
+template <int NC, int STRIDE = NC, bool HIST = false>
 struct TabCoef {
     const double *tab;
     int n_tab;
     double u0, inv_du, R_const;
+    PowFactor pw;
+    Knots kn;
     __device__ __forceinline__ void at(double u, double c[NCOL], double &R) const
     {
-        coef_interp<NC, STRIDE>(tab, n_tab, u0, inv_du, u, c);
+        coef_interp<NC, STRIDE, HIST>(tab, n_tab, u0, inv_du, kn, u, c);
         R = (NC == NCOL) ? c[COL_R] : R_const;
+        if constexpr (HIST) {
+            const double f = pow_factor(pw, u);
+            c[COL_K] *= f;
+            c[COL_KC] *= f;
+        }
     }
     // coefficients at uP and at uQ <= uP, a fraction of a step apart, from one
     // five-row window where they share it
@@ -46,9 +55,16 @@ struct TabCoef {
     __device__ __forceinline__ void at2(double uP, double uQ, double cP[NCOL], double &RP, double cQ[NCOL],
                                         double &RQ) const
     {
-        coef_interp2<NC, STRIDE>(tab, n_tab, u0, inv_du, uP, uQ, cP, cQ);
+        coef_interp2<NC, STRIDE, HIST>(tab, n_tab, u0, inv_du, kn, uP, uQ, cP, cQ);
         RP = (NC == NCOL) ? cP[COL_R] : R_const;
         RQ = (NC == NCOL) ? cQ[COL_R] : R_const;
+        if constexpr (HIST) {
+            const double fP = pow_factor(pw, uP), fQ = pow_factor(pw, uQ);
+            cP[COL_K] *= fP;
+            cP[COL_KC] *= fP;
+            cQ[COL_K] *= fQ;
+            cQ[COL_KC] *= fQ;
+        }
     }
 };
 

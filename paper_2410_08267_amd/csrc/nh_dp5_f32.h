@@ -4,8 +4,8 @@
 // State: positions in FP32 with a Kahan compensation term each (the carried
 // rounding error of the accumulated position), velocities in FP32, time u and
 // step h in FP64 (u also indexes the coefficient table).  Right-hand sides,
-// stage sums, error norm and step control run in FP32 on an FP32 copy of the
-// FP64 coefficient table.
+// stage sums, error norm and step control run in FP32; the drift and kick
+// coefficients are interpolated in FP64 and rounded afterwards (TabCoef32).
 #pragma once
 
 #include "nh_dp5.h"
@@ -63,49 +63,70 @@ __device__ __forceinline__ void rhs32(const float c[NCOL], float R, float x, flo
     dvy = -g * y;
 }
 
-// Cubic interpolation from the FP32 table; the node index and fraction come
-// from the FP64 time.
-struct Stencil4f {
-    int row;
-    float wa, wb, wc, wd;
-};
-__device__ __forceinline__ Stencil4f stencil32_at(int n_tab, double u0, double inv_du, double u)
-{
-    const double sd = (u - u0) * inv_du;
-    int i = (int)sd;
-    i = i < 1 ? 1 : (i > n_tab - 3 ? n_tab - 3 : i);
-    const float p = (float)(sd - (double)i);
-    const float pm = p + 1.0f, p1 = p - 1.0f, p2 = p - 2.0f;
-    Stencil4f w;
-    w.row = i - 1;
-    w.wa = -(p * p1 * p2) * (1.0f / 6.0f);
-    w.wb = (pm * p1 * p2) * 0.5f;
-    w.wc = -(pm * p * p2) * 0.5f;
-    w.wd = (pm * p * p1) * (1.0f / 6.0f);
-    return w;
-}
-
-__device__ __forceinline__ float stencil32_col(const Stencil4f &w, const float *row, int stride, int k)
-{
-    return fmaf(w.wa, row[k], fmaf(w.wb, row[stride + k], fmaf(w.wc, row[2 * stride + k], w.wd * row[3 * stride + k])));
-}
-
-// Rows of NC floats (NC = NCOL - 1 when R is constant).
+// Coefficients of the FP32 attempts.  The H(z)-derived columns A, K and Kc
+// (drift and kick, Sec. II.A) are interpolated from an FP64 table (rows of 3
+// doubles) with the FP64 stencil of the FP64 kernels and rounded to FP32 only
+// afterwards (K and Kc after their power-law factor when HIST, which also keeps
+// the stencils inside spline pieces); 1/s, c and a moving R come from an FP32
+// table (rows of NC - 3 floats) with the same weights rounded to FP32.
+constexpr int F32C_T64 = 3;   // FP64 columns: A, K, Kc
 template <int NC>
+__host__ __device__ constexpr size_t f32c_table_bytes(int n_tab)
+{
+    return (size_t)n_tab * (F32C_T64 * sizeof(double) + (NC - F32C_T64) * sizeof(float));
+}
+
+template <int NC, bool HIST = false>
 struct TabCoef32 {
-    const float *tab;
-    int n_tab;
+    const double *t64;      // n_tab rows of A, K, Kc
+    const float *t32;       // n_tab rows of 1/s, c (, R)
+    int nc, n_tab;          // nc: NCOL when this request's R moves (possible only when NC == NCOL)
     double u0, inv_du;
     float R_const;
+    PowFactor pw;
+    Knots kn;
     __device__ __forceinline__ void at(double u, float c[NCOL], float &R) const
     {
-        const Stencil4f w = stencil32_at(n_tab, u0, inv_du, u);
-        const float *row = tab + w.row * NC;
+        constexpr int N32 = NC - F32C_T64;
+        const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
+        const double *r64 = t64 + w.row * F32C_T64;
+        const double A = stencil_col(w, r64, F32C_T64, 0);
+        double K = stencil_col(w, r64, F32C_T64, 1), Kc = stencil_col(w, r64, F32C_T64, 2);
+        if constexpr (HIST) {
+            const double f = pow_factor(pw, u);
+            K *= f;
+            Kc *= f;
+        }
+        c[COL_A] = (float)A;
+        c[COL_K] = (float)K;
+        c[COL_KC] = (float)Kc;
+        const float wa = (float)w.wa, wb = (float)w.wb, wc = (float)w.wc, wd = (float)w.wd;
+        const float *r32 = t32 + w.row * N32;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) c[k] = stencil32_col(w, row, NC, k);
-        R = (NC == NCOL) ? c[COL_R] : R_const;
+        for (int k = 0; k < N32; ++k)
+            c[F32C_T64 + k] = fmaf(wd, r32[3 * N32 + k], fmaf(wc, r32[2 * N32 + k], fmaf(wb, r32[N32 + k], wa * r32[k])));
+        R = (NC == NCOL && nc == NCOL) ? c[COL_R] : R_const;
     }
 };
+
+// Copy the first NC columns of FP64 table rows (stride NCOL) into the FP32C
+// layout at dst: n_tab rows of A, K, Kc (FP64), then n_tab rows of the other
+// NC - 3 columns (FP32); by the threads first, first + step, ...
+template <int NC>
+__device__ __forceinline__ void stage_f32c_table(void *dst, const double *src, int n_tab, int first, int step)
+{
+    constexpr int N32 = NC - F32C_T64;
+    double *t64 = (double *)dst;
+    float *t32 = (float *)(t64 + (size_t)n_tab * F32C_T64);
+    for (int i = first; i < n_tab * F32C_T64; i += step) {
+        const int node = i / F32C_T64, col = i - node * F32C_T64;
+        t64[i] = src[node * NCOL + col];
+    }
+    for (int i = first; i < n_tab * N32; i += step) {
+        const int node = i / N32, col = i - node * N32;
+        t32[i] = (float)src[node * NCOL + F32C_T64 + col];
+    }
+}
 
 struct Lane32 {
     float x, y, xc, yc, vx, vy;   // xc, yc: Kahan compensation of the positions
@@ -283,12 +304,13 @@ __device__ __forceinline__ int f32c_attempt(Lane32 &L, const CF32 &cf, const CF6
     return st;
 }
 
-// Step control of the FP32-compensated form: FP32 cannot resolve tolerances
-// below ~1e-6, so it integrates at max(rtol, 1e-6); the promoted FP64
-// attempts use the same tolerances.
+// Step control of the FP32-compensated form: it integrates at
+// max(rtol, P.rtol32), 1e-7 by default (the FP32 state's own rounding, ~1e-7
+// relative per step in the velocities, bounds what a tighter tolerance could
+// buy); the promoted FP64 attempts use the same tolerances.
 __device__ __forceinline__ void f32c_controls(const TrajParams &P, DpCtl32 &ctl, DpCtl &ctl64)
 {
-    const double rtol32 = fmax(P.rtol, 1.0e-6);
+    const double rtol32 = fmax(P.rtol, P.rtol32);
     ctl.u_end = P.u_end;
     ctl.rtol = (float)rtol32;
     ctl.atol_x = (float)fmax(P.atol_x, rtol32);

@@ -36,6 +36,33 @@ enum : int {
                            // transposed so that neighbouring (costly) blocks go to different workgroups
 };
 
+// Power-law factors of the coefficients K and Kc (Sec. IV.A, IV.B).  The
+// growth xi(z)^alpha of the paper's halo model and the paper's G modulation
+// kappa = 1 + a [z/(1+z)]^b have an unbounded derivative where xi or z/(1+z)
+// reaches 0 (alpha or b below 1), and xi has a kink where it is clamped; a
+// cubic table through such a function is wrong near those points by far more
+// than rounding.  Requests with either factor tabulate K and Kc without it, and
+// the kernels multiply it back, evaluated exactly, at every stage.
+struct PowFactor {
+    int on_mass;            // M = M0 xi^alpha, xi = clamp((zf1 - e^{-u}) inv_dz, 0, 1)
+    int on_kappa;           // kappa = 1 + ka s^kb, s = z/(1+z) = -expm1(u)
+    double zf1;             // 1 + z_form
+    double inv_dz;          // 1 / (z_form - z_obs)
+    double alpha;
+    double ka, kb;
+};
+
+// Sampled histories (the spline pieces between uniform knots in u, R22): the
+// table nodes are placed so that every knot is a node and every piece spans
+// m >= 3 table intervals, and the kernels keep each interpolation stencil
+// inside one piece, where the history is an exact cubic (a stencil across a
+// knot would see the jump of the spline's third derivative).  For smooth
+// histories m = n_tab - 1: one piece spans the table, the usual stencil.
+struct Knots {
+    int m;                  // table intervals per piece
+    double inv_m;           // 1 / m
+};
+
 // Everything a trajectory kernel needs about one request, passed by value.
 struct TrajParams {
     // grid
@@ -63,8 +90,16 @@ struct TrajParams {
     int order;              // ORDER_*
     int block;              // workgroup size of the persistent kernels
     int max_wg;             // > 0: at most this many workgroups (plain Dormand-Prince launches)
-    // FP32-compensated form: steps with |h| below this run in FP64
+    // FP32-compensated form: steps with |h| below this run in FP64; the FP32
+    // attempts integrate at max(rtol, rtol32)
     double h_fp64;
+    double rtol32;
+    // Dormand-Prince tables of non-smooth histories: power-law factors of K and
+    // Kc applied at every stage, stencils kept inside spline pieces; hist = 1
+    // when either is needed (the kernels' HIST variant)
+    PowFactor pw;
+    Knots kn;
+    int hist;
 };
 
 // The relic's initial distribution as the reduction evaluates it.
@@ -162,6 +197,7 @@ struct Physics {
     int geometry, compensated;
     double z_obs, u_start;  // observation epoch (the halo's reference epoch) and u = -ln(1+z_obs)
     double R_fixed;         // NH_GEOM_PAPER: comoving Lagrangian radius from M(z_obs)
+    bool sampled() const { return hist_n > 0; }
     // sampled histories (the *_TABLE kinds): samples at u_i = hist_u_min + i du and
     // the second derivatives of their not-a-knot cubic splines
     int hist_n = 0;
@@ -175,7 +211,11 @@ struct Physics {
     double conc(double z) const;
     double kappa(double z) const;
     double hubble(double z) const;
-    void coef(double u, double out[NCOL]) const;
+    // coefficients at u; factored = true leaves out the power-law factors of
+    // K and Kc (pow_factor) that the kernels apply at every stage
+    void coef(double u, double out[NCOL], bool factored = false) const;
+    double pow_factor(double u) const;   // host value of the factor at u
+    PowFactor pw{};                      // which factors this request's tables leave out
     double r_exit(double u_end) const;   // radius beyond which the force is zero at every u
     double drift(double u_end) const;    // int_{u_end}^{u_start} (1+z)^2 / H du
 };
@@ -183,7 +223,7 @@ struct Physics {
 // Physical constants (the paper states only T_nu0 = 1.95 K).
 constexpr double GM_SUN_SI = 1.32712440018e20;        // m^3 s^-2, IAU 2015 nominal
 constexpr double KPC_IN_M = 3.0856775814913673e19;    // m
-constexpr double KB_EV_PER_K = 8.617333262e-5;        // eV / K
+constexpr double KB_EV_PER_K = 1.380649e-23 / 1.602176634e-19;   // eV / K: k_B / e, exact in SI
 constexpr double C_KM_S = 299792.458;                 // km / s
 
 double nfw_I_host(double q);
@@ -198,8 +238,20 @@ int validate(const nh_request *q, char *msg, size_t msg_len);
 long long n_traj_of(const nh_request *q);
 
 // Table builders (host, FP64).
-int default_table_nodes();
-void build_interp_table(const Physics &ph, double u_end, int n_tab, double *out, int threads = 1);   // nodes on [u_end, u_start]
+int default_table_nodes(bool f32c);
+// The Dormand-Prince table's grid: n nodes u0 + i du.  Smooth histories: n_max
+// nodes on [u_end, u_start].  Sampled histories: the knots at or around
+// [u_end, u_start] with m = floor((n_max - 1) / pieces) table intervals per
+// piece (m < 3 does not fit: sampled_table_fits).
+struct TableGrid {
+    int n;
+    double u0, du;
+    int m;
+};
+TableGrid table_grid(const Physics &ph, double u_end, int n_max);
+bool sampled_table_fits(const nh_request *q, int n_max);
+// K and Kc without the request's power-law factors (Physics::pw)
+void build_interp_table(const Physics &ph, const TableGrid &tg, double *out, int threads = 1);
 void build_rk4_table(const Physics &ph, double u_end, int n_steps, double *out);
 
 }  // namespace nh

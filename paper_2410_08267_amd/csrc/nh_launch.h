@@ -28,11 +28,13 @@ hipError_t launch_fma_probe(double *out, int blocks, hipStream_t s, double *flop
 
 // slice kernels (batched and serving forms)
 // nc: table columns of the launch (NCOL when any request has a moving R);
-// slots: tables per workgroup (1 or 2)
+// slots: tables per workgroup (1 or 2); pow: some request of the launch has a
+// power-law factor of K and Kc (PowFactor)
 size_t slice_lds_bytes(bool f32c, int nc, int slots, int n_tab);
 int slice_max_table_nodes(bool f32c, int nc, int slots);
-hipError_t slice_capacity(bool f32c, int nc, int slots, int n_tab, int block, int n_cu, int *grid);
-hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, int grid, int block, hipStream_t s);
+hipError_t slice_capacity(bool f32c, int nc, int slots, bool pow, int n_tab, int block, int n_cu, int *grid);
+hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, bool pow, int grid, int block,
+                        hipStream_t s);
 const void *fill_u64_kernel();
 // hipFuncSetAttribute (dynamic LDS) and the occupancy query, kept per (kernel, block, bytes)
 hipError_t occupancy_cached(const void *fn, int block, size_t lds, int *per_cu);
@@ -53,11 +55,11 @@ struct SliceGraph {
     hipKernelNodeParams params{};
     SliceArgs args{};
     void *arg_ptr[1] = {nullptr};
-    bool f32c = false;
+    bool f32c = false, pow = false;
     int nc = 0, slots = 0, grid = 0, block = 0;
 };
 hipError_t slice_graph_build(SliceGraph &G, const SliceGraphBufs &b, const SliceArgs &A, bool f32c, int nc,
-                             int slots, int grid, int block);
+                             int slots, bool pow, int grid, int block);
 hipError_t slice_graph_launch(SliceGraph &G, const SliceArgs &A, hipStream_t s);
 void slice_graph_destroy(SliceGraph &G);
 // profiles of the listed requests (n_blocks = their total radii; rstart[i] = first

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libnuhalo.so")
 NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ESTEPS = 0, -1, -2, -3, -4
 NH_ENONFINITE, NH_EBUSY, NH_ENOTREADY, NH_ENOTFOUND, NH_ECANCELED = -5, -6, -7, -8, -9
 OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4, "block_threads": 5,
-           "batch_slots": 6, "slice_us": 7, "serve_graph": 8, "workgroups": 9}
+           "batch_slots": 6, "slice_us": 7, "serve_graph": 8, "workgroups": 9, "fp32c_rtol": 10}
 
 _MASS = {"zero": 0, "paper": 1, "exponential": 2, "table": 3}
 _CONC = {"constant": 0, "power": 1, "table": 2}

@@ -15,22 +15,19 @@ which average over all of them, carry the tolerance:
     trajectories within 1e-8 (their sensitivity is <= 1e-10 per ulp, and the
     GPU's elementary functions round differently from the C library's by a
     few ulps on every right-hand side).
-  * Dormand-Prince FP64, the gate: at rtol 1e-10 on both sides, where the
-    accept/reject decisions no longer decide the 1e-8 digit, n/nbar within
-    1e-8 relative; for the rare halo whose orbits are chaotic enough that the
-    oracle itself moves by more under 1e-12 perturbations (seed 6 with a
-    0.3 eV relic: 1.4e-8), within four times that sensitivity, or four times
-    the GPU path's own under the same probes where that is larger (the paper
-    halo observed at z0 = 0.5: 1.2e-8 on the GPU, 1.6e-9 in the oracle).
-  * Dormand-Prince FP64 at the production rtol 1e-8: n/nbar within 1e-8
-    relative, or within four times the oracle's own sensitivity where that
-    is larger.  Adaptive step control amplifies tiny
-    force differences into flipped accept/reject decisions: for some halos
-    the oracle's profile moves by ~1e-8 when its force is perturbed by 1e-12
-    relative, the size of the device's table interpolation error.  The
-    sensitivity is measured per case (conftest: re-rounding by the oracle
-    built with FMA contraction, and 1e-12 relative changes of the halo mass
-    and of G(z)).  Conditioned trajectories agree to 1e-6.
+  * Dormand-Prince FP64, the gate: rtol 1e-12 on both sides, n/nbar within
+    1e-9 relative, every case, no allowance.  At that tolerance the
+    accept/reject decisions no longer decide the 1e-9 digit: the oracle's own
+    profile moves by at most 2.6e-10 under every probe of the `sensitivity`
+    measure, on every case here.
+  * Dormand-Prince FP64 at rtol 1e-10 and at the production rtol 1e-8: n/nbar
+    within 1e-8 relative, or within four times the oracle's own sensitivity
+    where that is larger.  Adaptive step control amplifies tiny differences of
+    the force into flipped accept/reject decisions, and at these tolerances
+    the discrete answer itself moves by up to a few 1e-8 under 1e-14 relative
+    changes of the halo mass (the oracle's rtol-1e-10 profiles are up to 4e-8
+    from its converged ones); the sensitivity is measured per case from the
+    oracle alone (conftest).  Conditioned trajectories agree to 1e-6.
 """
 import math
 
@@ -84,29 +81,6 @@ def conditioned(O, req, ref_ratio, index=None, tol=1e-10):
             s1 = O.integrate_states(O.model_of(req), O.integ_of(req), p)[0]
             sens = np.maximum(sens, rel(O.speed_ratio(p[:, 2:], s1[:, 2:]), ref_ratio))
     return sens <= tol
-
-
-def gpu_probes(req):
-    """The perturbations of the sensitivity measure that the GPU path can take
-    as requests: halo mass by 1 +- 1e-12 and the first trial step by 1 + 1e-12."""
-    if req.mass_kind == "zero":
-        return []
-    if req.mass_kind == "table":
-        m = [req.with_(hist_M=np.asarray(req.hist_M) * f) for f in (1 + 1e-12, 1 - 1e-12)]
-    else:
-        m = [req.with_(M0=req.M0 * f) for f in (1 + 1e-12, 1 - 1e-12)]
-    return m + [req.with_(h0=req.h0 * (1 + 1e-12))]
-
-
-def gpu_sensitivity(ctx, req, prof):
-    """Largest relative move of the GPU's own profile under gpu_probes: the
-    device path's counterpart of the oracle's sensitivity (its accept/reject
-    decisions flip under its own table interpolation error, ~1e-13-1e-12 of
-    the force, just as the oracle's do under 1e-12 probes)."""
-    worst = 0.0
-    for p in gpu_probes(req):
-        worst = max(worst, float(rel(gpu_ratios(ctx, p)[0], prof).max()))
-    return worst
 
 
 def gpu_ratios(ctx, req):
@@ -176,7 +150,22 @@ DP5_CASES = {
         method="dp5", mass_kind="paper", M0=1e14, conc_kind="constant", c0=7.0, m_eV=0.3, z_obs=0.5,
         z_form=1.5 * 200.0 ** (1.0 / 3.0) - 1.0, z_end=1.5 * 200.0 ** (1.0 / 3.0) - 1.0),
     "z_obs_exponential": lambda: W.shrink(W.plain_scale(1), 8, 16, 6).with_(z_obs=1.0, z_end=5.0),
+    # Sec. IV.A (Fig. 4): halo growth xi^alpha and an earlier onset of growth;
+    # Sec. IV.B (Fig. 5, bottom): the G modulations kappa_1 and kappa_2
+    "growth_alpha_0.5": lambda: _paper_sec4(mass_alpha=0.5),
+    "growth_alpha_2": lambda: _paper_sec4(mass_alpha=2.0),
+    "early_onset": lambda: _paper_sec4(z_form=2.0 * Z_FORM_PAPER),
+    "kappa_1": lambda: _paper_sec4(kappa_kind="paper", kappa_a=0.2, kappa_b=1.5),
+    "kappa_2": lambda: _paper_sec4(kappa_kind="paper", kappa_a=0.1, kappa_b=0.8),
 }
+
+
+def _paper_sec4(**kw):
+    """The paper's halo model with the settings of its Sec. IV studies: a relic of
+    0.3 eV around a 1e15 Msun halo (Figs. 4 and 5), observed at z0 = 0 and
+    integrated back to the base model's z_i."""
+    return W.shrink(W.plain_small(), 6, 10, 6).with_(
+        method="dp5", mass_kind="paper", M0=1e15, conc_kind="constant", c0=7.0, m_eV=0.3, z_end=Z_FORM_PAPER, **kw)
 
 
 def _sampled_history(req, n=41):
@@ -198,24 +187,42 @@ def _sampled_f0(req, n=60):
 
 
 @pytest.mark.parametrize("name", sorted(DP5_CASES))
+def test_dp5_fp64_gate(ctx, O, name):
+    """The FP64 gate: Dormand-Prince at rtol 1e-12 on both sides, every radius
+    of every case within 1e-9 of the oracle, with no allowance (the oracle's
+    own profile moves by at most 2.6e-10 there under any probe)."""
+    req = DP5_CASES[name]().with_(rtol=1e-12)
+    say(f"dp5 gate {name} rtol 1e-12 n_traj={req.n_traj}")
+    prof, _, stats = gpu_ratios(ctx, req)
+    ref = O.solve(req)
+    e = rel(prof, ref["n_over_nbar"]).max()
+    print(f"n/nbar max rel {e:.2e}; steps gpu {stats['accepted_steps']} oracle {int(ref['accepted'].sum())}",
+          flush=True)
+    assert stats["n_failed"] == 0 and np.all(ref["status"] == 0)
+    assert e <= 1e-9
+
+
+@pytest.mark.parametrize("name", sorted(DP5_CASES))
 def test_dp5_matches_oracle(ctx, O, sensitivity, name):
+    """At the case's own tolerance (rtol 1e-8 for most: the production
+    setting): within 1e-8, or 4x the oracle's own sensitivity where that is
+    larger; per trajectory, the median speed ratio within 1e-10 and nearly all
+    well-conditioned ones within 1e-6."""
     req = DP5_CASES[name]()
-    say(f"dp5 {name} n_traj={req.n_traj} M0={req.M0:.3g} m={req.m_eV}")
+    say(f"dp5 {name} n_traj={req.n_traj} M0={req.M0:.3g} m={req.m_eV} rtol {req.rtol}")
     prof, ratio, stats = gpu_ratios(ctx, req)
     ref = O.solve(req)
-    e = rel(prof, ref["n_over_nbar"])
+    e = rel(prof, ref["n_over_nbar"]).max()
     d = rel(ratio, ref["ratio"])
     acc_ref = int(ref["accepted"].sum())
     ok = conditioned(O, req, ref["ratio"])
-    sens = sensitivity(req, ref["n_over_nbar"])
-    if e.max() > max(1e-8, 4.0 * sens):
-        sens = max(sens, gpu_sensitivity(ctx, req, prof))
-    print(f"n/nbar max rel {e.max():.2e} (sensitivity {sens:.2e}); "
+    sens = sensitivity(req, ref["n_over_nbar"]) if e > 1e-8 else float("nan")
+    print(f"n/nbar max rel {e:.2e} (oracle sensitivity {sens:.2e}); "
           f"ratio median {np.median(d):.2e} p99 {np.quantile(d, 0.99):.2e} "
           f"max {d.max():.2e}; conditioned {ok.mean():.4f} p99 {np.quantile(d[ok], 0.99):.2e}; "
           f"steps gpu {stats['accepted_steps']} oracle {acc_ref} free exits {stats['free_exits']}",
           flush=True)
-    assert e.max() <= max(1e-8, 4.0 * sens)
+    assert e <= 1e-8 or e <= 4.0 * sens
     assert np.median(d) <= 1e-10
     assert np.quantile(d[ok], 0.99) <= 1e-6
     assert stats["n_failed"] == 0
@@ -224,14 +231,11 @@ def test_dp5_matches_oracle(ctx, O, sensitivity, name):
 
 
 @pytest.mark.parametrize("name", sorted(DP5_CASES))
-def test_dp5_matches_oracle_at_tight_rtol(ctx, O, sensitivity, name):
-    """The FP64 gate: at rtol 1e-10 the accept/reject decisions no longer
-    decide the 1e-8 digit: 1e-8, or 4x the sensitivity where the orbits make
-    that larger - the oracle's, or the GPU path's own under the same 1e-12
-    probes (z_obs_paper: the GPU profile moves by 1.2e-8 under them, the
-    oracle's by 1.6e-9)."""
-    req = DP5_CASES[name]()
-    req = req.with_(rtol=min(req.rtol, 1e-10))
+def test_dp5_matches_oracle_at_rtol_1e10(ctx, O, sensitivity, name):
+    """The oracle's reference tolerance, rtol 1e-10, on both sides: within
+    1e-8, or 4x the oracle's own sensitivity at that tolerance where that is
+    larger."""
+    req = DP5_CASES[name]().with_(rtol=1e-10)
     say(f"dp5 {name} at rtol {req.rtol} n_traj={req.n_traj}")
     prof, _, stats = gpu_ratios(ctx, req)
     ref = O.solve(req)["n_over_nbar"]
@@ -241,19 +245,18 @@ def test_dp5_matches_oracle_at_tight_rtol(ctx, O, sensitivity, name):
         print(f"n/nbar max rel {e:.2e}", flush=True)
         return
     sens = sensitivity(req, ref)
-    gsens = gpu_sensitivity(ctx, req, prof) if e > 4.0 * sens else 0.0
-    print(f"n/nbar max rel {e:.2e} (oracle sensitivity {sens:.2e}, GPU {gsens:.2e})", flush=True)
-    assert e <= 4.0 * max(sens, gsens)
+    print(f"n/nbar max rel {e:.2e} (oracle sensitivity {sens:.2e})", flush=True)
+    assert e <= 4.0 * sens
 
 
-def test_dp5_full_size_sampled(ctx, O):
-    """Full 100 x 200 x 64 grid in the benchmark's launch shape (1024-thread
-    workgroups, at most 64 of them, as when four profiles run side by side);
-    400 sampled trajectories integrated one by one on the oracle, plus the
-    quadrature re-done on the CPU from the GPU's own ratios.  The default
-    launch (768 threads on every CU) gives the same bits."""
+def test_dp5_full_size_launch_shapes_agree(ctx, O):
+    """Full 100 x 200 x 64 grid of a heavy halo (seed 4) in the benchmark's launch
+    shape (1024-thread workgroups, at most 64 of them, as when four profiles run
+    side by side) and in the default launch: the same bits, and the profile is
+    the oracle's quadrature of the GPU's own ratios.  (The whole profile against
+    the oracle's: test_gpu_full_size.py.)"""
     req = W.plain_scale(4)
-    say(f"dp5 full size seed 4 n_traj={req.n_traj}, 1024 threads x 64 workgroups")
+    say(f"dp5 full size seed 4 n_traj={req.n_traj}, 1024 threads x 64 workgroups vs default")
     ctx.set_option("block_threads", 1024)
     ctx.set_option("workgroups", 64)
     try:
@@ -264,16 +267,6 @@ def test_dp5_full_size_sampled(ctx, O):
     assert stats["n_failed"] == 0
     prof0, ratio0, _ = gpu_ratios(ctx, req)
     assert np.array_equal(ratio0, ratio) and np.array_equal(prof0, prof)
-    rng = np.random.default_rng(11)
-    idx = np.sort(rng.choice(req.n_traj, 400, replace=False))
-    tr = O.trajectories(req, index=idx)
-    d = rel(ratio[idx], tr["ratio"])
-    ok = conditioned(O, req, tr["ratio"], index=idx)
-    print(f"sampled ratio rel diff median {np.median(d):.2e} p99 {np.quantile(d, 0.99):.2e} max {d.max():.2e}; "
-          f"conditioned {ok.mean():.3f} their p99 {np.quantile(d[ok], 0.99):.2e}")
-    assert np.median(d) <= 1e-10
-    assert np.quantile(d[ok], 0.95) <= 1e-7
-    # the reduction at full size: oracle quadrature over the GPU's ratios
     cpu_prof = O.profile_from_ratio(req, ratio)
     assert rel(prof, cpu_prof).max() <= 1e-13
 

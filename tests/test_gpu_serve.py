@@ -3,8 +3,12 @@
 The server runs the batched slice kernel in time slices and resumes
 trajectories cut by a slice boundary from their saved state, so a served
 profile must equal the plain path's bit for bit whatever else is being served
-and however often it was interrupted.  Admission is by device-memory footprint
-against the budget; cancellation drops a request without disturbing the others.
+and however often it was interrupted.  Served profiles are also checked
+against the oracle with the plain paths' bounds: FP64 within 1e-9 at rtol
+1e-12 and within 1e-8 (or 4x the oracle's own sensitivity) at rtol 1e-8; FP32C
+within 1e-4 of the oracle's reference integration.  Admission is by
+device-memory footprint against the budget; cancellation drops a request
+without disturbing the others.
 """
 import time
 
@@ -47,6 +51,13 @@ def wait(ctx, ticket, n_r, timeout=60.0):
         time.sleep(0.001)
 
 
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
 def small(seed, n, prec="fp64"):
     reqs = W.batched(seed, n_req=n, prec=prec, freeze_in_frac=0.3, kappa_frac=0.2)
     return [W.shrink(r, 5 + i % 3, 10 + i % 5, 6 + i % 2) for i, r in enumerate(reqs)]
@@ -74,6 +85,56 @@ def test_served_equals_plain_bitwise_across_slices(ctx, prec, graph):
         assert st["rejected_steps"] == pst["rejected_steps"]
         assert st["latency_ms"] > 0.0
         assert st["kernel_ms"] > 0.0
+
+
+def serving_mix(prec, rtol):
+    """Serving-workload requests on small grids, with the serving workload's
+    kinds certainly present: freeze-in f0 (Sec. IV.B), G(z) = G0 (1 + 0.05 ln(1+z)),
+    both, and plain Fermi-Dirac."""
+    reqs = small(57, 8, prec)
+    reqs[0] = reqs[0].with_(f0_kind="freeze_in", kappa_kind="none", kappa_a=0.0)
+    reqs[1] = reqs[1].with_(f0_kind="fermi_dirac", kappa_kind="log", kappa_a=0.05)
+    reqs[2] = reqs[2].with_(f0_kind="freeze_in", kappa_kind="log", kappa_a=0.05)
+    return [r.with_(rtol=rtol) for r in reqs]
+
+
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-12), ("fp64", 1e-8), ("fp32c", 1e-8)])
+def test_served_vs_oracle(ctx, O, sensitivity, prec, rtol):
+    """Continuous batching: requests arrive in waves while earlier ones are on the
+    GPU, with 500 us slices; each served profile equals the same request solved
+    alone on the plain path bit for bit, and the oracle within the plain paths'
+    bounds."""
+    reqs = serving_mix(prec, rtol)
+    say(f"serve {prec} rtol {rtol} x{len(reqs)} in waves, slice 500 us, vs oracle")
+    ctx.set_option("slice_us", 500)
+    tickets = []
+    for i, r in enumerate(reqs):
+        t = ctx.submit(r)
+        assert t is not None
+        tickets.append(t)
+        if i % 3 == 2:
+            time.sleep(0.003)
+    res = [wait(ctx, t, r.n_r) for t, r in zip(tickets, reqs)]
+    for i, ((prof, st, rc), r) in enumerate(zip(res, reqs)):
+        assert rc == 0
+        assert np.array_equal(prof, plain(ctx, r)[0]), i
+        if prec == "fp32c":
+            ref = O.solve(r.with_(precision="fp64", rtol=1e-10))["n_over_nbar"]
+            e = np.abs(prof / ref - 1).max()
+            print(f"request {i} ({r.f0_kind}, kappa {r.kappa_kind}): fp32c max rel vs oracle {e:.2e}", flush=True)
+            assert e <= 1e-4, i
+            continue
+        ref = O.solve(r)["n_over_nbar"]
+        e = np.abs(prof / ref - 1).max()
+        if rtol <= 1e-12:
+            print(f"request {i} ({r.f0_kind}, kappa {r.kappa_kind}): max rel vs oracle {e:.2e}", flush=True)
+            assert e <= 1e-9, i
+        elif e > 1e-8:
+            sens = sensitivity(r, ref)
+            print(f"request {i}: max rel {e:.2e} (oracle sensitivity {sens:.2e})", flush=True)
+            assert e <= 4.0 * sens, i
+        else:
+            print(f"request {i} ({r.f0_kind}, kappa {r.kappa_kind}): max rel vs oracle {e:.2e}", flush=True)
 
 
 def test_served_full_size_requests(ctx):

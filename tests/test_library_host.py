@@ -118,7 +118,19 @@ REQS = {
     "uncompensated": lambda: W.plain_small().with_(compensated=False, M0=2e12),
     "sampled_histories": lambda: _sampled(W.plain_small().with_(M0=4e13), "paper"),
     "sampled_delta200": lambda: _sampled(W.plain_small().with_(M0=4e13), "delta200"),
+    # the paper's Sec. IV variants: growth xi^alpha (Fig. 4 left), an earlier onset
+    # (Fig. 4 middle) and the G modulations kappa_1, kappa_2 (Fig. 5 bottom)
+    "growth_alpha_0.5": lambda: _sec4(mass_alpha=0.5),
+    "growth_alpha_2": lambda: _sec4(mass_alpha=2.0),
+    "early_onset": lambda: _sec4(z_form=2.0 * Z_FORM_PAPER),
+    "kappa_1": lambda: _sec4(kappa_kind="paper", kappa_a=0.2, kappa_b=1.5),
+    "kappa_2": lambda: _sec4(kappa_kind="paper", kappa_a=0.1, kappa_b=0.8),
 }
+
+
+def _sec4(**kw):
+    return W.plain_small().with_(method="dp5", mass_kind="paper", M0=1e15, conc_kind="constant", c0=7.0,
+                                 m_eV=0.3, z_end=Z_FORM_PAPER, **kw)
 
 
 def _sampled(req, geometry, n=37):
