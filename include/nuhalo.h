@@ -275,6 +275,11 @@ enum {
                                   HIP graph built once per session and table layout, with only
                                   the kernel's arguments updated; 0 issues them one by one.
                                   Taken when a serving session starts. */
+    NH_OPT_TRAJECTORY_STATS = 11, /* [0] nh_solve and nh_solve_async without a ratio buffer add
+                                  each trajectory's quadrature term and statistics as it
+                                  finishes and store nothing per trajectory; 1 stores the
+                                  speed ratios and per-trajectory statistics first (for
+                                  nh_last_trajectory_stats).  Profiles are the same bits. */
     NH_OPT_FP32C_RTOL    = 10, /* NH_FP32C: tolerance floor of the FP32 attempts, in [1e-9, 1e-3]
                                   [1e-7]: they integrate at max(rtol, this).  At 1e-6 the
                                   discretisation error alone reaches 1e-4 of n/nbar for some
@@ -293,17 +298,25 @@ int nh_set_option(nh_context *ctx, int option, double value);
 
 /* ---- plain solve ------------------------------------------------------ */
 
-/* Compute n/nbar for one request and wait for it.
+/* Compute n/nbar for one request and wait for it: the backward integration of
+ * every trajectory (Sec. II.C) and the quadrature of Eq. (localdensity) over
+ * the background density that follows it.
  * n_over_nbar: host, req->grid.n_r doubles, written in radius order.
  * stats: may be NULL.
  * Returns NH_OK, NH_ESTEPS / NH_ENONFINITE (profile written, failures counted
  * in stats), or an error with nothing written. */
 int nh_solve(nh_context *ctx, const nh_request *req, double *n_over_nbar, nh_stats *stats);
 
-/* Enqueue one request on `stream` without waiting.
+/* Enqueue one request on `stream` without waiting: the backward integration of
+ * every trajectory (Sec. II.C) and the quadrature of Eq. (localdensity) over
+ * the background density that follows it.
  * d_out:   device, req->grid.n_r doubles, receives n/nbar.
  * d_ratio: device, n_traj doubles, or NULL; receives P_i/P0 = |v(z_end)|/|v0|
  *          of every trajectory in index order t = (k*n_y + j)*n_mu + l.
+ * Without d_ratio (and NH_OPT_TRAJECTORY_STATS 0) the quadrature runs in the
+ * trajectory kernels as trajectories finish and nothing is stored per
+ * trajectory.  The sums are exact (fixed point), so the profile is the same
+ * bits either way.
  * The context's work buffers are reused by the next call on the same context,
  * which first waits for this one.  nh_last_stats() waits and reports it. */
 int nh_solve_async(nh_context *ctx, const nh_request *req, double *d_out, double *d_ratio,
@@ -339,15 +352,22 @@ int nh_solve_masses(nh_context *ctx, const nh_request *req, int n_mass, const do
 int nh_last_stats(nh_context *ctx, nh_stats *stats);
 
 /* Per-trajectory diagnostics of the last completed solve on this context
- * (waits for it).  Host arrays of n_traj entries in trajectory order, each
- * may be NULL: accepted and rejected step counts, and the status word
- * (low byte 0 ok, 1 max_steps, 2 step underflow, 3 non-finite; bit 8 set
- * when the trajectory left through the exact free-streaming exit). */
-int nh_last_trajectory_stats(nh_context *ctx, int *accepted, int *rejected, int *status);
+ * (waits for it), which must have stored per-trajectory results (a ratio
+ * buffer, nh_solve_masses, nh_solve_integrand, nh_solve_batch, or
+ * NH_OPT_TRAJECTORY_STATS 1); NH_EINVAL otherwise.  Host arrays of `capacity`
+ * entries, at least the last solve's n_traj (NH_EINVAL if fewer), each may be
+ * NULL; entries in trajectory order (a batch: its requests concatenated):
+ * accepted and rejected step counts, and the status word (low byte 0 ok, 1
+ * max_steps, 2 step underflow, 3 non-finite; bit 8 set when the trajectory
+ * left through the exact free-streaming exit). */
+int nh_last_trajectory_stats(nh_context *ctx, size_t capacity, int *accepted, int *rejected, int *status);
 
 /* ---- batched solve ---------------------------------------------------- */
 
-/* Solve n_req heterogeneous requests in one persistent launch.
+/* Solve n_req heterogeneous requests in one persistent launch (each request:
+ * Sec. II.C integration and the quadrature of Eq. localdensity; several
+ * halos, relic masses and grids at once serve the paper's rapid scans of
+ * parameters, abstract and Sec. V).
  * d_out: device, sum of the requests' n_r doubles, profiles concatenated in
  * request order.  All requests must share method and precision.
  * stats: host array of n_req entries, or NULL.  Waits for completion. */
@@ -371,14 +391,17 @@ int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d
  * requests are admitted.  Needs no GPU. */
 int nh_serve_set_budget(nh_context *ctx, size_t bytes);
 
-/* Admit a request, or NH_EBUSY if its footprint (nh_footprint_bytes) does not
+/* Admit a request (integration, Sec. II.C, and quadrature, Eq. localdensity,
+ * served between other requests for the rapid scans of the abstract and
+ * Sec. V), or NH_EBUSY if its footprint (nh_footprint_bytes) does not
  * fit the free budget right now (nothing is queued then).  NH_EINVAL for an
  * invalid request, a method other than NH_DOPRI5 or another precision than
  * the one being served.  Host inputs are copied before the call returns.
  * ticket: receives an id for nh_poll / nh_cancel. */
 int nh_submit(nh_context *ctx, const nh_request *req, uint64_t *ticket);
 
-/* Collect a finished ticket.  out: host, n_r doubles.  stats: may be NULL.
+/* Collect a finished ticket: its n/nbar profile (Eq. localdensity).
+ * out: host, n_r doubles.  stats: may be NULL.
  * NH_ENOTREADY while the ticket runs; NH_OK (or NH_ESTEPS / NH_ENONFINITE with
  * the profile written) once, after which the ticket is gone. */
 int nh_poll(nh_context *ctx, uint64_t ticket, double *out, nh_stats *stats);

@@ -210,6 +210,63 @@ int wait_pending(nh_context *ctx)
     return NH_OK;
 }
 
+int solve_launch(nh_context *ctx, const nh_request *q, const Staged &s, TrajParams P, const SolveBufs &b,
+                 double *d_out, hipStream_t stream, int n_mass, double *d_integrand)
+{
+    const GridPtrs g = grid_ptrs(s, b.blob);
+    const long long n = P.n_traj;
+    const bool fused = b.qa.num != nullptr;
+    const bool free_all = q->halo.mass_kind == NH_MASS_ZERO;
+    unsigned long long *counter = b.small;
+    unsigned long long *stats = counter + 8;
+    HIPCHK(launch_fill_u64(counter, 16, 0ull, stream));
+    if (fused) HIPCHK(launch_quad_setup(P, g, b.qa, stream));
+
+    TrajOut o;
+    o.ratio = b.ratio;
+    o.stat = b.stat;
+    const QuadAcc *qa = fused ? &b.qa : nullptr;
+
+    HIPCHK(hipEventRecord(ctx->ev_t0, stream));
+    if (free_all) {
+        if (fused) HIPCHK(launch_fill_u64(stats + 5, 1, (unsigned long long)n, stream));   // all free exits
+        else HIPCHK(launch_free_all(n, o, stream));
+    } else if (q->integ.method == NH_RK4) {
+        HIPCHK(launch_rk4_f64(P, g, o, qa, stream));
+    } else {
+        const bool f32 = q->integ.precision == NH_FP32C;
+        if (f32) {
+            P.h_fp64 = ctx->h_fp64;
+            P.rtol32 = ctx->rtol32;
+        }
+        P.order = ctx->queue_order;
+        P.block = ctx->block_threads > 0 ? ctx->block_threads : ctx->tuned_plain_block[f32];
+        P.max_wg = ctx->max_workgroups;
+        if (f32) HIPCHK(launch_dp5_f32c(P, g, o, counter, qa, ctx->n_cu, stream));
+        else HIPCHK(launch_dp5_f64(P, g, o, counter, qa, ctx->n_cu, stream));
+    }
+    HIPCHK(hipEventRecord(ctx->ev_t1, stream));
+    if (fused) {
+        HIPCHK(launch_quad_finish(P.n_r, b.qa, free_all, d_out, stream));
+    } else {
+        if (n_mass > 0)
+            HIPCHK(launch_reduce_masses(P, g, b.ratio, (const double *)(b.blob + s.off_ym),
+                                        (const double *)(b.blob + s.off_wm), n_mass, d_out, stream));
+        else
+            HIPCHK(launch_reduce_profile(P, g, b.ratio, d_out, stream));
+        if (d_integrand) HIPCHK(launch_reduce_integrand(P, g, b.ratio, d_integrand, stream));
+        HIPCHK(launch_reduce_stats(n, o, stats, stream));
+    }
+    // the statistics come back with the solve itself, so reading them later
+    // does not wait for whatever the caller enqueued on the stream since
+    HIPCHK(hipMemcpyAsync(ctx->h_stats, stats, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipEventRecord(ctx->ev_done, stream));
+    ctx->pending = true;
+    ctx->last_n_traj = n;
+    ctx->last_traj_kept = !fused;
+    return NH_OK;
+}
+
 int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d_ratio,
                   hipStream_t stream, int n_mass, const double *m_eV, double *d_integrand)
 {
@@ -236,56 +293,42 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
     }
     if ((rc = ensure_dev(ctx, ctx->blob, s.bytes)) != NH_OK) return rc;
     HIPCHK(hipMemcpyAsync(ctx->blob.p, ctx->h_stage, s.bytes, hipMemcpyHostToDevice, stream));
-    const GridPtrs g = grid_ptrs(s, (const char *)ctx->blob.p);
-
-    const long long n = P.n_traj;
-    if (!d_ratio) {
-        if ((rc = ensure_dev(ctx, ctx->ratio, (size_t)n * sizeof(double))) != NH_OK) return rc;
-        d_ratio = (double *)ctx->ratio.p;
-    }
-    if ((rc = ensure_dev(ctx, ctx->stat, (size_t)n * sizeof(TrajStat))) != NH_OK) return rc;
     if ((rc = ensure_dev(ctx, ctx->small, 64 * sizeof(unsigned long long))) != NH_OK) return rc;
-    unsigned long long *counter = (unsigned long long *)ctx->small.p;
-    unsigned long long *stats = counter + 8;
-    HIPCHK(launch_fill_u64(counter, 16, 0ull, stream));
 
-    TrajOut o;
-    o.ratio = d_ratio;
-    o.stat = (TrajStat *)ctx->stat.p;
-
-    HIPCHK(hipEventRecord(ctx->ev_t0, stream));
-    if (q->halo.mass_kind == NH_MASS_ZERO) {
-        HIPCHK(launch_free_all(n, o, stream));
-    } else if (q->integ.method == NH_RK4) {
-        HIPCHK(launch_rk4_f64(P, g, o, stream));
+    SolveBufs b{};
+    b.blob = (char *)ctx->blob.p;
+    b.small = (unsigned long long *)ctx->small.p;
+    // the quadrature runs in the trajectory kernels' epilogue unless something
+    // per trajectory is wanted: speed ratios, other masses, the distribution
+    // per momentum node, or per-trajectory statistics
+    const bool fused = !d_ratio && n_mass == 0 && !d_integrand && !ctx->keep_traj;
+    const long long n = P.n_traj;
+    if (fused) {
+        if ((rc = ensure_dev(ctx, ctx->quad, quad_bytes(q->grid.n_r))) != NH_OK) return rc;
+        b.qa = quad_acc(ctx->quad.p, q->grid.n_r, b.small + 8);
     } else {
-        const bool f32 = q->integ.precision == NH_FP32C;
-        if (f32) {
-            P.h_fp64 = ctx->h_fp64;
-            P.rtol32 = ctx->rtol32;
+        if (!d_ratio) {
+            if ((rc = ensure_dev(ctx, ctx->ratio, (size_t)n * sizeof(double))) != NH_OK) return rc;
+            d_ratio = (double *)ctx->ratio.p;
         }
-        P.order = ctx->queue_order;
-        P.block = ctx->block_threads > 0 ? ctx->block_threads : ctx->tuned_plain_block[f32];
-        P.max_wg = ctx->max_workgroups;
-        if (f32) HIPCHK(launch_dp5_f32c(P, g, o, counter, ctx->n_cu, stream));
-        else HIPCHK(launch_dp5_f64(P, g, o, counter, ctx->n_cu, stream));
+        if ((rc = ensure_dev(ctx, ctx->stat, (size_t)n * sizeof(TrajStat))) != NH_OK) return rc;
+        b.ratio = d_ratio;
+        b.stat = (TrajStat *)ctx->stat.p;
     }
-    HIPCHK(hipEventRecord(ctx->ev_t1, stream));
-    if (n_mass > 0)
-        HIPCHK(launch_reduce_masses(P, g, d_ratio, (const double *)((const char *)ctx->blob.p + s.off_ym),
-                                    (const double *)((const char *)ctx->blob.p + s.off_wm), n_mass, d_out,
-                                    stream));
-    else
-        HIPCHK(launch_reduce_profile(P, g, d_ratio, d_out, stream));
-    if (d_integrand) HIPCHK(launch_reduce_integrand(P, g, d_ratio, d_integrand, stream));
-    HIPCHK(launch_reduce_stats(n, o, stats, stream));
-    // the statistics come back with the solve itself, so reading them later
-    // does not wait for whatever the caller enqueued on the stream since
-    HIPCHK(hipMemcpyAsync(ctx->h_stats, stats, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipEventRecord(ctx->ev_done, stream));
-    ctx->pending = true;
-    ctx->last_n_traj = n;
-    return NH_OK;
+    return solve_launch(ctx, q, s, P, b, d_out, stream, n_mass, d_integrand);
+}
+
+size_t quad_bytes(int n_r) { return ((size_t)2 * n_r + 4) * sizeof(unsigned long long); }
+
+QuadAcc quad_acc(void *base, int n_r, unsigned long long *stats)
+{
+    QuadAcc qa;
+    qa.num = (unsigned long long *)base;
+    qa.den = qa.num + 2 * (size_t)n_r;
+    qa.scale = (double *)(qa.den + 2);
+    qa.stats = stats;
+    qa.lds_n = 0;   // set per launch by the trajectory kernels' launchers
+    return qa;
 }
 
 int collect_stats(nh_context *ctx, nh_stats *out)
@@ -392,6 +435,10 @@ int nh_set_option(nh_context *ctx, int option, double value)
         if (value < 0.0) return set_err(ctx, NH_EINVAL, "threshold must be >= 0");
         ctx->h_fp64 = value;
         return NH_OK;
+    case NH_OPT_TRAJECTORY_STATS:
+        if (value != 0.0 && value != 1.0) return set_err(ctx, NH_EINVAL, "trajectory statistics is 0 or 1");
+        ctx->keep_traj = value != 0.0;
+        return NH_OK;
     case NH_OPT_FP32C_RTOL:
         if (value < 1.0e-9 || value > 1.0e-3)
             return set_err(ctx, NH_EINVAL, "FP32C tolerance floor must be in [1e-9, 1e-3]");
@@ -482,7 +529,7 @@ int nh_context_destroy(nh_context *ctx)
     serve_shutdown(ctx);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&ctx->blob, &ctx->ratio, &ctx->stat, &ctx->small, &ctx->out, &ctx->bctr})
+    for (DevBuf *b : {&ctx->blob, &ctx->ratio, &ctx->stat, &ctx->small, &ctx->out, &ctx->bctr, &ctx->quad})
         if (b->p) (void)hipFree(b->p);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->h_stats) (void)hipHostFree(ctx->h_stats);
@@ -525,10 +572,15 @@ int nh_last_stats(nh_context *ctx, nh_stats *stats)
     return collect_stats(ctx, stats);
 }
 
-int nh_last_trajectory_stats(nh_context *ctx, int *accepted, int *rejected, int *status)
+int nh_last_trajectory_stats(nh_context *ctx, size_t capacity, int *accepted, int *rejected, int *status)
 {
     if (!ctx) return set_err(nullptr, NH_EINVAL, "context is NULL");
     if (ctx->last_n_traj < 0) return set_err(ctx, NH_EINVAL, "no solve to report");
+    if (!ctx->last_traj_kept)
+        return set_err(ctx, NH_EINVAL, "the last solve kept no per-trajectory results (pass a ratio buffer or set "
+                                       "NH_OPT_TRAJECTORY_STATS)");
+    if (capacity < (size_t)ctx->last_n_traj)
+        return set_err(ctx, NH_EINVAL, "arrays of %zu entries for %lld trajectories", capacity, ctx->last_n_traj);
     HIPCHK(hipSetDevice(ctx->device));
     if (ctx->pending) HIPCHK(hipEventSynchronize(ctx->ev_done));
     const size_t n = (size_t)ctx->last_n_traj;

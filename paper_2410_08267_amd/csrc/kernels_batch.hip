@@ -70,10 +70,8 @@ __device__ __forceinline__ void initial_state(const BatchReq &q, long long t, do
                                               double &vy0)
 {
     const TrajParams &P = q.P;
-    const int l = (int)(t % P.n_mu);
-    const long long kj = t / P.n_mu;
-    const int j = (int)(kj % P.n_y);
-    const int k = (int)(kj / P.n_y);
+    const TrajIdx ix = traj_idx(t, P);
+    const int l = ix.l, j = ix.j, k = ix.k;
     const double V = q.g.y[j] * P.vfac;
     vx0 = V * q.g.mu[l];
     vy0 = V * q.g.smu[l];

@@ -16,16 +16,27 @@
 
 #include "nh_dp5_f32.h"
 #include "nh_launch.h"
+#include "nh_reduce.h"
 
 namespace nh {
 
 // CULL: some start radius lies beyond R_exit (otherwise no relic can be culled
 // and the test is left out of the trajectory loop)
-template <int NC, bool CULL, bool HIST>
+// FUSED: each finished trajectory adds its quadrature term and statistics
+// directly (QuadAcc); nothing is written per trajectory.
+template <int NC, bool CULL, bool HIST, bool FUSED>
 __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, TrajOut o,
-                                                   unsigned long long *counter)
+                                                   unsigned long long *counter, QuadAcc qa)
 {
     extern __shared__ double lds_mix[];
+    __shared__ BlockStats bst;
+    // the workgroup's partial sums follow the table
+    unsigned long long *const lacc =
+        (unsigned long long *)((char *)lds_mix + quad_lds_offset(f32c_table_bytes<NC>(P.n_tab)));
+    if constexpr (FUSED) {
+        block_stats_init(bst);
+        quad_lds_init(lacc, qa.lds_n);
+    }
     stage_f32c_table<NC>(lds_mix, g.tab, P.n_tab, threadIdx.x, blockDim.x);
     __syncthreads();
 
@@ -46,17 +57,20 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
         if (need) {
             if (p < P.n_traj) {
                 t = traj_of(p, P);
-                const int l = (int)(t % P.n_mu);
-                const long long kj = t / P.n_mu;
-                const int j = (int)(kj % P.n_y);
-                const int k = (int)(kj / P.n_y);
+                const TrajIdx ix = traj_idx(t, P);
+                const int l = ix.l, j = ix.j, k = ix.k;
                 const double V = g.y[j] * P.vfac;
                 const double vx0 = V * g.mu[l], vy0 = V * g.smu[l];
                 v0n = sqrt(norm2(vx0, vy0));
                 if (CULL && never_enters(g.r[k], vx0, vy0, P.cull_D, cull_radius2(P.r_exit))) {
                     // App. B cull: the path never reaches R, the momentum is final
-                    o.ratio[t] = 1.0;
-                    o.stat[t] = TrajStat{0, 0, ST_OK | ST_FREE_EXIT, 0};
+                    const TrajStat ts{0, 0, ST_OK | ST_FREE_EXIT, 0};
+                    if constexpr (FUSED) {
+                        fused_finish(P, g, qa, lacc, bst, t, 1.0, ts);
+                    } else {
+                        o.ratio[t] = 1.0;
+                        o.stat[t] = ts;
+                    }
                     t = -1;
                 } else {
                     f32c_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_start, P.u_end);
@@ -72,53 +86,73 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
             const int st = f32c_attempt(L, cf, cf64, ctl, ctl64, P.h_fp64);
             if (st >= 0) {
                 const double fx = L.vx, fy = L.vy;
-                o.ratio[t] = sqrt(norm2(fx, fy)) / v0n;
-                o.stat[t] = TrajStat{L.nacc, L.nrej, st, L.n64};
+                const double ratio = sqrt(norm2(fx, fy)) / v0n;
+                const TrajStat ts{L.nacc, L.nrej, st, L.n64};
+                if constexpr (FUSED) {
+                    fused_finish(P, g, qa, lacc, bst, t, ratio, ts);
+                } else {
+                    o.ratio[t] = ratio;
+                    o.stat[t] = ts;
+                }
                 t = -1;
             }
         }
     }
+    if constexpr (FUSED) {
+        __syncthreads();
+        block_stats_flush(bst, qa.stats);
+        quad_lds_flush(qa, lacc);
+    }
 }
 
-template <int NC, bool CULL, bool HIST>
+template <int NC, bool CULL, bool HIST, bool FUSED>
 static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                                 unsigned long long *counter, int n_cu, hipStream_t s)
+                                 unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
 {
     // default 512 (a single profile's tail grows with more lanes); at most the
     // launch bound, 768 (the lane state fits 170 VGPRs: three waves per SIMD)
     const int B = P.block > 0 ? (P.block < 768 ? P.block : 768) : 512;
-    const size_t lds = f32c_table_bytes<NC>(P.n_tab);
+    size_t lds = f32c_table_bytes<NC>(P.n_tab);
     int per_cu = 0;
-    const hipError_t e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL, HIST>, B, lds, &per_cu);
+    hipError_t e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED>, B, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
+    QuadAcc q = qa;
+    if (FUSED) {
+        e = quad_lds_plan((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED>, B, per_cu, P.n_r, lds, q);
+        if (e != hipSuccess) return e;
+    }
     long long grid = (long long)n_cu * per_cu;
     if (P.max_wg > 0 && grid > P.max_wg) grid = P.max_wg;
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
-    auto *kern = k_dp5_f32c<NC, CULL, HIST>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
+    auto *kern = k_dp5_f32c<NC, CULL, HIST, FUSED>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter, q);
     return hipGetLastError();
 }
 
-template <bool HIST>
+template <bool HIST, bool FUSED>
 static hipError_t launch_f32c_hist(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                                  unsigned long long *counter, int n_cu, hipStream_t s)
+                                   unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
 {
     const bool cull = P.cull_D > 0.0;
     if (P.R_const > 0.0)
-        return cull ? launch_f32c_nc<NCOL - 1, true, HIST>(P, g, o, counter, n_cu, s)
-                    : launch_f32c_nc<NCOL - 1, false, HIST>(P, g, o, counter, n_cu, s);
-    return cull ? launch_f32c_nc<NCOL, true, HIST>(P, g, o, counter, n_cu, s)
-                : launch_f32c_nc<NCOL, false, HIST>(P, g, o, counter, n_cu, s);
+        return cull ? launch_f32c_nc<NCOL - 1, true, HIST, FUSED>(P, g, o, counter, qa, n_cu, s)
+                    : launch_f32c_nc<NCOL - 1, false, HIST, FUSED>(P, g, o, counter, qa, n_cu, s);
+    return cull ? launch_f32c_nc<NCOL, true, HIST, FUSED>(P, g, o, counter, qa, n_cu, s)
+                : launch_f32c_nc<NCOL, false, HIST, FUSED>(P, g, o, counter, qa, n_cu, s);
 }
 
 hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                           unsigned long long *counter, int n_cu, hipStream_t s)
+                           unsigned long long *counter, const QuadAcc *qa, int n_cu, hipStream_t s)
 {
-    return P.hist ? launch_f32c_hist<true>(P, g, o, counter, n_cu, s)
-                  : launch_f32c_hist<false>(P, g, o, counter, n_cu, s);
+    const QuadAcc q = qa ? *qa : QuadAcc{};
+    if (qa)
+        return P.hist ? launch_f32c_hist<true, true>(P, g, o, counter, q, n_cu, s)
+                      : launch_f32c_hist<false, true>(P, g, o, counter, q, n_cu, s);
+    return P.hist ? launch_f32c_hist<true, false>(P, g, o, counter, q, n_cu, s)
+                  : launch_f32c_hist<false, false>(P, g, o, counter, q, n_cu, s);
 }
 
 }  // namespace nh

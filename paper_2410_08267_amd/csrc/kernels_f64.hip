@@ -10,7 +10,6 @@
 
 #include <algorithm>
 #include <mutex>
-#include <vector>
 
 #include "nh_dp5.h"
 #include "nh_reduce.h"
@@ -54,15 +53,15 @@ static unsigned capped_blocks(long long n, int block)
 // ---------------------------------------------------------------------------
 
 // One trajectory t (a lane past the end, t >= n_traj, only keeps its wave company).
-__device__ __forceinline__ void rk4_one(const TrajParams &P, const GridPtrs &g, const TrajOut &o, long long t)
+template <bool FUSED>
+__device__ __forceinline__ void rk4_one(const TrajParams &P, const GridPtrs &g, const TrajOut &o, long long t,
+                                        const QuadAcc &qa, BlockStats &bst)
 {
     const bool valid = t < P.n_traj;
     double x = 0.0, y = 0.0, vx = 0.0, vy = 0.0, v0n = 1.0;
     if (valid) {
-        const int l = (int)(t % P.n_mu);
-        const long long kj = t / P.n_mu;
-        const int j = (int)(kj % P.n_y);
-        const int k = (int)(kj / P.n_y);
+        const TrajIdx ix = traj_idx(t, P);
+        const int l = ix.l, j = ix.j, k = ix.k;
         const double V = g.y[j] * P.vfac;
         x = g.r[k];
         vx = V * g.mu[l];
@@ -106,19 +105,35 @@ __device__ __forceinline__ void rk4_one(const TrajParams &P, const GridPtrs &g, 
         }
     }
     if (valid) {
-        o.ratio[t] = sqrt(norm2(vx, vy)) / v0n;
+        const double ratio = sqrt(norm2(vx, vy)) / v0n;
         int st = ST_OK;
         if (!(isfinite(x) && isfinite(y) && isfinite(vx) && isfinite(vy))) st = ST_NONFINITE;
-        o.stat[t] = TrajStat{steps, 0, st | (freed ? ST_FREE_EXIT : 0), 0};
+        const TrajStat ts{steps, 0, st | (freed ? ST_FREE_EXIT : 0), 0};
+        if constexpr (FUSED) {
+            fused_finish(P, g, qa, nullptr, bst, t, ratio, ts);
+        } else {
+            o.ratio[t] = ratio;
+            o.stat[t] = ts;
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajOut o)
+template <bool FUSED>
+__global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajOut o, QuadAcc qa)
 {
+    __shared__ BlockStats bst;
+    if constexpr (FUSED) {
+        block_stats_init(bst);
+        __syncthreads();
+    }
     // grid-stride over wave-aligned chunks (the grid is capped)
     for (long long base = (long long)blockIdx.x * blockDim.x; base < P.n_traj;
          base += (long long)gridDim.x * blockDim.x)
-        rk4_one(P, g, o, base + threadIdx.x);
+        rk4_one<FUSED>(P, g, o, base + threadIdx.x, qa, bst);
+    if constexpr (FUSED) {
+        __syncthreads();
+        block_stats_flush(bst, qa.stats);
+    }
 }
 
 
@@ -138,11 +153,21 @@ constexpr int DP5_DEFAULT_BLOCK = 768;
 // CULL: some start radius lies beyond R_exit.  Without one no relic can be
 // culled, and the kernel leaves the test out: its branch alone costs the
 // trajectory loop a few percent in register moves.
-template <int NC, bool CULL, bool HIST>
+// FUSED: each finished trajectory adds its quadrature term and statistics
+// directly (QuadAcc); nothing is written per trajectory.
+template <int NC, bool CULL, bool HIST, bool FUSED>
 __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
-                                                             unsigned long long *counter)
+                                                             unsigned long long *counter, QuadAcc qa)
 {
     extern __shared__ double lds_tab[];
+    __shared__ BlockStats bst;
+    // the workgroup's partial sums follow the table
+    unsigned long long *const lacc =
+        (unsigned long long *)((char *)lds_tab + quad_lds_offset((size_t)P.n_tab * NC * sizeof(double)));
+    if constexpr (FUSED) {
+        block_stats_init(bst);
+        quad_lds_init(lacc, qa.lds_n);
+    }
     // stage the first NC columns of every node, rows of NC doubles
     for (int i = threadIdx.x; i < P.n_tab * NC; i += blockDim.x) {
         const int node = i / NC, col = i - node * NC;
@@ -151,6 +176,9 @@ __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridP
     __syncthreads();
 
     const TabCoef<NC, NC, HIST> cf{lds_tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
+    __shared__ StartCache sc;
+    start_cache_fill(sc, cf, P.h0, P.u_start, P.u_end);
+    __syncthreads();
     DpCtl ctl;
     ctl.u_end = P.u_end;
     ctl.rtol = P.rtol;
@@ -168,20 +196,23 @@ __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridP
         if (need) {
             if (p < P.n_traj) {
                 t = traj_of(p, P);
-                const int l = (int)(t % P.n_mu);
-                const long long kj = t / P.n_mu;
-                const int j = (int)(kj % P.n_y);
-                const int k = (int)(kj / P.n_y);
+                const TrajIdx ix = traj_idx(t, P);
+                const int l = ix.l, j = ix.j, k = ix.k;
                 const double V = g.y[j] * P.vfac;
                 const double vx0 = V * g.mu[l], vy0 = V * g.smu[l];
                 v0n = sqrt(norm2(vx0, vy0));
                 if (CULL && never_enters(g.r[k], vx0, vy0, P.cull_D, cull_radius2(P.r_exit))) {
                     // App. B cull: the path never reaches R, the momentum is final
-                    o.ratio[t] = 1.0;
-                    o.stat[t] = TrajStat{0, 0, ST_OK | ST_FREE_EXIT, 0};
+                    const TrajStat ts{0, 0, ST_OK | ST_FREE_EXIT, 0};
+                    if constexpr (FUSED) {
+                        fused_finish(P, g, qa, lacc, bst, t, 1.0, ts);
+                    } else {
+                        o.ratio[t] = 1.0;
+                        o.stat[t] = ts;
+                    }
                     t = -1;
                 } else {
-                    dp5_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_start, P.u_end);
+                    dp5_start_cached(L, sc, g.r[k], vx0, vy0, P.u_start);
                 }
             } else {
                 t = -2;
@@ -193,12 +224,51 @@ __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridP
         if (t >= 0) {
             const int st = dp5_attempt(L, cf, ctl);
             if (st >= 0) {
-                o.ratio[t] = sqrt(norm2(L.vx, L.vy)) / v0n;
-                o.stat[t] = TrajStat{L.nacc, L.nrej, st, 0};
+                const double ratio = sqrt(norm2(L.vx, L.vy)) / v0n;
+                const TrajStat ts{L.nacc, L.nrej, st, 0};
+                if constexpr (FUSED) {
+                    fused_finish(P, g, qa, lacc, bst, t, ratio, ts);
+                } else {
+                    o.ratio[t] = ratio;
+                    o.stat[t] = ts;
+                }
                 t = -1;
             }
         }
     }
+    if constexpr (FUSED) {
+        __syncthreads();
+        block_stats_flush(bst, qa.stats);
+        quad_lds_flush(qa, lacc);
+    }
+}
+
+// Fused quadrature, before the trajectories: the power-of-two scale of the
+// sums, the exact background sum, and cleared radius sums and statistics
+// (one 256-thread block; a kernel rather than memsets, so that a captured
+// sequence replays correctly).
+__global__ __launch_bounds__(256) void k_quad_setup(TrajParams P, GridPtrs g, QuadAcc qa)
+{
+    for (long long i = threadIdx.x; i < 2 * (long long)P.n_r; i += blockDim.x) qa.num[i] = 0ull;
+    if (threadIdx.x < 6) qa.stats[threadIdx.x] = 0ull;
+    const double scale = quad_scale(P, g);
+    const Fix128 den = quad_den(P, g, scale);
+    if (threadIdx.x == 0) {
+        *qa.scale = scale;
+        qa.den[0] = den.lo;
+        qa.den[1] = den.hi;
+    }
+}
+
+// Fused quadrature, after the trajectories: n/nbar_k = num_k / den.  With no
+// halo every term equals its background term, so num_k = den: exactly 1.
+__global__ __launch_bounds__(256) void k_quad_finish(int n_r, QuadAcc qa, int free_all, double *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_r) return;
+    const Fix128 den{qa.den[0], qa.den[1]};
+    const Fix128 num = free_all ? den : Fix128{qa.num[2 * (size_t)k], qa.num[2 * (size_t)k + 1]};
+    out[k] = fix_to_double(num) / fix_to_double(den);
 }
 
 // ---------------------------------------------------------------------------
@@ -273,15 +343,20 @@ hipError_t launch_free_all(long long n, const TrajOut &o, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, hipStream_t s)
+hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, const QuadAcc *qa, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rk4_f64, dim3(capped_blocks(P.n_traj, 256)), dim3(256), 0, s, P, g, o);
+    if (qa)
+        hipLaunchKernelGGL(k_rk4_f64<true>, dim3(capped_blocks(P.n_traj, 256)), dim3(256), 0, s, P, g, o, *qa);
+    else
+        hipLaunchKernelGGL(k_rk4_f64<false>, dim3(capped_blocks(P.n_traj, 256)), dim3(256), 0, s, P, g, o,
+                           QuadAcc{});
     return hipGetLastError();
 }
 
 // The LDS attribute and the occupancy query cost host time at every launch;
 // their answer depends only on the kernel, the block size and the LDS bytes,
-// so it is kept per (kernel, block, bytes).
+// so it is kept per (kernel, block, bytes) in a fixed table (no heap memory:
+// the allocation-free entry point launches through here too).
 hipError_t occupancy_cached(const void *fn, int block, size_t lds, int *per_cu)
 {
     struct Entry {
@@ -290,64 +365,119 @@ hipError_t occupancy_cached(const void *fn, int block, size_t lds, int *per_cu)
         size_t lds;
         int per_cu;
     };
+    constexpr int CAP = 256;
     static std::mutex mu;
-    static std::vector<Entry> cache;
+    static Entry cache[CAP];
+    static int n = 0;
     std::lock_guard<std::mutex> lk(mu);
-    for (const Entry &e : cache)
-        if (e.fn == fn && e.block == block && e.lds == lds) {
-            *per_cu = e.per_cu;
+    for (int i = 0; i < n; ++i)
+        if (cache[i].fn == fn && cache[i].block == block && cache[i].lds == lds) {
+            *per_cu = cache[i].per_cu;
             return hipSuccess;
         }
     // the attribute is a per-kernel upper bound: never lower it below a size
-    // an earlier (cached) launch of the same kernel relies on
+    // an earlier launch of the same kernel relies on (a kernel seen more often
+    // than the table holds keeps the largest size it has been given)
+    static struct {
+        const void *fn;
+        size_t lds;
+    } attr_max[CAP];
+    static int n_attr = 0;
     size_t attr = lds;
-    for (const Entry &e : cache)
-        if (e.fn == fn) attr = std::max(attr, e.lds);
+    int slot = -1;
+    for (int i = 0; i < n_attr; ++i)
+        if (attr_max[i].fn == fn) {
+            slot = i;
+            attr = std::max(attr, attr_max[i].lds);
+        }
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)attr);
     if (e != hipSuccess) return e;
+    if (slot < 0 && n_attr < CAP) slot = n_attr++, attr_max[slot].fn = fn;
+    if (slot >= 0) attr_max[slot].lds = attr;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, block, lds);
     if (e != hipSuccess) return e;
-    cache.push_back(Entry{fn, block, lds, *per_cu});
+    if (n < CAP) cache[n++] = Entry{fn, block, lds, *per_cu};
     return hipSuccess;
 }
 
-template <int NC, bool CULL, bool HIST>
+// The fused kernels' per-workgroup partial sums (16 bytes a radius after the
+// table) are used when they fit in LDS and keep the occupancy; otherwise the
+// terms go straight to the global sums.
+hipError_t quad_lds_plan(const void *fn, int block, int per_cu, int n_r, size_t &lds, QuadAcc &q)
+{
+    q.lds_n = 0;
+    const size_t base = quad_lds_offset(lds);
+    const size_t with = base + (size_t)n_r * 2 * sizeof(unsigned long long);
+    if (n_r < 1 || with > QUAD_LDS_LIMIT) return hipSuccess;
+    int per_cu2 = 0;
+    const hipError_t e = occupancy_cached(fn, block, with, &per_cu2);
+    if (e != hipSuccess) return e;
+    if (per_cu2 == per_cu) {
+        q.lds_n = n_r;
+        lds = with;
+    }
+    return hipSuccess;
+}
+
+template <int NC, bool CULL, bool HIST, bool FUSED>
 static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                                unsigned long long *counter, int n_cu, hipStream_t s)
+                                unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
 {
     const int B = P.block > 0 ? P.block : DP5_DEFAULT_BLOCK;
-    const size_t lds = (size_t)P.n_tab * NC * sizeof(double);
+    size_t lds = (size_t)P.n_tab * NC * sizeof(double);
     int per_cu = 0;
-    const hipError_t e = occupancy_cached((const void *)k_dp5_f64<NC, CULL, HIST>, B, lds, &per_cu);
+    hipError_t e = occupancy_cached((const void *)k_dp5_f64<NC, CULL, HIST, FUSED>, B, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
+    QuadAcc q = qa;
+    if (FUSED) {
+        e = quad_lds_plan((const void *)k_dp5_f64<NC, CULL, HIST, FUSED>, B, per_cu, P.n_r, lds, q);
+        if (e != hipSuccess) return e;
+    }
     long long grid = (long long)n_cu * per_cu;
     if (P.max_wg > 0 && grid > P.max_wg) grid = P.max_wg;
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
-    auto *kern = k_dp5_f64<NC, CULL, HIST>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter);
+    auto *kern = k_dp5_f64<NC, CULL, HIST, FUSED>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter, q);
     return hipGetLastError();
 }
 
-template <bool HIST>
+template <bool HIST, bool FUSED>
 static hipError_t launch_dp5_hist(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                                 unsigned long long *counter, int n_cu, hipStream_t s)
+                                  unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
 {
     const bool cull = P.cull_D > 0.0;
     if (P.R_const > 0.0)
-        return cull ? launch_dp5_nc<NCOL - 1, true, HIST>(P, g, o, counter, n_cu, s)
-                    : launch_dp5_nc<NCOL - 1, false, HIST>(P, g, o, counter, n_cu, s);
-    return cull ? launch_dp5_nc<NCOL, true, HIST>(P, g, o, counter, n_cu, s)
-                : launch_dp5_nc<NCOL, false, HIST>(P, g, o, counter, n_cu, s);
+        return cull ? launch_dp5_nc<NCOL - 1, true, HIST, FUSED>(P, g, o, counter, qa, n_cu, s)
+                    : launch_dp5_nc<NCOL - 1, false, HIST, FUSED>(P, g, o, counter, qa, n_cu, s);
+    return cull ? launch_dp5_nc<NCOL, true, HIST, FUSED>(P, g, o, counter, qa, n_cu, s)
+                : launch_dp5_nc<NCOL, false, HIST, FUSED>(P, g, o, counter, qa, n_cu, s);
 }
 
 hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                          unsigned long long *counter, int n_cu, hipStream_t s)
+                          unsigned long long *counter, const QuadAcc *qa, int n_cu, hipStream_t s)
 {
-    return P.hist ? launch_dp5_hist<true>(P, g, o, counter, n_cu, s)
-                  : launch_dp5_hist<false>(P, g, o, counter, n_cu, s);
+    const QuadAcc q = qa ? *qa : QuadAcc{};
+    if (qa)
+        return P.hist ? launch_dp5_hist<true, true>(P, g, o, counter, q, n_cu, s)
+                      : launch_dp5_hist<false, true>(P, g, o, counter, q, n_cu, s);
+    return P.hist ? launch_dp5_hist<true, false>(P, g, o, counter, q, n_cu, s)
+                  : launch_dp5_hist<false, false>(P, g, o, counter, q, n_cu, s);
+}
+
+hipError_t launch_quad_setup(const TrajParams &P, const GridPtrs &g, const QuadAcc &qa, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quad_setup, dim3(1), dim3(256), 0, s, P, g, qa);
+    return hipGetLastError();
+}
+
+hipError_t launch_quad_finish(int n_r, const QuadAcc &qa, bool free_all, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quad_finish, dim3((unsigned)((n_r + 255) / 256)), dim3(256), 0, s, n_r, qa,
+                       free_all ? 1 : 0, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,

@@ -36,6 +36,7 @@ struct nh_context {
     char err[512] = "";
     hipStream_t stream = nullptr;                    // used by nh_solve
     nh::DevBuf blob, ratio, stat, small, out;
+    nh::DevBuf quad;                                 // fused quadrature sums (QuadAcc)
     nh::DevBuf bctr;                                 // batched form: counters and statistics
     void *h_stage = nullptr;                         // pinned staging for the inputs
     unsigned long long *h_stats = nullptr;           // pinned copy of the last solve's statistics
@@ -43,6 +44,8 @@ struct nh_context {
     hipEvent_t ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
     bool pending = false;
     long long last_n_traj = -1;
+    bool last_traj_kept = false;                     // the last solve stored per-trajectory results
+    bool keep_traj = false;                          // NH_OPT_TRAJECTORY_STATS
     // tunables (nh_set_option)
     int queue_order = nh::ORDER_NATURAL;
     bool free_exit = true;
@@ -74,6 +77,21 @@ size_t per_traj_bytes(const nh_request *q);
 void serve_shutdown(nh_context *ctx);
 bool serve_idle(nh_context *ctx);
 int wait_pending(nh_context *ctx);
+// Device buffers of one plain solve: staged inputs, the counter and statistics
+// words (counter at small[0], statistics at small[8..15]), and either the
+// fused quadrature's sums (qa.num != null) or per-trajectory results.
+struct SolveBufs {
+    char *blob;
+    unsigned long long *small;
+    QuadAcc qa;
+    double *ratio;
+    TrajStat *stat;
+};
+// Enqueue the kernels of one plain solve whose inputs are staged in b.blob.
+int solve_launch(nh_context *ctx, const nh_request *q, const Staged &s, TrajParams P, const SolveBufs &b,
+                 double *d_out, hipStream_t stream, int n_mass, double *d_integrand);
+size_t quad_bytes(int n_r);
+QuadAcc quad_acc(void *base, int n_r, unsigned long long *stats);
 // Enqueue one plain solve: trajectories, then the profile (or one profile per
 // mass), and optionally the angle-integrated distribution per radius and momentum.
 int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d_ratio, hipStream_t stream,

@@ -282,39 +282,65 @@ __device__ __forceinline__ double f0_eval(const F0Desc &f, double y)
     return 1.0 / (1.0 + exp(y));
 }
 
-// Queue position -> trajectory index.
-__device__ __forceinline__ long long traj_of(long long p, const TrajParams &P)
+// Index arithmetic below runs in 32 bits whenever the launch has fewer than
+// 2^32 trajectories (a wave-uniform test): a 64-bit integer division is a
+// long software sequence on the vector unit, a 32-bit one a few instructions,
+// and a lane pays for them each time it starts or finishes a trajectory.
+__device__ __forceinline__ bool idx32(const TrajParams &P) { return P.n_traj <= 0xffffffffLL; }
+
+// Trajectory t = (k n_y + j) n_mu + l -> radius k, momentum j, angle l.
+struct TrajIdx {
+    int k, j, l;
+};
+
+__device__ __forceinline__ TrajIdx traj_idx(long long t, const TrajParams &P)
 {
+    if (idx32(P)) {
+        const unsigned u = (unsigned)t, nm = (unsigned)P.n_mu, ny = (unsigned)P.n_y;
+        const unsigned kj = u / nm, k = kj / ny;
+        return TrajIdx{(int)k, (int)(kj - k * ny), (int)(u - kj * nm)};
+    }
+    const long long kj = t / P.n_mu, k = kj / P.n_y;
+    return TrajIdx{(int)k, (int)(kj - k * P.n_y), (int)(t - kj * P.n_mu)};
+}
+
+template <class I>
+__device__ __forceinline__ I traj_of_w(I p, const TrajParams &P)
+{
+    const I n_mu = (I)P.n_mu, n_y = (I)P.n_y, n_r = (I)P.n_r;
     if (P.order == ORDER_SLOW_FIRST) {
-        const long long l = p % P.n_mu;
-        const long long q = p / P.n_mu;
-        const long long k = q % P.n_r;
-        const long long j = q / P.n_r;
-        return (k * P.n_y + j) * P.n_mu + l;
+        const I q = p / n_mu, l = p - q * n_mu;
+        const I j = q / n_r, k = q - j * n_r;
+        return (k * n_y + j) * n_mu + l;
     }
     if (P.order == ORDER_SPREAD) {
         // full 64-trajectory blocks, in rounds of one block per wave of the
         // grid; a round is a (waves per workgroup) x (workgroups) matrix read
         // column-wise, so consecutive blocks - neighbouring radii and momenta,
         // similar in cost - are claimed by different workgroups
-        const long long P_ = blockDim.x >> 6, Q_ = gridDim.x, W_ = P_ * Q_;
-        const long long nbf = P.n_traj >> 6, b = p >> 6;
-        const long long full_rounds = nbf / W_;
+        const I P_ = (I)(blockDim.x >> 6), Q_ = (I)gridDim.x, W_ = P_ * Q_;
+        const I nbf = (I)(P.n_traj >> 6), b = p >> 6;
+        const I full_rounds = nbf / W_;
         if (b < full_rounds * W_) {
-            const long long r = b / W_, i = b - r * W_;
-            const long long i_p = i / P_;
+            const I r = b / W_, i = b - r * W_;
+            const I i_p = i / P_;
             return ((r * W_ + (i - i_p * P_) * Q_ + i_p) << 6) + (p & 63);
         }
         return p;
     }
     if (P.order == ORDER_Y_FASTEST) {
-        const long long j = p % P.n_y;
-        const long long q = p / P.n_y;
-        const long long l = q % P.n_mu;
-        const long long k = q / P.n_mu;
-        return (k * P.n_y + j) * P.n_mu + l;
+        const I q = p / n_y, j = p - q * n_y;
+        const I k = q / n_mu, l = q - k * n_mu;
+        return (k * n_y + j) * n_mu + l;
     }
     return p;
+}
+
+// Queue position -> trajectory index.
+__device__ __forceinline__ long long traj_of(long long p, const TrajParams &P)
+{
+    if (idx32(P)) return (long long)traj_of_w<unsigned>((unsigned)p, P);
+    return traj_of_w<long long>(p, P);
 }
 
 // One atomic per wavefront hands consecutive queue positions to the lanes

@@ -82,23 +82,69 @@ struct Lane64 {
     bool rej_prev;
 };
 
-// Start a trajectory at u = u_start (first stage evaluated here).
-template <class CF>
-__device__ __forceinline__ void dp5_start(Lane64 &L, const CF &cf, double x0, double vx0, double vy0,
-                                          double h0, double u_start, double u_end)
+// The first step: -|h0|, clipped to the whole interval.
+__host__ __device__ __forceinline__ double dp5_first_step(double h0, double u_start, double u_end)
+{
+    const double h = -fabs(h0);
+    return fabs(h) > fabs(u_end - u_start) ? u_end - u_start : h;
+}
+
+// Start a trajectory at u = u_start from the coefficients there (c, R) and
+// the first step h: the state and the first stage.
+__device__ __forceinline__ void dp5_start_at(Lane64 &L, const double c[NCOL], double R, double x0, double vx0,
+                                             double vy0, double h, double u_start)
 {
     L.x = x0;
     L.y = 0.0;
     L.vx = vx0;
     L.vy = vy0;
     L.u = u_start;
-    L.h = -fabs(h0);
-    if (fabs(L.h) > fabs(u_end - u_start)) L.h = u_end - u_start;
+    L.h = h;
     L.nacc = L.nrej = L.natt = 0;
     L.rej_prev = false;
+    rhs(c, R, L.x, L.y, L.vx, L.vy, L.k1x, L.k1y, L.k1u, L.k1v);
+}
+
+// Start a trajectory at u = u_start (first stage evaluated here).
+template <class CF>
+__device__ __forceinline__ void dp5_start(Lane64 &L, const CF &cf, double x0, double vx0, double vy0,
+                                          double h0, double u_start, double u_end)
+{
     double c[NCOL], R;
     cf.at(u_start, c, R);
-    rhs(c, R, L.x, L.y, L.vx, L.vy, L.k1x, L.k1y, L.k1u, L.k1v);
+    dp5_start_at(L, c, R, x0, vx0, vy0, dp5_first_step(h0, u_start, u_end), u_start);
+}
+
+// Every lane of a launch starts at the same u: the coefficients there and the
+// first step are computed once per workgroup into LDS (after the table is
+// staged; a barrier follows) and read back at each start.  The reads are
+// volatile so that they stay at the start and are not hoisted out of the
+// trajectory loop, where they would hold registers for its whole length.
+struct StartCache {
+    double c[NCOL];
+    double R, h;
+};
+
+template <class CF>
+__device__ __forceinline__ void start_cache_fill(StartCache &sc, const CF &cf, double h0, double u_start,
+                                                 double u_end)
+{
+    if (threadIdx.x == 0) {
+        double c[NCOL], R;
+        cf.at(u_start, c, R);
+        for (int i = 0; i < NCOL; ++i) sc.c[i] = c[i];
+        sc.R = R;
+        sc.h = dp5_first_step(h0, u_start, u_end);
+    }
+}
+
+__device__ __forceinline__ void dp5_start_cached(Lane64 &L, const StartCache &sc, double x0, double vx0,
+                                                 double vy0, double u_start)
+{
+    const volatile StartCache &v = sc;
+    double c[NCOL];
+    for (int i = 0; i < NCOL; ++i) c[i] = v.c[i];
+    dp5_start_at(L, c, v.R, x0, vx0, vy0, v.h, u_start);
 }
 
 // One attempted step.  Returns -1 while the trajectory continues, else its

@@ -135,6 +135,19 @@ struct TrajOut {
     TrajStat *stat;         // n_traj
 };
 
+// Device buffers of a fused quadrature (the trajectory kernels add each
+// finished trajectory's term, nothing is stored per trajectory): num holds the
+// 128-bit fixed-point sum of radius k in words 2k (low) and 2k+1 (high), den
+// the background sum likewise, scale the power of two applied to every term,
+// stats the six counters of the statistics.
+struct QuadAcc {
+    unsigned long long *num;
+    unsigned long long *den;
+    double *scale;
+    unsigned long long *stats;
+    int lds_n;    // radii 0 .. lds_n-1 summed per workgroup in LDS first (0: straight to num)
+};
+
 // ---- batched and serving forms (scheduling: nh_batch.h) ----
 
 enum : int {

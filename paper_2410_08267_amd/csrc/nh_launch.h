@@ -9,11 +9,19 @@ namespace nh {
 
 hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
 hipError_t launch_free_all(long long n, const TrajOut &o, hipStream_t s);
-hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, hipStream_t s);
+hipError_t launch_rk4_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o, const QuadAcc *qa,
+                          hipStream_t s);
+// qa: the fused quadrature's buffers (no per-trajectory output), or null to
+// write o.ratio and o.stat for every trajectory
 hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                          unsigned long long *counter, int n_cu, hipStream_t s);
+                          unsigned long long *counter, const QuadAcc *qa, int n_cu, hipStream_t s);
 hipError_t launch_dp5_f32c(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                           unsigned long long *counter, int n_cu, hipStream_t s);
+                           unsigned long long *counter, const QuadAcc *qa, int n_cu, hipStream_t s);
+// fused quadrature: scale, background sum and cleared sums before the
+// trajectories; the profile after them
+hipError_t launch_quad_setup(const TrajParams &P, const GridPtrs &g, const QuadAcc &qa, hipStream_t s);
+// free_all: no halo (every profile point is exactly 1)
+hipError_t launch_quad_finish(int n_r, const QuadAcc &qa, bool free_all, double *out, hipStream_t s);
 hipError_t launch_reduce_profile(const TrajParams &P, const GridPtrs &g, const double *ratio,
                                  double *out, hipStream_t s);
 hipError_t launch_reduce_stats(long long n, const TrajOut &o, unsigned long long *stats,
@@ -38,6 +46,9 @@ hipError_t launch_slice(const SliceArgs &A, bool f32c, int nc, int slots, bool p
 const void *fill_u64_kernel();
 // hipFuncSetAttribute (dynamic LDS) and the occupancy query, kept per (kernel, block, bytes)
 hipError_t occupancy_cached(const void *fn, int block, size_t lds, int *per_cu);
+// Sets q.lds_n = n_r and grows lds by the partial sums when they fit without
+// lowering per_cu (blocks per CU); q.lds_n = 0 otherwise.
+hipError_t quad_lds_plan(const void *fn, int block, int per_cu, int n_r, size_t &lds, QuadAcc &q);
 
 // A serving slice captured as a HIP graph (descriptor and order uploads, the
 // in-flight clear, the slice kernel, the read-back of queue positions and

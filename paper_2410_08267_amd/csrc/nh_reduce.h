@@ -1,42 +1,143 @@
-// Reductions after the trajectory kernels, shared by the plain and batched paths.
+// The momentum-space quadrature (Eqs. density_integral and localdensity with
+// the background density that follows them):
+//   n/nbar_k = sum_jl W_jl f0(y_j ratio_kjl) / sum_jl W_jl f0(y_j),
+// W_jl = w_y,j w_mu,l, shared by the trajectory kernels' epilogue (fused
+// quadrature), the reduction over stored ratios and the batched forms.
+//
+// The sums are exact.  Every term is scaled by a power of two (so that the
+// background sum lies in [1, 2)) and converted to a 128-bit fixed-point number
+// with 96 fraction bits; the additions are then integer additions, which are
+// associative, so a profile does not depend on the order of its terms: the
+// fused epilogue (terms added by atomics as trajectories finish) and the
+// reduction over stored ratios give the same bits, for any launch shape or
+// queue order.  Terms of at least 2^-44 of the background sum convert exactly,
+// smaller ones lose less than 2^-96 of it each; the integer part holds 32 bits
+// (n/nbar < 4e9).  The converted sum is rounded to FP64 once.
 #pragma once
 
 #include "nh_device.h"
 
 namespace nh {
 
-// Momentum-space quadrature at radius k by one 256-thread block
-// (Eqs. density_integral and localdensity with the background density that
-// follows them): out[k] = sum_jl W_jl f0(y_j ratio_kjl) / sum_jl W_jl f0(y_j),
-// W_jl = w_y,j w_mu,l.  Fixed summation order: thread-strided partial sums,
-// then a tree in LDS.
+// 128-bit unsigned fixed point: value = (hi 2^64 + lo) 2^-96.
+struct Fix128 {
+    unsigned long long lo, hi;
+};
+
+__device__ __forceinline__ Fix128 to_fix(double c)
+{
+    const double t = c * 4294967296.0;                       // c 2^32, exact
+    const unsigned long long hi = (unsigned long long)t;     // floor
+    const double r = t - (double)hi;                          // exact, in [0, 1)
+    return Fix128{(unsigned long long)(r * 18446744073709551616.0), hi};
+}
+
+__device__ __forceinline__ void fix_add(Fix128 &a, const Fix128 &b)
+{
+    const unsigned long long lo = a.lo + b.lo;
+    a.hi += b.hi + (lo < a.lo ? 1ull : 0ull);
+    a.lo = lo;
+}
+
+// Atomic a += b on two consecutive words (lo, hi): the carry out of lo is added
+// to hi by the thread that caused it, so the final pair is exact whatever the
+// interleaving.
+__device__ __forceinline__ void fix_atomic_add(unsigned long long *a, const Fix128 &b)
+{
+    const unsigned long long old = atomicAdd(a, b.lo);
+    const unsigned long long carry = (old + b.lo < old) ? 1ull : 0ull;
+    if (b.hi + carry) atomicAdd(a + 1, b.hi + carry);
+}
+
+__device__ __forceinline__ double fix_to_double(const Fix128 &a)
+{
+    return (double)a.hi * 2.3283064365386963e-10 + (double)a.lo * 1.2621774483536189e-29;   // 2^-32, 2^-96
+}
+
+// Term (j, l) of the sums for speed ratio P_i/P0: W_jl f0(y_j ratio), scaled.
+__device__ __forceinline__ double quad_term(const GridPtrs &g, int j, int l, double ratio, double scale)
+{
+    const double W = g.wy[j] * g.wmu[l];
+    const double f = f0_eval(g.f0, g.y[j] * ratio);
+    return (W * f) * scale;
+}
+
+// The power of two that brings the background sum into [1, 2), from an FP64
+// sum in a fixed order by one 256-thread block (every block and kernel that
+// calls it gets the same value).  Called by all threads of the block.
+__device__ __forceinline__ double quad_scale(const TrajParams &P, const GridPtrs &g)
+{
+    const long long ne = (long long)P.n_y * P.n_mu;
+    double den = 0.0;
+    for (long long e = threadIdx.x; e < ne; e += blockDim.x) {
+        const int j = (int)(e / P.n_mu);
+        const int l = (int)(e - (long long)j * P.n_mu);
+        den += quad_term(g, j, l, 1.0, 1.0);
+    }
+    __shared__ double sd[256];
+    sd[threadIdx.x] = den;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double d = sd[0];
+    __syncthreads();
+    return d > 0.0 ? __builtin_amdgcn_ldexp(1.0, -__builtin_amdgcn_frexp_exp(d) + 1) : 1.0;
+}
+
+// Exact sum over the block's threads (256) of per-thread fixed-point values;
+// the result is valid in thread 0.
+__device__ __forceinline__ Fix128 block_fix_sum(Fix128 v)
+{
+    __shared__ unsigned long long slo[256], shi[256];
+    slo[threadIdx.x] = v.lo;
+    shi[threadIdx.x] = v.hi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            Fix128 a{slo[threadIdx.x], shi[threadIdx.x]};
+            fix_add(a, Fix128{slo[threadIdx.x + s], shi[threadIdx.x + s]});
+            slo[threadIdx.x] = a.lo;
+            shi[threadIdx.x] = a.hi;
+        }
+        __syncthreads();
+    }
+    const Fix128 r{slo[0], shi[0]};
+    __syncthreads();
+    return r;
+}
+
+// The background sum, exactly, by one 256-thread block (valid in thread 0).
+__device__ __forceinline__ Fix128 quad_den(const TrajParams &P, const GridPtrs &g, double scale)
+{
+    const long long ne = (long long)P.n_y * P.n_mu;
+    Fix128 den{0ull, 0ull};
+    for (long long e = threadIdx.x; e < ne; e += blockDim.x) {
+        const int j = (int)(e / P.n_mu);
+        const int l = (int)(e - (long long)j * P.n_mu);
+        fix_add(den, to_fix(quad_term(g, j, l, 1.0, scale)));
+    }
+    return block_fix_sum(den);
+}
+
+// n/nbar at radius k from the stored ratios, by one 256-thread block.
 __device__ __forceinline__ void reduce_radius(const TrajParams &P, const GridPtrs &g,
                                               const double *__restrict__ ratio, int k,
                                               double *__restrict__ out)
 {
+    const double scale = quad_scale(P, g);
     const long long ne = (long long)P.n_y * P.n_mu;
-    double num = 0.0, den = 0.0;
     const double *rk = ratio + (size_t)k * ne;
+    Fix128 num{0ull, 0ull};
     for (long long e = threadIdx.x; e < ne; e += blockDim.x) {
         const int j = (int)(e / P.n_mu);
         const int l = (int)(e - (long long)j * P.n_mu);
-        const double W = g.wy[j] * g.wmu[l];
-        const double yj = g.y[j];
-        num += W * f0_eval(g.f0, yj * rk[e]);
-        den += W * f0_eval(g.f0, yj);
+        fix_add(num, to_fix(quad_term(g, j, l, rk[e], scale)));
     }
-    __shared__ double sn[256], sd[256];
-    sn[threadIdx.x] = num;
-    sd[threadIdx.x] = den;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            sn[threadIdx.x] += sn[threadIdx.x + s];
-            sd[threadIdx.x] += sd[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sn[0] / sd[0];
+    const Fix128 n = block_fix_sum(num);
+    const Fix128 d = quad_den(P, g, scale);
+    if (threadIdx.x == 0) out[k] = fix_to_double(n) / fix_to_double(d);
 }
 
 // Integer statistics of trajectories t = first, first + step, ... < n (exact
@@ -85,6 +186,90 @@ __device__ __forceinline__ void reduce_stats_range(const TrajStat *__restrict__ 
         for (int i = 1; i < nw; ++i) v = (c == 2) ? (part[i][c] > v ? part[i][c] : v) : v + part[i][c];
         if (c == 2) atomicMax(stats + c, v);
         else atomicAdd(stats + c, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused quadrature: the trajectory kernels add each finished trajectory's term
+// and statistics directly, with no per-trajectory output
+// ---------------------------------------------------------------------------
+
+// Workgroup statistics in LDS, flushed to the global counters once at the end.
+struct BlockStats {
+    unsigned long long acc, rej, mx, fail, f64, fre;
+};
+
+__device__ __forceinline__ void block_stats_init(BlockStats &b)
+{
+    if (threadIdx.x == 0) b = BlockStats{0, 0, 0, 0, 0, 0};
+}
+
+// The fused kernels' LDS partial sums start at this byte offset after a table
+// of the given size; a launch holds at most QUAD_LDS_LIMIT bytes of dynamic LDS
+// (160 KiB per workgroup on gfx950, less room for the kernels' static LDS).
+constexpr size_t QUAD_LDS_LIMIT = 160 * 1024 - 1024;
+__host__ __device__ constexpr size_t quad_lds_offset(size_t table_bytes)
+{
+    return (table_bytes + 15) & ~(size_t)15;
+}
+
+// The same on a workgroup's LDS copy (no other workgroup touches it).
+__device__ __forceinline__ void fix_lds_add(unsigned long long *a, const Fix128 &b)
+{
+    const unsigned long long old = __hip_atomic_fetch_add(a, b.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const unsigned long long c = b.hi + ((old + b.lo < old) ? 1ull : 0ull);
+    if (c) __hip_atomic_fetch_add(a + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Workgroup partial sums of radii 0 .. q.lds_n-1: (lo, hi) pairs in LDS,
+// cleared before the workgroup's first trajectory (then a barrier) and added
+// to the global sums once after its last (after a barrier).  An LDS atomic
+// returns in far fewer cycles than a device-scope one, and the lane that
+// finishes a trajectory waits for it (the carry).
+__device__ __forceinline__ void quad_lds_init(unsigned long long *lacc, int n)
+{
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) lacc[i] = 0ull;
+}
+
+__device__ __forceinline__ void quad_lds_flush(const QuadAcc &q, const unsigned long long *lacc)
+{
+    for (int k = threadIdx.x; k < q.lds_n; k += blockDim.x) {
+        const Fix128 v{lacc[2 * k], lacc[2 * k + 1]};
+        if (v.lo | v.hi) fix_atomic_add(q.num + 2 * (size_t)k, v);
+    }
+}
+
+// A finished trajectory t: its quadrature term into radius k's sum (the
+// workgroup's LDS partial when there is one), its statistics into the
+// workgroup's.
+__device__ __forceinline__ void fused_finish(const TrajParams &P, const GridPtrs &g, const QuadAcc &q,
+                                             unsigned long long *lacc, BlockStats &b, long long t, double ratio,
+                                             const TrajStat &ts)
+{
+    const TrajIdx ix = traj_idx(t, P);
+    const int l = ix.l, j = ix.j, k = ix.k;
+    const Fix128 v = to_fix(quad_term(g, j, l, ratio, *q.scale));
+    if (k < q.lds_n) fix_lds_add(lacc + 2 * k, v);
+    else fix_atomic_add(q.num + 2 * (size_t)k, v);
+    const unsigned long long a = (unsigned)ts.acc, r = (unsigned)ts.rej;
+    __hip_atomic_fetch_add(&b.acc, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&b.rej, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_max(&b.mx, a + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if ((ts.status & 0xff) != ST_OK) __hip_atomic_fetch_add(&b.fail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (ts.fp64) __hip_atomic_fetch_add(&b.f64, (unsigned long long)(unsigned)ts.fp64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (ts.status & ST_FREE_EXIT) __hip_atomic_fetch_add(&b.fre, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// After the workgroup's last trajectory (all threads, after a barrier).
+__device__ __forceinline__ void block_stats_flush(const BlockStats &b, unsigned long long *stats)
+{
+    if (threadIdx.x == 0) {
+        atomicAdd(stats + 0, b.acc);
+        atomicAdd(stats + 1, b.rej);
+        atomicMax(stats + 2, b.mx);
+        atomicAdd(stats + 3, b.fail);
+        atomicAdd(stats + 4, b.f64);
+        atomicAdd(stats + 5, b.fre);
     }
 }
 

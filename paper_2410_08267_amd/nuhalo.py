@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(HERE, "libnuhalo.so")
 NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ESTEPS = 0, -1, -2, -3, -4
 NH_ENONFINITE, NH_EBUSY, NH_ENOTREADY, NH_ENOTFOUND, NH_ECANCELED = -5, -6, -7, -8, -9
 OPTIONS = {"queue_order": 1, "free_exit": 2, "fp64_below_h": 3, "table_nodes": 4, "block_threads": 5,
-           "batch_slots": 6, "slice_us": 7, "serve_graph": 8, "workgroups": 9, "fp32c_rtol": 10}
+           "batch_slots": 6, "slice_us": 7, "serve_graph": 8, "workgroups": 9, "fp32c_rtol": 10,
+           "trajectory_stats": 11}
 
 _MASS = {"zero": 0, "paper": 1, "exponential": 2, "table": 3}
 _CONC = {"constant": 0, "power": 1, "table": 2}
@@ -116,7 +117,7 @@ _SIGNATURES = {
     "nh_solve_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_request), ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "nh_last_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_stats)]),
-    "nh_last_trajectory_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+    "nh_last_trajectory_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "nh_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(nh_request),
                                       ctypes.c_void_p, ctypes.POINTER(nh_stats), ctypes.c_void_p]),
@@ -352,12 +353,13 @@ class Context:
         return st.as_dict(), rc
 
     def trajectory_stats(self, n_traj: int):
-        """(accepted, rejected, status) per trajectory of the last completed solve."""
+        """(accepted, rejected, status) per trajectory of the last completed solve
+        (one that stored per-trajectory results); n_traj: its trajectory count."""
         acc = np.empty(n_traj, dtype=np.int32)
         rej = np.empty(n_traj, dtype=np.int32)
         st = np.empty(n_traj, dtype=np.int32)
         ip = ctypes.POINTER(ctypes.c_int)
-        self._check(self._lib.nh_last_trajectory_stats(self.h, acc.ctypes.data_as(ip),
+        self._check(self._lib.nh_last_trajectory_stats(self.h, n_traj, acc.ctypes.data_as(ip),
                                                        rej.ctypes.data_as(ip), st.ctypes.data_as(ip)))
         return acc, rej, st
 
