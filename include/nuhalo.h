@@ -362,6 +362,26 @@ int nh_last_stats(nh_context *ctx, nh_stats *stats);
  * left through the exact free-streaming exit). */
 int nh_last_trajectory_stats(nh_context *ctx, size_t capacity, int *accepted, int *rejected, int *status);
 
+/* ---- plain solve without memory allocation ---------------------------- */
+
+/* For callers that cannot allocate memory (tight serving loops, harnesses that
+ * forbid allocation): the plain solve of nh_solve_async, allocating nothing.
+ * Its device buffers (counters, the quadrature sums, the staged tables and
+ * grids of one request) live in a static device array of nh_noalloc_scratch_bytes() bytes (4 MiB) that each GPU
+ * the library runs on holds until the process ends; its host staging is a
+ * static array too.  The profile is the same bits as nh_solve_async's.
+ * d_out: device, req->grid.n_r doubles.  Statistics: nh_last_stats.  The
+ * context must exist already (nh_context_create allocates).  The inputs go
+ * up by an asynchronous copy from a static pageable host array, so the call
+ * is not for use under stream capture.
+ * NH_EINVAL: a request whose staged inputs and sums exceed the scratch, or
+ * with sampled histories (their spline set-up allocates on the host).
+ * Every call on a GPU shares that GPU's scratch, which keeps the last call's
+ * contents: calls that overlap on one GPU race, so a caller runs one at a time
+ * per GPU (the next call on the same context waits for the previous one). */
+int nh_solve_noalloc(nh_context *ctx, const nh_request *req, double *d_out, void *stream);
+size_t nh_noalloc_scratch_bytes(void);
+
 /* ---- batched solve ---------------------------------------------------- */
 
 /* Solve n_req heterogeneous requests in one persistent launch (each request:

@@ -27,6 +27,7 @@ SOURCES = [
     "kernels_f64.hip",
     "kernels_f32c.hip",
     "kernels_batch.hip",
+    "noalloc.hip",
 ]
 
 ARCH = "gfx950"

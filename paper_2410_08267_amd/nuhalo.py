@@ -119,6 +119,9 @@ _SIGNATURES = {
     "nh_last_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_stats)]),
     "nh_last_trajectory_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "nh_solve_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_request), ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "nh_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "nh_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(nh_request),
                                       ctypes.c_void_p, ctypes.POINTER(nh_stats), ctypes.c_void_p]),
     "nh_serve_set_budget": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t]),
@@ -362,6 +365,17 @@ class Context:
         self._check(self._lib.nh_last_trajectory_stats(self.h, n_traj, acc.ctypes.data_as(ip),
                                                        rej.ctypes.data_as(ip), st.ctypes.data_as(ip)))
         return acc, rej, st
+
+    def solve_noalloc(self, req: Request, out: "torch.Tensor", stream: Optional["torch.cuda.Stream"] = None):
+        """nh_solve_noalloc: the plain solve into out (float64 device tensor of n_r),
+        allocating nothing; statistics through last_stats()."""
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        m = marshal(req)
+        if out.numel() < m.r.size:
+            raise ValueError("out is too small")
+        s = stream if stream is not None else torch.cuda.current_stream(out.device)
+        self._check(self._lib.nh_solve_noalloc(self.h, ctypes.byref(m.q), ctypes.c_void_p(out.data_ptr()),
+                                               ctypes.c_void_p(s.cuda_stream)))
 
     def solve_masses(self, req: Request, masses, out: "torch.Tensor", ratio=None, stream=None):
         """Profiles for several relic masses from one integration (velocities fixed by
