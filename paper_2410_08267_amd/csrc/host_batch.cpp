@@ -62,6 +62,7 @@ void describe(const nh_context *ctx, const nh_request *q, const Staged &s, char 
         d.P.r_exit = -1.0;
         d.P.cull_D = 0.0;
     }
+    d.P.r_exit2 = exit_radius2(d.P);
     d.P.order = ctx->queue_order;
     d.P.h_fp64 = q->integ.precision == NH_FP32C ? ctx->h_fp64 : 0.0;
     d.P.rtol32 = ctx->rtol32;

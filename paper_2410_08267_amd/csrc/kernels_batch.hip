@@ -185,7 +185,7 @@ __device__ __forceinline__ void setup64(const BatchReq &q, const double *slot, L
     p.ctl.rtol = P.rtol;
     p.ctl.atol_x = P.atol_x;
     p.ctl.atol_v = P.atol_v;
-    p.ctl.r_exit2 = P.r_exit > 0.0 ? P.r_exit * P.r_exit : -1.0;
+    p.ctl.r_exit2 = P.r_exit2;
     p.ctl.max_steps = (int)P.max_steps;
 }
 

@@ -127,8 +127,10 @@ static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const T
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
+    TrajParams Pk = P;
+    Pk.r_exit2 = exit_radius2(P);
     auto *kern = k_dp5_f32c<NC, CULL, HIST, FUSED>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter, q);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, Pk, g, o, counter, q);
     return hipGetLastError();
 }
 

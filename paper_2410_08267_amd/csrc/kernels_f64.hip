@@ -184,7 +184,7 @@ __global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridP
     ctl.rtol = P.rtol;
     ctl.atol_x = P.atol_x;
     ctl.atol_v = P.atol_v;
-    ctl.r_exit2 = P.r_exit > 0.0 ? P.r_exit * P.r_exit : -1.0;
+    ctl.r_exit2 = P.r_exit2;
     ctl.max_steps = (int)P.max_steps;
 
     long long t = -1;          // -1: wants work, -2: queue drained, >= 0: trajectory
@@ -439,8 +439,10 @@ static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const Tr
     const long long need = (P.n_traj + B - 1) / B;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
+    TrajParams Pk = P;
+    Pk.r_exit2 = exit_radius2(P);
     auto *kern = k_dp5_f64<NC, CULL, HIST, FUSED>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, P, g, o, counter, q);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, Pk, g, o, counter, q);
     return hipGetLastError();
 }
 

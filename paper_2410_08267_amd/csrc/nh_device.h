@@ -104,7 +104,7 @@ __device__ __forceinline__ void stencil_weights(double p, Stencil4 &w)
 {
     const double a = fma(p, p, -p);
     const double a6 = a * (1.0 / 6.0);
-    const double b2 = (a - 2.0) * 0.5;
+    const double b2 = fma(a, 0.5, -1.0);     // (a - 2)/2, the same rounding
     w.wa = a6 * (2.0 - p);
     w.wb = fma(b2, p, -b2);
     w.wc = -(b2 * p);
@@ -153,6 +153,14 @@ __device__ __forceinline__ Stencil4 table_stencil(int n_tab, double u0, double i
     else return stencil_at(n_tab, u0, inv_du, u);
 }
 
+// Row `row` of a table of rows of `stride` doubles.  The byte offset is a
+// 24-bit multiply (full rate; a 32-bit one is quarter rate): tables have far
+// fewer than 2^24 / (8 stride) rows.
+__device__ __forceinline__ const double *tab_row(const double *tab, int row, int stride)
+{
+    return (const double *)((const char *)tab + __umul24((unsigned)row, (unsigned)stride * 8u));
+}
+
 // Column k of the interpolated coefficients from rows of `stride` doubles.
 // The sum runs node by node as one FMA chain, so that the five-node form
 // below reproduces it bit for bit.
@@ -169,7 +177,7 @@ __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int 
                                             double inv_du, const Knots &kn, double u, double c[NCOL])
 {
     const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
-    const double *row = tab + w.row * STRIDE;
+    const double *row = tab_row(tab, w.row, STRIDE);
 #pragma unroll
     for (int k = 0; k < NC; ++k) c[k] = stencil_col(w, row, STRIDE, k);
 }
@@ -188,8 +196,8 @@ __device__ __forceinline__ void coef_interp2(const double *__restrict__ tab, int
 {
     const Stencil4 wQ = table_stencil<HIST>(n_tab, u0, inv_du, kn, uQ);
     const Stencil4 wP = table_stencil<HIST>(n_tab, u0, inv_du, kn, uP);
-    const double *row = tab + wQ.row * STRIDE;
-    const double *row4 = tab + min(wQ.row + 4, n_tab - 1) * STRIDE;
+    const double *row = tab_row(tab, wQ.row, STRIDE);
+    const double *row4 = tab_row(tab, min(wQ.row + 4, n_tab - 1), STRIDE);
     const int d = wP.row - wQ.row;
     const bool s = d == 1;
     const double v0 = s ? 0.0 : wP.wa, v1 = s ? wP.wa : wP.wb, v2 = s ? wP.wb : wP.wc;
@@ -201,7 +209,7 @@ __device__ __forceinline__ void coef_interp2(const double *__restrict__ tab, int
         cP[k] = fma(v4, row4[k], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
     }
     if ((unsigned)d > 1u) {
-        const double *rp = tab + wP.row * STRIDE;
+        const double *rp = tab_row(tab, wP.row, STRIDE);
 #pragma unroll
         for (int k = 0; k < NC; ++k) cP[k] = stencil_col(wP, rp, STRIDE, k);
     }
@@ -364,18 +372,21 @@ __device__ __forceinline__ long long wave_claim(bool need, unsigned long long *c
 // from the FP32 hardware log2/exp2 (relative error ~1e-6) and takes two Newton
 // steps y <- y + y (1 - err2 y^10) / 10 (each squares the error, times 5.5).
 // Outside [1e-8, 1e7] the clamps decide: 0.9 y > 5.6 below, < 0.18 above.
+// Branch-free (the iteration runs on err2 clamped to that range and selects
+// pick the clamps' values), so that the lanes of a wavefront that accept and
+// those that reject share one instruction stream.  err2 must be finite.
 __device__ __forceinline__ double step_factor(double err2, double fcap)
 {
-    if (err2 < 1.0e-8) return fcap;
-    if (err2 > 1.0e7) return 0.2;
-    const float l2 = __builtin_amdgcn_logf((float)err2);
+    const double e = fmin(fmax(err2, 1.0e-8), 1.0e7);
+    const float l2 = __builtin_amdgcn_logf((float)e);
     double y = (double)__builtin_amdgcn_exp2f(-0.1f * l2);
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
         const double y2 = y * y, y4 = y2 * y2, y10 = y4 * y4 * y2;
-        y = fma(0.1 * y, fma(-err2, y10, 1.0), y);
+        y = fma(0.1 * y, fma(-e, y10, 1.0), y);
     }
-    return fmin(fcap, fmax(0.2, 0.9 * y));
+    const double f = fmin(fcap, fmax(0.2, 0.9 * y));
+    return err2 < 1.0e-8 ? fcap : (err2 > 1.0e7 ? 0.2 : f);
 }
 
 }  // namespace nh

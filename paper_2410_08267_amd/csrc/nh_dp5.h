@@ -71,7 +71,7 @@ struct TabCoef {
 struct DpCtl {
     double u_end;      // integration ends here (below the start)
     double rtol, atol_x, atol_v;
-    double r_exit2;    // squared free-streaming exit radius; < 0 disables
+    double r_exit2;    // squared free-streaming exit radius; +inf disables
     int max_steps;
 };
 
@@ -211,7 +211,11 @@ __device__ __forceinline__ int dp5_attempt(Lane64 &L, const CF &cf, const DpCtl 
     const double qx = ex * isx, qy = ey * isx, qu = eu * isv, qv = ev * isv;
     const double err2 = 0.25 * (qx * qx + qy * qy + qu * qu + qv * qv);   // err^2
     if (!(err2 <= 1.0e300)) return ST_NONFINITE;
-    if (err2 <= 1.0) {
+    const bool accept = err2 <= 1.0;
+    // the next trial step's factor, growth capped at 1 right after a rejection
+    // (one evaluation for both outcomes: a wavefront holds lanes of each)
+    const double fac = step_factor(err2, (accept && L.rej_prev) ? 1.0 : 5.0);
+    if (accept) {
         ++L.nacc;
         L.u = last ? ctl.u_end : u + h;
         L.x = x5;
@@ -223,13 +227,12 @@ __device__ __forceinline__ int dp5_attempt(Lane64 &L, const CF &cf, const DpCtl 
         L.k1u = k7u;
         L.k1v = k7v;
         if (last) return ST_OK;
-        if (ctl.r_exit2 >= 0.0 && x5 * x5 + y5 * y5 >= ctl.r_exit2 && x5 * vx5 + y5 * vy5 <= 0.0)
-            return ST_OK | ST_FREE_EXIT;
-        L.h = h * step_factor(err2, L.rej_prev ? 1.0 : 5.0);
+        if (x5 * x5 + y5 * y5 >= ctl.r_exit2 && x5 * vx5 + y5 * vy5 <= 0.0) return ST_OK | ST_FREE_EXIT;
+        L.h = h * fac;
         L.rej_prev = false;
     } else {
         ++L.nrej;
-        L.h = h * step_factor(err2, 5.0);
+        L.h = h * fac;
         L.rej_prev = true;
     }
     if (fabs(L.h) <= 8.881784197001252e-16 * fmax(1.0, fabs(L.u))) return ST_UNDERFLOW;

@@ -321,7 +321,7 @@ __device__ __forceinline__ void f32c_controls(const TrajParams &P, DpCtl32 &ctl,
     ctl64.rtol = rtol32;
     ctl64.atol_x = fmax(P.atol_x, rtol32);
     ctl64.atol_v = fmax(P.atol_v, rtol32);
-    ctl64.r_exit2 = P.r_exit > 0.0 ? P.r_exit * P.r_exit : -1.0;
+    ctl64.r_exit2 = P.r_exit2;
     ctl64.max_steps = (int)P.max_steps;
 }
 

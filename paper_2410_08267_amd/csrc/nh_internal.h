@@ -84,6 +84,8 @@ struct TrajParams {
     long long max_steps;
     // exact free-streaming exit: beyond r_exit moving outward the force is zero forever
     double r_exit;          // <= 0 disables (and disables the cull below)
+    double r_exit2;         // r_exit^2, +inf when disabled: set on the host (exit_radius2) so that
+                            // the Dormand-Prince kernels hold it as a uniform scalar
     double cull_D;          // int_{u_end}^{u_start} A du: the straight backward path is x0 - v0 s, s <= cull_D;
                             // 0 where no start radius reaches R_exit (no relic can be culled)
     double R_const;         // > 0: the compensation radius is this constant (no R column)
@@ -101,6 +103,13 @@ struct TrajParams {
     Knots kn;
     int hist;
 };
+
+// The squared free-streaming exit radius the Dormand-Prince kernels test
+// against: +inf when the exit is off, so that the test needs no guard.
+inline double exit_radius2(const TrajParams &P)
+{
+    return P.r_exit > 0.0 ? P.r_exit * P.r_exit : __builtin_inf();
+}
 
 // The relic's initial distribution as the reduction evaluates it.
 struct F0Desc {
