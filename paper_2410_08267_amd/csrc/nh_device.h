@@ -118,11 +118,23 @@ __device__ __forceinline__ int stencil_interval(int n, double s)
     return i < 1 ? 1 : (i > n - 3 ? n - 3 : i);
 }
 
+// The same for the coefficient tables, as one three-operand integer median
+// (for a bound that is not a constant the compiler emits a compare and a
+// select or a min and a max).  The bound is a scalar register where n is
+// wave-uniform and a vector register otherwise; either form of the
+// instruction computes the lane's own clamp.
+__device__ __forceinline__ int table_interval(int n, double s)
+{
+    int i;
+    asm("v_med3_i32 %0, %1, 1, %2" : "=v"(i) : "v"((int)s), "s"(n - 3));
+    return i;
+}
+
 // Stencil of the coefficient table (nodes u_i = u0 + i du) at u.
 __device__ __forceinline__ Stencil4 stencil_at(int n_tab, double u0, double inv_du, double u)
 {
     const double s = fma(u, inv_du, -(u0 * inv_du));
-    const int i = stencil_interval(n_tab, s);
+    const int i = table_interval(n_tab, s);
     Stencil4 w;
     w.row = i - 1;
     stencil_weights(s - (double)i, w);
@@ -234,17 +246,25 @@ __device__ __noinline__ double pow_factor(const PowFactor &f, double u)
 
 // dY/du for Y = (x, y, vx, vy): dx/du = A v, dv/du = -g x with
 // g = K I(min(r/s, c)) / r^3 - Kc inside R and 0 outside (and at r = 0).
+//
+// Kc = K I(c) / R^3, and the NFW truncation radius c s never exceeds R on the
+// integration interval (validation keeps the paper geometry at z <= z_i; the
+// Delta-200 one has c s = R / 200^(1/3)).  Inside R the bracket is therefore
+// >= 0: the NFW fraction of the mass within r, I(q)/I(c), is at least the
+// uniform sphere's (r/R)^3.  At and beyond R it is <= 0, since I(q) <= I(c)
+// and r^3 >= R^3, where the enclosed perturbation is zero.  max(g, 0) thus
+// gives both cases without a compare (R is not needed).  At r = 0 the
+// reciprocal square root makes g NaN, and max(NaN, 0) = 0: no force there.
 __device__ __forceinline__ void rhs(const double c[NCOL], double R, double x, double y, double vx,
                                     double vy, double &dx, double &dy, double &dvx, double &dvy)
 {
+    (void)R;
     const double r2 = x * x + y * y;
     const double ri = rsq64(r2);
     const double r = r2 * ri;
     const double q = fmin(r * c[COL_INVS], c[COL_C]);
     const double I = nfw_I(q);
-    double g = fma(c[COL_K] * I, ri * ri * ri, -c[COL_KC]);
-    // r2 = 0 makes ri and r NaN, so r < R alone also zeroes the force there
-    g = (r < R) ? g : 0.0;
+    const double g = fmax(fma(c[COL_K] * I, ri * ri * ri, -c[COL_KC]), 0.0);
     dx = c[COL_A] * vx;
     dy = c[COL_A] * vy;
     dvx = -g * x;

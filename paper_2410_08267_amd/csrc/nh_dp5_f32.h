@@ -55,8 +55,9 @@ __device__ __forceinline__ void rhs32(const float c[NCOL], float R, float x, flo
     const float r = r2 * ri;
     const float q = fminf(r * c[COL_INVS], c[COL_C]);
     const float I = nfw_I32(q);
-    float g = fmaf(c[COL_K] * I, ri * ri * ri, -c[COL_KC]);
-    g = (r2 > 0.0f && r < R) ? g : 0.0f;
+    // max(., 0) as in rhs(): the bracket is >= 0 inside R and <= 0 beyond it
+    (void)R;
+    const float g = fmaxf(fmaf(c[COL_K] * I, ri * ri * ri, -c[COL_KC]), 0.0f);
     dx = c[COL_A] * vx;
     dy = c[COL_A] * vy;
     dvx = -g * x;
@@ -89,7 +90,7 @@ struct TabCoef32 {
     {
         constexpr int N32 = NC - F32C_T64;
         const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
-        const double *r64 = t64 + w.row * F32C_T64;
+        const double *r64 = tab_row(t64, w.row, F32C_T64);
         const double A = stencil_col(w, r64, F32C_T64, 0);
         double K = stencil_col(w, r64, F32C_T64, 1), Kc = stencil_col(w, r64, F32C_T64, 2);
         if constexpr (HIST) {
@@ -101,7 +102,7 @@ struct TabCoef32 {
         c[COL_K] = (float)K;
         c[COL_KC] = (float)Kc;
         const float wa = (float)w.wa, wb = (float)w.wb, wc = (float)w.wc, wd = (float)w.wd;
-        const float *r32 = t32 + w.row * N32;
+        const float *r32 = t32 + __umul24((unsigned)w.row, (unsigned)N32);
 #pragma unroll
         for (int k = 0; k < N32; ++k)
             c[F32C_T64 + k] = fmaf(wd, r32[3 * N32 + k], fmaf(wc, r32[2 * N32 + k], fmaf(wb, r32[N32 + k], wa * r32[k])));
