@@ -78,6 +78,9 @@ Staged stage_layout(const nh_request *q, int table_nodes, int n_mass)
                   : (table_nodes > 0 ? table_nodes : default_table_nodes(q->integ.precision == NH_FP32C));
     size_t off = 0;
     s.off_tab = off;  off = align_up(off + (size_t)s.n_tab * NCOL * sizeof(double));
+    // Dormand-Prince: the drift column A once more, node by node (the plain
+    // FP64 kernel reads it from here and the other columns from LDS)
+    s.off_tabA = off; off = align_up(off + (rk4 ? 0 : (size_t)s.n_tab * sizeof(double)));
     s.off_r = off;    off = align_up(off + (size_t)q->grid.n_r * sizeof(double));
     s.off_y = off;    off = align_up(off + (size_t)q->grid.n_y * sizeof(double));
     s.off_wy = off;   off = align_up(off + (size_t)q->grid.n_y * sizeof(double));
@@ -119,6 +122,8 @@ void stage_fill(const nh_request *q, const Staged &s, char *base, TrajParams &P,
     } else {
         const TableGrid tg = table_grid(ph, u_end, s.n_tab);
         build_interp_table(ph, tg, tab, table_threads);
+        double *tabA = (double *)(base + s.off_tabA);
+        for (int i = 0; i < tg.n; ++i) tabA[i] = tab[(size_t)i * NCOL + COL_A];
         P.n_tab = tg.n;
         P.tab_u0 = tg.u0;
         P.tab_inv_du = ph.sampled() ? 1.0 / tg.du : (double)(tg.n - 1) / (u_start - u_end);
@@ -183,6 +188,7 @@ GridPtrs grid_ptrs(const Staged &s, const char *dev)
 {
     GridPtrs g;
     g.tab = (const double *)(dev + s.off_tab);
+    g.tabA = (const double *)(dev + s.off_tabA);
     g.r = (const double *)(dev + s.off_r);
     g.y = (const double *)(dev + s.off_y);
     g.wy = (const double *)(dev + s.off_wy);

@@ -146,8 +146,7 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
 // 768 (three waves per SIMD) is the default: a single profile has ~1e6
 // trajectories, and more lanes per profile lengthen the tail where the last
 // long trajectories run alone.  The autotuner picks per workload.
-template <int NC>
-constexpr int dp5_block() { return 1024; }
+constexpr int DP5_MAX_BLOCK = 1024;
 constexpr int DP5_DEFAULT_BLOCK = 768;
 
 // CULL: some start radius lies beyond R_exit.  Without one no relic can be
@@ -155,27 +154,29 @@ constexpr int DP5_DEFAULT_BLOCK = 768;
 // trajectory loop a few percent in register moves.
 // FUSED: each finished trajectory adds its quadrature term and statistics
 // directly (QuadAcc); nothing is written per trajectory.
-template <int NC, bool CULL, bool HIST, bool FUSED>
-__global__ __launch_bounds__(dp5_block<NC>()) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
-                                                             unsigned long long *counter, QuadAcc qa)
+// The table: K, Kc, 1/s and c in LDS (TabCoefSplit), the drift column A from
+// g.tabA; R, constant or not, is not needed by the right-hand side.
+template <bool CULL, bool HIST, bool FUSED>
+__global__ __launch_bounds__(DP5_MAX_BLOCK) void k_dp5_f64(TrajParams P, GridPtrs g, TrajOut o,
+                                                           unsigned long long *counter, QuadAcc qa)
 {
     extern __shared__ double lds_tab[];
     __shared__ BlockStats bst;
     // the workgroup's partial sums follow the table
     unsigned long long *const lacc =
-        (unsigned long long *)((char *)lds_tab + quad_lds_offset((size_t)P.n_tab * NC * sizeof(double)));
+        (unsigned long long *)((char *)lds_tab + quad_lds_offset((size_t)P.n_tab * SPLIT_ROW * sizeof(double)));
     if constexpr (FUSED) {
         block_stats_init(bst);
         quad_lds_init(lacc, qa.lds_n);
     }
-    // stage the first NC columns of every node, rows of NC doubles
-    for (int i = threadIdx.x; i < P.n_tab * NC; i += blockDim.x) {
-        const int node = i / NC, col = i - node * NC;
-        lds_tab[i] = g.tab[node * NCOL + col];
+    // stage K, Kc, 1/s and c of every node into rows of SPLIT_ROW doubles
+    for (int i = threadIdx.x; i < P.n_tab * 4; i += blockDim.x) {
+        const int node = i >> 2, col = i & 3;
+        lds_tab[node * SPLIT_ROW + col] = g.tab[node * NCOL + COL_K + col];
     }
     __syncthreads();
 
-    const TabCoef<NC, NC, HIST> cf{lds_tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
+    const TabCoefSplit<HIST> cf{lds_tab, g.tabA, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     __shared__ StartCache sc;
     start_cache_fill(sc, cf, P.h0, P.u_start, P.u_end);
     __syncthreads();
@@ -419,19 +420,19 @@ hipError_t quad_lds_plan(const void *fn, int block, int per_cu, int n_r, size_t 
     return hipSuccess;
 }
 
-template <int NC, bool CULL, bool HIST, bool FUSED>
-static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                                unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
+template <bool CULL, bool HIST, bool FUSED>
+static hipError_t launch_dp5_k(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                               unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
 {
     const int B = P.block > 0 ? P.block : DP5_DEFAULT_BLOCK;
-    size_t lds = (size_t)P.n_tab * NC * sizeof(double);
+    size_t lds = (size_t)P.n_tab * SPLIT_ROW * sizeof(double);
     int per_cu = 0;
-    hipError_t e = occupancy_cached((const void *)k_dp5_f64<NC, CULL, HIST, FUSED>, B, lds, &per_cu);
+    hipError_t e = occupancy_cached((const void *)k_dp5_f64<CULL, HIST, FUSED>, B, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     QuadAcc q = qa;
     if (FUSED) {
-        e = quad_lds_plan((const void *)k_dp5_f64<NC, CULL, HIST, FUSED>, B, per_cu, P.n_r, lds, q);
+        e = quad_lds_plan((const void *)k_dp5_f64<CULL, HIST, FUSED>, B, per_cu, P.n_r, lds, q);
         if (e != hipSuccess) return e;
     }
     long long grid = (long long)n_cu * per_cu;
@@ -441,7 +442,7 @@ static hipError_t launch_dp5_nc(const TrajParams &P, const GridPtrs &g, const Tr
     if (grid < 1) grid = 1;
     TrajParams Pk = P;
     Pk.r_exit2 = exit_radius2(P);
-    auto *kern = k_dp5_f64<NC, CULL, HIST, FUSED>;
+    auto *kern = k_dp5_f64<CULL, HIST, FUSED>;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, Pk, g, o, counter, q);
     return hipGetLastError();
 }
@@ -450,12 +451,8 @@ template <bool HIST, bool FUSED>
 static hipError_t launch_dp5_hist(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
                                   unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
 {
-    const bool cull = P.cull_D > 0.0;
-    if (P.R_const > 0.0)
-        return cull ? launch_dp5_nc<NCOL - 1, true, HIST, FUSED>(P, g, o, counter, qa, n_cu, s)
-                    : launch_dp5_nc<NCOL - 1, false, HIST, FUSED>(P, g, o, counter, qa, n_cu, s);
-    return cull ? launch_dp5_nc<NCOL, true, HIST, FUSED>(P, g, o, counter, qa, n_cu, s)
-                : launch_dp5_nc<NCOL, false, HIST, FUSED>(P, g, o, counter, qa, n_cu, s);
+    return P.cull_D > 0.0 ? launch_dp5_k<true, HIST, FUSED>(P, g, o, counter, qa, n_cu, s)
+                          : launch_dp5_k<false, HIST, FUSED>(P, g, o, counter, qa, n_cu, s);
 }
 
 hipError_t launch_dp5_f64(const TrajParams &P, const GridPtrs &g, const TrajOut &o,

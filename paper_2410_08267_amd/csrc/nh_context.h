@@ -18,7 +18,7 @@ struct DevBuf {
 // Byte offsets of one request's inputs inside the staged blob.
 struct Staged {
     int n_tab;
-    size_t off_tab, off_r, off_y, off_wy, off_mu, off_smu, off_wmu, off_f0;
+    size_t off_tab, off_tabA, off_r, off_y, off_wy, off_mu, off_smu, off_wmu, off_f0;
     int n_mass;             // multi-mass solve: scaled y grids and weights per mass
     size_t off_ym, off_wm;
     int f0_kind, f0_n;

@@ -227,6 +227,62 @@ __device__ __forceinline__ void coef_interp2(const double *__restrict__ tab, int
     }
 }
 
+// The same from a split table: the drift column A from `a`, one value per node
+// (device memory, read through the vector cache), the other four columns
+// (K, Kc, 1/s, c) from LDS rows of `stride` doubles.  The values equal those
+// of coef_interp / coef_interp2 on the whole table bit for bit: each column
+// is the same FMA chain over the same four (or five) node values.
+__device__ __forceinline__ double stencil_a(const Stencil4 &w, const double *a)
+{
+    return fma(w.wd, a[3], fma(w.wc, a[2], fma(w.wb, a[1], w.wa * a[0])));
+}
+
+template <int STRIDE, bool HIST = false>
+__device__ __forceinline__ void coef_interp_split(const double *__restrict__ lds, const double *__restrict__ a,
+                                                  int n_tab, double u0, double inv_du, const Knots &kn, double u,
+                                                  double c[NCOL])
+{
+    const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
+    c[COL_A] = stencil_a(w, a + (unsigned)w.row);
+    const double *row = tab_row(lds, w.row, STRIDE);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[COL_K + k] = stencil_col(w, row, STRIDE, k);
+}
+
+template <int STRIDE, bool HIST = false>
+__device__ __forceinline__ void coef_interp2_split(const double *__restrict__ lds, const double *__restrict__ a,
+                                                   int n_tab, double u0, double inv_du, const Knots &kn, double uP,
+                                                   double uQ, double cP[NCOL], double cQ[NCOL])
+{
+    const Stencil4 wQ = table_stencil<HIST>(n_tab, u0, inv_du, kn, uQ);
+    const Stencil4 wP = table_stencil<HIST>(n_tab, u0, inv_du, kn, uP);
+    const int row4i = min(wQ.row + 4, n_tab - 1);
+    const double *row = tab_row(lds, wQ.row, STRIDE);
+    const double *row4 = tab_row(lds, row4i, STRIDE);
+    const double *aq = a + (unsigned)wQ.row;
+    const int d = wP.row - wQ.row;
+    const bool s = d == 1;
+    const double v0 = s ? 0.0 : wP.wa, v1 = s ? wP.wa : wP.wb, v2 = s ? wP.wb : wP.wc;
+    const double v3 = s ? wP.wc : wP.wd, v4 = s ? wP.wd : 0.0;
+    {
+        const double r0 = aq[0], r1 = aq[1], r2 = aq[2], r3 = aq[3];
+        cQ[COL_A] = fma(wQ.wd, r3, fma(wQ.wc, r2, fma(wQ.wb, r1, wQ.wa * r0)));
+        cP[COL_A] = fma(v4, a[(unsigned)row4i], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double r0 = row[k], r1 = row[STRIDE + k], r2 = row[2 * STRIDE + k], r3 = row[3 * STRIDE + k];
+        cQ[COL_K + k] = fma(wQ.wd, r3, fma(wQ.wc, r2, fma(wQ.wb, r1, wQ.wa * r0)));
+        cP[COL_K + k] = fma(v4, row4[k], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
+    }
+    if ((unsigned)d > 1u) {
+        cP[COL_A] = stencil_a(wP, a + (unsigned)wP.row);
+        const double *rp = tab_row(lds, wP.row, STRIDE);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cP[COL_K + k] = stencil_col(wP, rp, STRIDE, k);
+    }
+}
+
 // The power-law factor of K and Kc at u (PowFactor): xi^alpha of the paper's
 // growth model and kappa = 1 + a [z/(1+z)]^b, from the library's FP64 exp,
 // expm1 and log (a few ulp); 0^alpha = 0 (alpha > 0 wherever it applies).

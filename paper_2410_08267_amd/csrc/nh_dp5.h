@@ -68,6 +68,50 @@ struct TabCoef {
     }
 };
 
+// The plain FP64 kernel's coefficient source: the drift column A from its
+// node-by-node copy in device memory (GridPtrs::tabA, read through the vector
+// cache) and K, Kc, 1/s and c from LDS rows of SPLIT_ROW doubles.  The LDS is
+// the kernel's busiest unit beside the FP64 VALU (random table rows: most of
+// its cycles are bank conflicts); taking a fifth of the table reads off it
+// pays for the extra vector-memory loads.  A row stride of five doubles (ten
+// banks; one unused) spreads random rows over the banks as the five-column
+// rows did.  Values equal TabCoef's bit for bit; R (no longer read by the
+// right-hand side) is the request's constant.
+constexpr int SPLIT_ROW = 5;
+template <bool HIST = false>
+struct TabCoefSplit {
+    const double *lds;     // n_tab rows of K, Kc, 1/s, c (and one unused double)
+    const double *a;       // n_tab values of A
+    int n_tab;
+    double u0, inv_du, R_const;
+    PowFactor pw;
+    Knots kn;
+    __device__ __forceinline__ void at(double u, double c[NCOL], double &R) const
+    {
+        coef_interp_split<SPLIT_ROW, HIST>(lds, a, n_tab, u0, inv_du, kn, u, c);
+        R = R_const;
+        if constexpr (HIST) {
+            const double f = pow_factor(pw, u);
+            c[COL_K] *= f;
+            c[COL_KC] *= f;
+        }
+    }
+    static constexpr bool paired = true;
+    __device__ __forceinline__ void at2(double uP, double uQ, double cP[NCOL], double &RP, double cQ[NCOL],
+                                        double &RQ) const
+    {
+        coef_interp2_split<SPLIT_ROW, HIST>(lds, a, n_tab, u0, inv_du, kn, uP, uQ, cP, cQ);
+        RP = RQ = R_const;
+        if constexpr (HIST) {
+            const double fP = pow_factor(pw, uP), fQ = pow_factor(pw, uQ);
+            cP[COL_K] *= fP;
+            cP[COL_KC] *= fP;
+            cQ[COL_K] *= fQ;
+            cQ[COL_KC] *= fQ;
+        }
+    }
+};
+
 struct DpCtl {
     double u_end;      // integration ends here (below the start)
     double rtol, atol_x, atol_v;
@@ -189,25 +233,38 @@ __device__ __forceinline__ int dp5_attempt(Lane64 &L, const CF &cf, const DpCtl 
         vx + h * (a51 * k1u + a52 * k2u + a53 * k3u + a54 * k4u),
         vy + h * (a51 * k1v + a52 * k2v + a53 * k3v + a54 * k4v), k5x, k5y, k5u, k5v);
     cf.at(u + h, c, R);
-    rhs(c, R, x + h * (a61 * k1x + a62 * k2x + a63 * k3x + a64 * k4x + a65 * k5x),
-        y + h * (a61 * k1y + a62 * k2y + a63 * k3y + a64 * k4y + a65 * k5y),
-        vx + h * (a61 * k1u + a62 * k2u + a63 * k3u + a64 * k4u + a65 * k5u),
-        vy + h * (a61 * k1v + a62 * k2v + a63 * k3v + a64 * k4v + a65 * k5v), k6x, k6y, k6u, k6v);
-    const double x5 = x + h * (b1 * k1x + b3 * k3x + b4 * k4x + b5 * k5x + b6 * k6x);
-    const double y5 = y + h * (b1 * k1y + b3 * k3y + b4 * k4y + b5 * k5y + b6 * k6y);
-    const double vx5 = vx + h * (b1 * k1u + b3 * k3u + b4 * k4u + b5 * k5u + b6 * k6u);
-    const double vy5 = vy + h * (b1 * k1v + b3 * k3v + b4 * k4v + b5 * k5v + b6 * k6v);
+    const double x6 = x + h * (a61 * k1x + a62 * k2x + a63 * k3x + a64 * k4x + a65 * k5x);
+    const double y6 = y + h * (a61 * k1y + a62 * k2y + a63 * k3y + a64 * k4y + a65 * k5y);
+    const double vx6 = vx + h * (a61 * k1u + a62 * k2u + a63 * k3u + a64 * k4u + a65 * k5u);
+    const double vy6 = vy + h * (a61 * k1v + a62 * k2v + a63 * k3v + a64 * k4v + a65 * k5v);
+    // the solution and error sums over stages 1-5, formed here so that k2-k5
+    // are dead during the last two right-hand sides (the same operations in
+    // the same order as the whole sums: b1 k1 + b3 k3 + ... + b6 k6)
+    const double sx = b1 * k1x + b3 * k3x + b4 * k4x + b5 * k5x;
+    const double sy = b1 * k1y + b3 * k3y + b4 * k4y + b5 * k5y;
+    const double su = b1 * k1u + b3 * k3u + b4 * k4u + b5 * k5u;
+    const double sv = b1 * k1v + b3 * k3v + b4 * k4v + b5 * k5v;
+    const double tx = e1 * k1x + e3 * k3x + e4 * k4x + e5 * k5x;
+    const double ty = e1 * k1y + e3 * k3y + e4 * k4y + e5 * k5y;
+    const double tu = e1 * k1u + e3 * k3u + e4 * k4u + e5 * k5u;
+    const double tv = e1 * k1v + e3 * k3v + e4 * k4v + e5 * k5v;
+    rhs(c, R, x6, y6, vx6, vy6, k6x, k6y, k6u, k6v);
+    const double x5 = x + h * (sx + b6 * k6x);
+    const double y5 = y + h * (sy + b6 * k6y);
+    const double vx5 = vx + h * (su + b6 * k6u);
+    const double vy5 = vy + h * (sv + b6 * k6v);
+    const double wx = tx + e6 * k6x, wy = ty + e6 * k6y, wu = tu + e6 * k6u, wv = tv + e6 * k6v;
     rhs(c, R, x5, y5, vx5, vy5, k7x, k7y, k7u, k7v);   // c7 = c6 = 1: same coefficients
 
-    const double ex = h * (e1 * k1x + e3 * k3x + e4 * k4x + e5 * k5x + e6 * k6x + e7 * k7x);
-    const double ey = h * (e1 * k1y + e3 * k3y + e4 * k4y + e5 * k5y + e6 * k6y + e7 * k7y);
-    const double eu = h * (e1 * k1u + e3 * k3u + e4 * k4u + e5 * k5u + e6 * k6u + e7 * k7u);
-    const double ev = h * (e1 * k1v + e3 * k3v + e4 * k4v + e5 * k5v + e6 * k6v + e7 * k7v);
+    const double ex = h * (wx + e7 * k7x);
+    const double ey = h * (wy + e7 * k7y);
+    const double eu = h * (wu + e7 * k7u);
+    const double ev = h * (wv + e7 * k7v);
     // sc = atol + rtol max(|.|_n, |.|_{n+1}); max of the norms = sqrt of the max of the squares
-    const double sx = ctl.atol_x + ctl.rtol * sqrt_pos(fmax(x * x + y * y, x5 * x5 + y5 * y5));
-    const double sv = ctl.atol_v + ctl.rtol * sqrt_pos(fmax(vx * vx + vy * vy, vx5 * vx5 + vy5 * vy5));
-    const double rp = rcp64(sx * sv);                   // one reciprocal for both scales
-    const double isx = sv * rp, isv = sx * rp;
+    const double scx = ctl.atol_x + ctl.rtol * sqrt_pos(fmax(x * x + y * y, x5 * x5 + y5 * y5));
+    const double scv = ctl.atol_v + ctl.rtol * sqrt_pos(fmax(vx * vx + vy * vy, vx5 * vx5 + vy5 * vy5));
+    const double rp = rcp64(scx * scv);                 // one reciprocal for both scales
+    const double isx = scv * rp, isv = scx * rp;
     const double qx = ex * isx, qy = ey * isx, qu = eu * isv, qv = ev * isv;
     const double err2 = 0.25 * (qx * qx + qy * qy + qu * qu + qv * qv);   // err^2
     if (!(err2 <= 1.0e300)) return ST_NONFINITE;

@@ -122,6 +122,7 @@ struct F0Desc {
 // Device pointers of one request's staged inputs (one contiguous blob).
 struct GridPtrs {
     const double *tab;      // n_tab * NCOL (DP5) or (2 n_steps + 1) * NCOL (RK4)
+    const double *tabA;     // DP5: column COL_A of tab, n_tab values (the plain FP64 kernel's drift)
     const double *r;        // n_r
     const double *y;        // n_y
     const double *wy;       // n_y
