@@ -246,7 +246,7 @@ CU_SHARE = 1.0            # workgroups per launch: this many CUs' worth over the
 def overlapped(reqs, outs, block, warm_req):
     """Solve reqs[i] into outs[i] on PIPE_DEPTH contexts, each on its own stream
     and capped to its share of the CUs; a context takes the next profile as soon
-    as its previous one is done.
+    as its previous one is done, the profiles taken heaviest halo first.
 
     Returns the wall time, the summed statistics, each launch's own kernel time,
     the span of GPU work over the timed region from HIP events recorded on every
@@ -273,7 +273,11 @@ def overlapped(reqs, outs, block, warm_req):
     ev0.record(streams[0])
     for s in streams[1:]:
         s.wait_event(ev0)            # no stream starts before the start event
-    todo = list(zip(reqs, outs))
+    # longest expected first: halo mass is the dominant cost driver of a
+    # profile (rank correlation 0.91 between M0 and mean attempts per
+    # trajectory over the plain-at-scale seeds 0-19, from the oracle), so the
+    # heaviest halos start first and the run ends on the cheapest ones
+    todo = sorted(zip(reqs, outs), key=lambda ro: -ro[0].M0)
     free = list(range(PIPE_DEPTH))
     busy = {}
     while todo or busy:
