@@ -72,13 +72,14 @@ __device__ __forceinline__ double nfw_I(double q)
     po = fma(z2, po, 2.0 / 5.0);
     const double p = fma(s2, po, pe);
     const double t3 = s * s2 * p;                        // 2 (atanh(s) - s)
-    const bool small = (e == 0);
-    // e = 0: m = 1+q, so 2/(1+s) = (m+1)/m = 1 + 1/(1+q); otherwise 1/(1+q)
-    const double inv = small ? iw + 1.0 : iw;
+    // e = 0: m = 1+q, so 2 s^2/(1+s) = s^2 (m+1)/m = s^2 (1 + 1/(1+q))
+    const double sm = fma(s2, iw, s2);
+    // ln 2 as the Cody-Waite pair of fdlibm's log: a high part whose products
+    // with small integers are exact, and the remainder
     const double de = (double)e;
     const double big = fma(de, 6.93147180369123816490e-01,
-                           fma(de, 1.90821492927058770002e-10, fma(-q, inv, s + s)));
-    return (small ? s2 * inv : big) + t3;
+                           fma(de, 1.90821492927058770002e-10, fma(-q, iw, s + s)));
+    return ((e == 0) ? sm : big) + t3;
 }
 
 // |v|^2 with a fixed operation order (the final and initial speeds must round
