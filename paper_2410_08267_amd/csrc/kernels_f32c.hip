@@ -51,9 +51,10 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
     long long t = -1;
     double v0n = 1.0;
     Lane32 L{};
+    WaveQueue wq{0ull, 0ull};
     for (;;) {
         const bool need = (t == -1);
-        const long long p = wave_claim(need, counter);
+        const long long p = wave_claim(need, counter, wq);
         if (need) {
             if (p < P.n_traj) {
                 t = traj_of(p, P);

@@ -191,9 +191,10 @@ __global__ __launch_bounds__(DP5_MAX_BLOCK) void k_dp5_f64(TrajParams P, GridPtr
     long long t = -1;          // -1: wants work, -2: queue drained, >= 0: trajectory
     double v0n = 1.0;
     Lane64 L{};
+    WaveQueue wq{0ull, 0ull};
     for (;;) {
         const bool need = (t == -1);
-        const long long p = wave_claim(need, counter);
+        const long long p = wave_claim(need, counter, wq);
         if (need) {
             if (p < P.n_traj) {
                 t = traj_of(p, P);

@@ -428,19 +428,46 @@ __device__ __forceinline__ long long traj_of(long long p, const TrajParams &P)
     return traj_of_w<long long>(p, P);
 }
 
-// One atomic per wavefront hands consecutive queue positions to the lanes
-// that asked for work; returns this lane's position (meaningful if `need`).
-__device__ __forceinline__ long long wave_claim(bool need, unsigned long long *counter)
+// A wavefront's share of the work queue: positions [next, end) it has taken
+// from the global counter but not yet handed to its lanes.  A wavefront takes
+// QUEUE_BLOCK positions at a time, so the counter (a device-scope atomic,
+// performed at the memory side and waited for by the whole wavefront) is
+// touched once per QUEUE_BLOCK trajectories instead of once per pass in which
+// some lane finished.  Which lane runs which trajectory does not change any
+// result.  Positions past the end of the queue mean it is drained.
+constexpr unsigned QUEUE_BLOCK = 64;
+struct WaveQueue {
+    unsigned long long next, end;
+};
+
+// Hands the lanes that ask for work (`need`) the wavefront's next positions,
+// in lane order, taking a new block when the wavefront's share runs out;
+// returns this lane's position (meaningful if `need`).  Called by every lane
+// of the wavefront (the new block is taken by lane 0); q stays wave-uniform.
+__device__ __forceinline__ long long wave_claim(bool need, unsigned long long *counter, WaveQueue &q)
 {
     const unsigned long long mask = __ballot(need);
     if (mask == 0ull) return -1;
+    const unsigned n = (unsigned)__popcll(mask);
     const int lane = __lane_id();
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader);
-    const unsigned long long below = mask & ((1ull << lane) - 1ull);
-    return (long long)(base + (unsigned long long)__popcll(below));
+    const unsigned rank = (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+    const unsigned long long have = q.end - q.next;
+    long long pos;
+    if (have >= n) {
+        pos = (long long)(q.next + rank);
+        q.next += n;
+    } else {
+        // the rest of this share, then a fresh block (n <= 64 = QUEUE_BLOCK)
+        unsigned long long nb = 0;
+        if (lane == 0) nb = atomicAdd(counter, (unsigned long long)QUEUE_BLOCK);
+        const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)nb);
+        const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(nb >> 32));
+        nb = ((unsigned long long)hi << 32) | lo;
+        pos = (long long)(rank < have ? q.next + rank : nb + (rank - have));
+        q.next = nb + (n - have);
+        q.end = nb + QUEUE_BLOCK;
+    }
+    return pos;
 }
 
 // Step-size factor of the controller, min(fmax, max(0.2, 0.9 err^(-1/5))),
