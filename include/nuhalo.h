@@ -246,7 +246,10 @@ enum {
     NH_OPT_FREE_EXIT     = 2,  /* [1] stop a trajectory once it is beyond the compensation
                                   radius and receding (exact: the force is zero from then on);
                                   0 integrates every trajectory to z_end */
-    NH_OPT_FP64_BELOW_H  = 3,  /* NH_FP32C: attempted steps with |h| below this run in FP64 [1e-5] */
+    NH_OPT_FP64_BELOW_H  = 3,  /* NH_FP32C: attempted steps with |h| below this run in FP64 [1e-6].
+                                  A wavefront runs an FP64 attempt whenever one of its lanes
+                                  needs one; at 1e-5 that was a quarter of all passes on the
+                                  plain-at-scale halos (7 % of the time), for the same profiles */
     NH_OPT_TABLE_NODES   = 4,  /* Dormand-Prince coefficient table nodes, 64..3073, or 0 for the
                                   default [0]: 3073, or for the batched and serving forms as many
                                   as their LDS slots hold (a larger value is NH_EINVAL there) */

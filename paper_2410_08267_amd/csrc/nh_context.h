@@ -49,7 +49,7 @@ struct nh_context {
     // tunables (nh_set_option)
     int queue_order = nh::ORDER_NATURAL;
     bool free_exit = true;
-    double h_fp64 = 1.0e-5;                          // FP32C: |h| below this runs in FP64
+    double h_fp64 = 1.0e-6;                          // FP32C: |h| below this runs in FP64
     double rtol32 = 1.0e-7;                          // FP32C: tolerance floor of the FP32 attempts
     int table_nodes = 0;                             // 0: default_table_nodes()
     int block_threads = 0;                           // Dormand-Prince workgroup size (0: default)

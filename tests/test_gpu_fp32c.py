@@ -72,7 +72,7 @@ def test_fp32c_within_1e4_of_oracle(ctx, O, name, h_fp64):
     try:
         got, stats, _ = ctx.solve(req)
     finally:
-        ctx.set_option("fp64_below_h", 1e-5)
+        ctx.set_option("fp64_below_h", 1e-6)
     ref = O.solve(req.with_(precision="fp64", rtol=1e-10))["n_over_nbar"]
     e = np.abs(got / ref - 1)
     ed = np.abs((got - 1) - (ref - 1)) / np.maximum(np.abs(ref - 1), 1e-12)
