@@ -36,16 +36,19 @@ FLOP_PER_DP5_ATTEMPT = 6 * 84 + 5 * 55 + 184 + 182
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # HBM bytes per k_dp5_f64 launch on this workload (1024 threads, 64 workgroups),
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE (seeds 0 and 1), each scaled by what
-# the counter reads for a plain 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the sources and
-# build flags these hashes name; any change to them reports traffic as null.
-TRAFFIC_BYTES_PER_LAUNCH = 95092911
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE over the five 64-workgroup timed
+# launches of an 8-profile run, each scaled by what the counter reads for a
+# plain 256 MiB device copy (FETCH x 2.0, WRITE x 0.5).  Valid only for the
+# sources and build flags these hashes name; any change to them reports
+# traffic as null.
+TRAFFIC_BYTES_PER_LAUNCH = 2189126
 TRAFFIC_SOURCES = {
-    "kernels_f64.hip": "d065db7771698004f0767fd903a37d9fc2e31d2085710e1dba8aba635957f22f",
-    "nh_dp5.h": "c9a09aa826db44ed57190ecea29756224b6bed2220cca89efc3195073061ed3a",
-    "nh_device.h": "8116fd1511b47db24c57e787620b7a5ffcc31c7e63a968b5e300c21a28d8c5fa",
-    "nh_internal.h": "423e35d973ade1aed18f5b891a95f413abbb973fe70b762c40a6eb4438732d31",
-    "../build.py": "d3c1c397d53ea82ca441cf34bd1c9ffeb38cae9062c9fad6166ddba8eb10aa87",
+    "kernels_f64.hip": "e214d1ffa13fe116ab16acbe9eee6a3f1f5ddf236b14a8c85070702f8b68a01c",
+    "nh_dp5.h": "3b9db5a803dcdf58bfb719f7e0f4439627029cf78d7d79b76bba406ef7b847ef",
+    "nh_device.h": "a4114d94dcd9599b02d75d9ec0ce188c334a886c4ee4b03ac4964c2051aaba02",
+    "nh_internal.h": "7ae9c8a38332d355885dedcd99ead21490360a72aef49c868341dc134f74e86d",
+    "nh_reduce.h": "4a7614c397af55b2edd74db041836b4390af4c5f8f53aab960413dbe1eede52e",
+    "../build.py": "a2f74296fa1f0cf61f1cac1b26c9c8152bfd7190acc99c5f531c13443aadf33d",
 }
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
 
