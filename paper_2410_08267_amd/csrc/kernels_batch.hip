@@ -21,7 +21,7 @@ namespace nh {
 // histories keep each request's stencils inside its spline pieces (Knots) and
 // apply its power-law factor of K and Kc (PowFactor); for smooth requests both
 // leave the values unchanged bit for bit (one piece, factor exactly 1).
-template <int NC, int STRIDE = NC, bool HIST = false>
+template <int NC, int STRIDE = NC, bool HIST = false, bool PAIRED = false>
 struct TabCoefB {
     const double *tab;
     int nc, n_tab;
@@ -38,9 +38,18 @@ struct TabCoefB {
             c[COL_KC] *= f;
         }
     }
-    // four rows per stage: the shared window of stages 2 and 3 costs registers
-    // this kernel does not have (the values are the same either way)
-    static constexpr bool paired = false;
+    // PAIRED: stages 2 and 3 share one five-row window, as in the plain
+    // kernel (same values bit for bit); otherwise four rows per stage, where
+    // the window's registers are not available
+    static constexpr bool paired = PAIRED;
+    __device__ __forceinline__ void at2(double uP, double uQ, double cP[NCOL], double &RP, double cQ[NCOL],
+                                        double &RQ) const
+    {
+        static_assert(!HIST, "paired window only for smooth histories");
+        coef_interp2<NC, STRIDE, HIST>(tab, n_tab, u0, inv_du, kn, uP, uQ, cP, cQ);
+        RP = (NC == NCOL && nc == NCOL) ? cP[COL_R] : R_const;
+        RQ = (NC == NCOL && nc == NCOL) ? cQ[COL_R] : R_const;
+    }
 };
 
 // Copy request q's table into a slot: FP64 rows of NC doubles (NC of the
@@ -171,22 +180,47 @@ __device__ __forceinline__ void unpack32(const LaneSave &s, Lane32 &L, double &v
 }
 
 // Per-lane parameters of a trajectory of request q whose table sits in `slot`.
-template <int NC, bool HIST>
+template <int NC, bool HIST, bool PAIRED = false>
 struct Lane64Params {
-    TabCoefB<NC, NC, HIST> cf;
+    TabCoefB<NC, NC, HIST, PAIRED> cf;
     DpCtl ctl;
 };
-template <int NC, bool HIST>
-__device__ __forceinline__ void setup64(const BatchReq &q, const double *slot, Lane64Params<NC, HIST> &p)
+template <int NC, bool HIST, bool PAIRED>
+__device__ __forceinline__ void setup64(const BatchReq &q, const double *slot, Lane64Params<NC, HIST, PAIRED> &p)
 {
     const TrajParams &P = q.P;
-    p.cf = TabCoefB<NC, NC, HIST>{slot, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
+    p.cf = TabCoefB<NC, NC, HIST, PAIRED>{slot, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     p.ctl.u_end = P.u_end;
     p.ctl.rtol = P.rtol;
     p.ctl.atol_x = P.atol_x;
     p.ctl.atol_v = P.atol_v;
     p.ctl.r_exit2 = P.r_exit2;
     p.ctl.max_steps = (int)P.max_steps;
+}
+
+// The same from a wave-uniform request index, through the constant address
+// space: descriptors do not change while a kernel runs, so these are scalar
+// loads into scalar registers (through a generic pointer the compiler cannot
+// rule out the kernel's own stores and loads them per lane).  Smooth
+// histories only: the spline pieces and factors are not read.
+using ConstReq = const __attribute__((address_space(4))) BatchReq;
+template <int NC, bool PAIRED>
+__device__ __forceinline__ void setup64_uniform(const BatchReq *reqs, int ru, const double *slot,
+                                                Lane64Params<NC, false, PAIRED> &p)
+{
+    ConstReq *q = (ConstReq *)(reqs + ru);
+    p.cf.tab = slot;
+    p.cf.nc = q->nc;
+    p.cf.n_tab = q->P.n_tab;
+    p.cf.u0 = q->P.tab_u0;
+    p.cf.inv_du = q->P.tab_inv_du;
+    p.cf.R_const = q->P.R_const;
+    p.ctl.u_end = q->P.u_end;
+    p.ctl.rtol = q->P.rtol;
+    p.ctl.atol_x = q->P.atol_x;
+    p.ctl.atol_v = q->P.atol_v;
+    p.ctl.r_exit2 = q->P.r_exit2;
+    p.ctl.max_steps = (int)q->P.max_steps;
 }
 
 template <int NC, bool HIST>
@@ -231,13 +265,15 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
     double v0n = 1.0;
     Lane64 L{};
     Lane64Params<NC, HIST> lp{};
-    LaneSave *const my = A.lane_save ? A.lane_save + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) : nullptr;
-    if (A.resume && my) {
-        const LaneSave sv = *my;
+    // this lane's save record (recomputed where used rather than held in
+    // registers through the loop)
+    const auto my_save = [&]() { return A.lane_save + ((size_t)blockIdx.x * blockDim.x + threadIdx.x); };
+    if (A.resume && A.lane_save) {
+        const LaneSave sv = *my_save();
         if (sv.t >= 0 && !A.reqs[sv.req].retired) {
             t = sv.t;
             rq = sv.req;
-            sl = sv.slot;
+            sl = SLOTS == 1 ? 0 : sv.slot;
             unpack64(sv, L, v0n);
             setup64(A.reqs[rq], lds64 + sl * slot_n, lp);
             __hip_atomic_fetch_add(&S.active[sl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -257,24 +293,30 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
                 copy_table<NC>(lds64 + slot * slot_n, A.reqs[req], (int)__lane_id(), 64);
             });
             if (r >= 0) {
-                const BatchReq &q = A.reqs[r];
-                rq = r;
-                sl = s;
+                // the lanes that got a trajectory share one request and slot
+                const int ru = __builtin_amdgcn_readfirstlane(r);
+                const BatchReq &q = A.reqs[ru];
+                rq = ru;
+                sl = SLOTS == 1 ? 0 : s;
                 t = traj_of(p, q.P);
                 if (q.free_all) {
                     finish_free(q, t);
-                    slot_release(S, s);
+                    slot_release(S, sl);
                     t = -1;
                 } else {
-                    setup64(q, lds64 + s * slot_n, lp);
                     double x0, vx0, vy0;
                     initial_state(q, t, x0, vx0, vy0);
                     v0n = sqrt(norm2(vx0, vy0));
                     if (q.P.cull_D > 0.0 && never_enters(x0, vx0, vy0, q.P.cull_D, cull_radius2(q.P.r_exit))) {
                         finish_free(q, t);
-                        slot_release(S, s);
+                        slot_release(S, sl);
                         t = -1;
+                    } else if constexpr (SLOTS == 1 && !HIST) {
+                        Lane64Params<NC, HIST, true> up;
+                        setup64_uniform(A.reqs, ru, lds64, up);
+                        dp5_start(L, up.cf, x0, vx0, vy0, q.P.h0, q.P.u_start, q.P.u_end);
                     } else {
+                        setup64(q, lds64 + sl * slot_n, lp);
                         dp5_start(L, lp.cf, x0, vx0, vy0, q.P.h0, q.P.u_start, q.P.u_end);
                     }
                 }
@@ -287,7 +329,21 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
         }
         if (expired) break;
         if (t >= 0) {
-            const int st = dp5_attempt(L, lp.cf, lp.ctl);
+            int st;
+            if constexpr (SLOTS == 1 && !HIST) {
+                // With one slot a workgroup loads a new request only once no
+                // lane runs a trajectory of the old one, so every lane here
+                // serves the same request: its parameters are wave-uniform and
+                // come through scalar loads instead of lane registers, which
+                // leaves room for the shared window of stages 2 and 3.  (The
+                // spline pieces and factors of sampled histories would not fit
+                // the scalar registers.)
+                Lane64Params<NC, HIST, true> up;
+                setup64_uniform(A.reqs, __builtin_amdgcn_readfirstlane(rq), lds64, up);
+                st = dp5_attempt(L, up.cf, up.ctl);
+            } else {
+                st = dp5_attempt(L, lp.cf, lp.ctl);
+            }
             if (st >= 0) {
                 const TrajOut o = A.reqs[rq].o;
                 o.ratio[t] = sqrt(norm2(L.vx, L.vy)) / v0n;
@@ -297,7 +353,7 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
             }
         }
     }
-    if (my) {
+    if (A.lane_save) {
         LaneSave sv;
         sv.t = t;
         sv.req = rq;
@@ -306,7 +362,7 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
             pack64(L, v0n, sv);
             atomicAdd(&A.inflight[rq], 1u);
         }
-        *my = sv;
+        *my_save() = sv;
     }
     __syncthreads();
     if (threadIdx.x == 0 && A.wg_save) A.wg_save[blockIdx.x] = WgSave{{S.slot_req[0], S.slot_req[1]}, S.cur, 0};

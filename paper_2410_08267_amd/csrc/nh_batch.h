@@ -4,8 +4,8 @@
 //
 // Each workgroup holds the coefficient tables of one or two requests in LDS
 // (SLOTS).  Lanes draw trajectories from the request of the "current" slot
-// through a per-request queue counter in HBM (one atomic per wavefront, as in
-// the plain kernels).  When that request has no unclaimed trajectories left,
+// through a per-request queue counter in HBM (one atomic per wavefront pass
+// that has free lanes).  When that request has no unclaimed trajectories left,
 // the wave holding the workgroup's lock picks another request and loads its
 // table into the next slot once the lanes still running trajectories from that
 // slot have finished.  With two slots the other lanes keep integrating the
