@@ -66,6 +66,19 @@ __device__ __forceinline__ void copy_table(double *dst, const BatchReq &q, int f
     }
 }
 
+// The plain kernel's split layout in a slot of n_tab rows of SPLIT_ROW
+// doubles: K, Kc, 1/s and c (the drift column A is read from the request's
+// staged copy in device memory).
+__device__ __forceinline__ void copy_table_split(double *dst, const BatchReq &q, int first, int step)
+{
+    const int n = q.P.n_tab * 4;
+    const double *src = q.g.tab;
+    for (int i = first; i < n; i += step) {
+        const int node = i >> 2, col = i & 3;
+        dst[node * SPLIT_ROW + col] = src[node * NCOL + COL_K + col];
+    }
+}
+
 // Bytes of one FP32C table slot (kept a multiple of 16 so the next slot's
 // FP64 rows stay aligned).
 template <int NC>
@@ -223,6 +236,32 @@ __device__ __forceinline__ void setup64_uniform(const BatchReq *reqs, int ru, co
     p.ctl.max_steps = (int)q->P.max_steps;
 }
 
+// Five-column launches with one slot and smooth histories: the split table
+// (as the plain kernel: a fifth of the table reads off the LDS) with the
+// parameters as scalars, same values bit for bit.
+template <int NC, int SLOTS, bool HIST>
+constexpr bool slice_split = NC == SPLIT_ROW && SLOTS == 1 && !HIST;
+struct SplitParams {
+    TabCoefSplit<false> cf;
+    DpCtl ctl;
+};
+__device__ __forceinline__ void setup_split_uniform(const BatchReq *reqs, int ru, const double *slot, SplitParams &p)
+{
+    ConstReq *q = (ConstReq *)(reqs + ru);
+    p.cf.lds = slot;
+    p.cf.a = q->g.tabA;
+    p.cf.n_tab = q->P.n_tab;
+    p.cf.u0 = q->P.tab_u0;
+    p.cf.inv_du = q->P.tab_inv_du;
+    p.cf.R_const = q->P.R_const;
+    p.ctl.u_end = q->P.u_end;
+    p.ctl.rtol = q->P.rtol;
+    p.ctl.atol_x = q->P.atol_x;
+    p.ctl.atol_v = q->P.atol_v;
+    p.ctl.r_exit2 = q->P.r_exit2;
+    p.ctl.max_steps = (int)q->P.max_steps;
+}
+
 template <int NC, bool HIST>
 struct Lane32Params {
     TabCoef32<NC, HIST> cf;
@@ -257,8 +296,12 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
     const int slot_n = A.n_tab * NC;
     if (threadIdx.x == 0) sched_init(S, A);
     __syncthreads();
+    constexpr bool SPLIT = slice_split<NC, SLOTS, HIST>;
     for (int s = 0; s < SLOTS; ++s)
-        if (S.slot_req[s] >= 0) copy_table<NC>(lds64 + s * slot_n, A.reqs[S.slot_req[s]], threadIdx.x, blockDim.x);
+        if (S.slot_req[s] >= 0) {
+            if constexpr (SPLIT) copy_table_split(lds64 + s * slot_n, A.reqs[S.slot_req[s]], threadIdx.x, blockDim.x);
+            else copy_table<NC>(lds64 + s * slot_n, A.reqs[S.slot_req[s]], threadIdx.x, blockDim.x);
+        }
 
     long long t = -1;
     int rq = 0, sl = 0;
@@ -290,7 +333,8 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
             int r, s;
             long long p;
             wave_acquire<SLOTS>(S, A, mask, r, p, s, [&](int slot, int req) {
-                copy_table<NC>(lds64 + slot * slot_n, A.reqs[req], (int)__lane_id(), 64);
+                if constexpr (SPLIT) copy_table_split(lds64 + slot * slot_n, A.reqs[req], (int)__lane_id(), 64);
+                else copy_table<NC>(lds64 + slot * slot_n, A.reqs[req], (int)__lane_id(), 64);
             });
             if (r >= 0) {
                 // the lanes that got a trajectory share one request and slot
@@ -311,6 +355,10 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
                         finish_free(q, t);
                         slot_release(S, sl);
                         t = -1;
+                    } else if constexpr (SPLIT) {
+                        SplitParams up;
+                        setup_split_uniform(A.reqs, ru, lds64, up);
+                        dp5_start(L, up.cf, x0, vx0, vy0, q.P.h0, q.P.u_start, q.P.u_end);
                     } else if constexpr (SLOTS == 1 && !HIST) {
                         Lane64Params<NC, HIST, true> up;
                         setup64_uniform(A.reqs, ru, lds64, up);
@@ -330,7 +378,11 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
         if (expired) break;
         if (t >= 0) {
             int st;
-            if constexpr (SLOTS == 1 && !HIST) {
+            if constexpr (SPLIT) {
+                SplitParams up;
+                setup_split_uniform(A.reqs, __builtin_amdgcn_readfirstlane(rq), lds64, up);
+                st = dp5_attempt(L, up.cf, up.ctl);
+            } else if constexpr (SLOTS == 1 && !HIST) {
                 // With one slot a workgroup loads a new request only once no
                 // lane runs a trajectory of the old one, so every lane here
                 // serves the same request: its parameters are wave-uniform and
