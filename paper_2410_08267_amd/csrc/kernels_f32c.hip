@@ -32,16 +32,18 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
     __shared__ BlockStats bst;
     // the workgroup's partial sums follow the table
     unsigned long long *const lacc =
-        (unsigned long long *)((char *)lds_mix + quad_lds_offset(f32c_table_bytes<NC>(P.n_tab)));
+        (unsigned long long *)((char *)lds_mix + quad_lds_offset(f32c_table_bytes<NC, true>(P.n_tab)));
     if constexpr (FUSED) {
         block_stats_init(bst);
         quad_lds_init(lacc, qa.lds_n);
     }
-    stage_f32c_table<NC>(lds_mix, g.tab, P.n_tab, threadIdx.x, blockDim.x);
+    stage_f32c_table<NC, true>(lds_mix, g.tab, P.n_tab, threadIdx.x, blockDim.x);
     __syncthreads();
 
-    const TabCoef32<NC, HIST> cf{lds_mix, (const float *)(lds_mix + (size_t)P.n_tab * F32C_T64), NC, P.n_tab,
-                                P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30), P.pw, P.kn};
+    // K and Kc (FP64) and 1/s, c (FP32) from LDS, A from device memory
+    const TabCoef32<NC, HIST, true> cf{lds_mix, (const float *)(lds_mix + (size_t)P.n_tab * f32c_t64<true>), NC,
+                                      P.n_tab, P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30), P.pw, P.kn,
+                                      g.tabA};
     // the promoted FP64 steps read the FP64 table from global memory (rows of NCOL)
     const TabCoef<NC, NCOL, HIST> cf64{g.tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     DpCtl32 ctl;
@@ -113,7 +115,7 @@ static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const T
     // default 512 (a single profile's tail grows with more lanes); at most the
     // launch bound, 768 (the lane state fits 170 VGPRs: three waves per SIMD)
     const int B = P.block > 0 ? (P.block < 768 ? P.block : 768) : 512;
-    size_t lds = f32c_table_bytes<NC>(P.n_tab);
+    size_t lds = f32c_table_bytes<NC, true>(P.n_tab);
     int per_cu = 0;
     hipError_t e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED>, B, lds, &per_cu);
     if (e != hipSuccess) return e;

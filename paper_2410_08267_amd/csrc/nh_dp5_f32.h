@@ -70,29 +70,44 @@ __device__ __forceinline__ void rhs32(const float c[NCOL], float R, float x, flo
 // afterwards (K and Kc after their power-law factor when HIST, which also keeps
 // the stencils inside spline pieces); 1/s, c and a moving R come from an FP32
 // table (rows of NC - 3 floats) with the same weights rounded to FP32.
+// SPLIT: as in the plain FP64 kernel, A comes from its node-by-node copy in
+// device memory and the LDS rows hold only K and Kc (a quarter of the table's
+// LDS bytes per stage less; the same FMA chain, so the same bits).
 constexpr int F32C_T64 = 3;   // FP64 columns: A, K, Kc
-template <int NC>
+template <bool SPLIT>
+constexpr int f32c_t64 = SPLIT ? F32C_T64 - 1 : F32C_T64;   // FP64 columns in LDS
+template <int NC, bool SPLIT = false>
 __host__ __device__ constexpr size_t f32c_table_bytes(int n_tab)
 {
-    return (size_t)n_tab * (F32C_T64 * sizeof(double) + (NC - F32C_T64) * sizeof(float));
+    return (size_t)n_tab * (f32c_t64<SPLIT> * sizeof(double) + (NC - F32C_T64) * sizeof(float));
 }
 
-template <int NC, bool HIST = false>
+template <int NC, bool HIST = false, bool SPLIT = false>
 struct TabCoef32 {
-    const double *t64;      // n_tab rows of A, K, Kc
+    const double *t64;      // n_tab rows of A, K, Kc (SPLIT: K, Kc)
     const float *t32;       // n_tab rows of 1/s, c (, R)
     int nc, n_tab;          // nc: NCOL when this request's R moves (possible only when NC == NCOL)
     double u0, inv_du;
     float R_const;
     PowFactor pw;
     Knots kn;
+    const double *a = nullptr;   // SPLIT: n_tab values of A
     __device__ __forceinline__ void at(double u, float c[NCOL], float &R) const
     {
         constexpr int N32 = NC - F32C_T64;
+        constexpr int T64 = f32c_t64<SPLIT>;
         const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
-        const double *r64 = tab_row(t64, w.row, F32C_T64);
-        const double A = stencil_col(w, r64, F32C_T64, 0);
-        double K = stencil_col(w, r64, F32C_T64, 1), Kc = stencil_col(w, r64, F32C_T64, 2);
+        const double *r64 = tab_row(t64, w.row, T64);
+        double A, K, Kc;
+        if constexpr (SPLIT) {
+            A = stencil_a(w, a + (unsigned)w.row);
+            K = stencil_col(w, r64, T64, 0);
+            Kc = stencil_col(w, r64, T64, 1);
+        } else {
+            A = stencil_col(w, r64, T64, 0);
+            K = stencil_col(w, r64, T64, 1);
+            Kc = stencil_col(w, r64, T64, 2);
+        }
         if constexpr (HIST) {
             const double f = pow_factor(pw, u);
             K *= f;
@@ -108,20 +123,94 @@ struct TabCoef32 {
             c[F32C_T64 + k] = fmaf(wd, r32[3 * N32 + k], fmaf(wc, r32[2 * N32 + k], fmaf(wb, r32[N32 + k], wa * r32[k])));
         R = (NC == NCOL && nc == NCOL) ? c[COL_R] : R_const;
     }
+    // SPLIT tables: the coefficients at uP and at uQ <= uP, a fraction of a
+    // step apart, from one five-row window where their stencils start on the
+    // same or adjacent nodes, P's weights shifted onto Q's rows (a zero weight
+    // on the unused end row); lanes whose stencils lie further apart read P's
+    // own rows.  Either way the values equal those of two at() calls bit for
+    // bit: an FMA with a zero weight adds an exact zero.
+    static constexpr bool paired = SPLIT;
+    __device__ __forceinline__ void at2(double uP, double uQ, float cP[NCOL], float &RP, float cQ[NCOL],
+                                        float &RQ) const
+    {
+        static_assert(SPLIT, "the paired window reads the split layout");
+        constexpr int N32 = NC - F32C_T64;
+        constexpr int T64 = f32c_t64<SPLIT>;
+        const Stencil4 wQ = table_stencil<HIST>(n_tab, u0, inv_du, kn, uQ);
+        const Stencil4 wP = table_stencil<HIST>(n_tab, u0, inv_du, kn, uP);
+        const int d = wP.row - wQ.row;
+        const bool sh = d == 1;
+        const double v0 = sh ? 0.0 : wP.wa, v1 = sh ? wP.wa : wP.wb, v2 = sh ? wP.wb : wP.wc;
+        const double v3 = sh ? wP.wc : wP.wd, v4 = sh ? wP.wd : 0.0;
+        const int row4i = min(wQ.row + 4, n_tab - 1);
+        double q64[F32C_T64], p64[F32C_T64];   // A, K, Kc
+        {
+            const double *aq = a + (unsigned)wQ.row;
+            const double r0 = aq[0], r1 = aq[1], r2 = aq[2], r3 = aq[3];
+            q64[0] = fma(wQ.wd, r3, fma(wQ.wc, r2, fma(wQ.wb, r1, wQ.wa * r0)));
+            p64[0] = fma(v4, a[(unsigned)row4i], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
+        }
+        const double *row = tab_row(t64, wQ.row, T64);
+        const double *row4 = tab_row(t64, row4i, T64);
+#pragma unroll
+        for (int k = 0; k < T64; ++k) {
+            const double r0 = row[k], r1 = row[T64 + k], r2 = row[2 * T64 + k], r3 = row[3 * T64 + k];
+            q64[1 + k] = fma(wQ.wd, r3, fma(wQ.wc, r2, fma(wQ.wb, r1, wQ.wa * r0)));
+            p64[1 + k] = fma(v4, row4[k], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
+        }
+        const float qa = (float)wQ.wa, qb = (float)wQ.wb, qc = (float)wQ.wc, qd = (float)wQ.wd;
+        const float f0 = (float)v0, f1 = (float)v1, f2 = (float)v2, f3 = (float)v3, f4 = (float)v4;
+        const float *r32 = t32 + __umul24((unsigned)wQ.row, (unsigned)N32);
+        const float *r32e = t32 + __umul24((unsigned)row4i, (unsigned)N32);
+#pragma unroll
+        for (int k = 0; k < N32; ++k) {
+            const float r0 = r32[k], r1 = r32[N32 + k], r2 = r32[2 * N32 + k], r3 = r32[3 * N32 + k];
+            cQ[F32C_T64 + k] = fmaf(qd, r3, fmaf(qc, r2, fmaf(qb, r1, qa * r0)));
+            cP[F32C_T64 + k] = fmaf(f4, r32e[k], fmaf(f3, r3, fmaf(f2, r2, fmaf(f1, r1, f0 * r0))));
+        }
+        if ((unsigned)d > 1u) {
+            p64[0] = stencil_a(wP, a + (unsigned)wP.row);
+            const double *rp = tab_row(t64, wP.row, T64);
+#pragma unroll
+            for (int k = 0; k < T64; ++k) p64[1 + k] = stencil_col(wP, rp, T64, k);
+            const float pa = (float)wP.wa, pb = (float)wP.wb, pc = (float)wP.wc, pd = (float)wP.wd;
+            const float *rp32 = t32 + __umul24((unsigned)wP.row, (unsigned)N32);
+#pragma unroll
+            for (int k = 0; k < N32; ++k)
+                cP[F32C_T64 + k] =
+                    fmaf(pd, rp32[3 * N32 + k], fmaf(pc, rp32[2 * N32 + k], fmaf(pb, rp32[N32 + k], pa * rp32[k])));
+        }
+        if constexpr (HIST) {
+            const double fP = pow_factor(pw, uP), fQ = pow_factor(pw, uQ);
+            p64[1] *= fP;
+            p64[2] *= fP;
+            q64[1] *= fQ;
+            q64[2] *= fQ;
+        }
+#pragma unroll
+        for (int k = 0; k < F32C_T64; ++k) {
+            cP[k] = (float)p64[k];
+            cQ[k] = (float)q64[k];
+        }
+        RP = (NC == NCOL && nc == NCOL) ? cP[COL_R] : R_const;
+        RQ = (NC == NCOL && nc == NCOL) ? cQ[COL_R] : R_const;
+    }
 };
 
 // Copy the first NC columns of FP64 table rows (stride NCOL) into the FP32C
-// layout at dst: n_tab rows of A, K, Kc (FP64), then n_tab rows of the other
-// NC - 3 columns (FP32); by the threads first, first + step, ...
-template <int NC>
+// layout at dst: n_tab rows of A, K, Kc (FP64; SPLIT: K, Kc), then n_tab rows
+// of the other NC - 3 columns (FP32); by the threads first, first + step, ...
+template <int NC, bool SPLIT = false>
 __device__ __forceinline__ void stage_f32c_table(void *dst, const double *src, int n_tab, int first, int step)
 {
     constexpr int N32 = NC - F32C_T64;
+    constexpr int T64 = f32c_t64<SPLIT>;
+    constexpr int C0 = F32C_T64 - T64;   // first FP64 column held in LDS
     double *t64 = (double *)dst;
-    float *t32 = (float *)(t64 + (size_t)n_tab * F32C_T64);
-    for (int i = first; i < n_tab * F32C_T64; i += step) {
-        const int node = i / F32C_T64, col = i - node * F32C_T64;
-        t64[i] = src[node * NCOL + col];
+    float *t32 = (float *)(t64 + (size_t)n_tab * T64);
+    for (int i = first; i < n_tab * T64; i += step) {
+        const int node = i / T64, col = i - node * T64;
+        t64[i] = src[node * NCOL + C0 + col];
     }
     for (int i = first; i < n_tab * N32; i += step) {
         const int node = i / N32, col = i - node * N32;
@@ -170,15 +259,21 @@ __device__ __forceinline__ int dp5_attempt32(Lane32 &L, const CF &cf, const DpCt
     const double u = L.u;
     const float x = L.x + L.xc, y = L.y + L.yc, vx = L.vx, vy = L.vy;
     const float k1x = L.k1x, k1y = L.k1y, k1u = L.k1u, k1v = L.k1v;
-    float c[NCOL], R;
+    float c[NCOL], R, cb[NCOL], Rb;
     float k2x, k2y, k2u, k2v, k3x, k3y, k3u, k3v, k4x, k4y, k4u, k4v;
     float k5x, k5y, k5u, k5v, k6x, k6y, k6u, k6v, k7x, k7y, k7u, k7v;
 
-    cf.at(u + (double)c2 * hd, c, R);
+    // stages 2 and 3 lie a tenth of a step apart: one table window for both
+    // where the source has one
+    if constexpr (CF::paired) {
+        cf.at2(u + (double)c2 * hd, u + (double)c3 * hd, c, R, cb, Rb);
+    } else {
+        cf.at(u + (double)c2 * hd, c, R);
+    }
     rhs32(c, R, x + h * (a21 * k1x), y + h * (a21 * k1y), vx + h * (a21 * k1u), vy + h * (a21 * k1v),
           k2x, k2y, k2u, k2v);
-    cf.at(u + (double)c3 * hd, c, R);
-    rhs32(c, R, x + h * (a31 * k1x + a32 * k2x), y + h * (a31 * k1y + a32 * k2y),
+    if constexpr (!CF::paired) cf.at(u + (double)c3 * hd, cb, Rb);
+    rhs32(cb, Rb, x + h * (a31 * k1x + a32 * k2x), y + h * (a31 * k1y + a32 * k2y),
           vx + h * (a31 * k1u + a32 * k2u), vy + h * (a31 * k1v + a32 * k2v), k3x, k3y, k3u, k3v);
     cf.at(u + (double)c4 * hd, c, R);
     rhs32(c, R, x + h * (a41 * k1x + a42 * k2x + a43 * k3x), y + h * (a41 * k1y + a42 * k2y + a43 * k3y),
