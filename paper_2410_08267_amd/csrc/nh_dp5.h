@@ -162,11 +162,12 @@ __device__ __forceinline__ void dp5_start(Lane64 &L, const CF &cf, double x0, do
 // Every lane of a launch starts at the same u: the coefficients there and the
 // first step are computed once per workgroup into LDS (after the table is
 // staged; a barrier follows) and read back at each start.  The reads are
-// volatile so that they stay at the start and are not hoisted out of the
-// trajectory loop, where they would hold registers for its whole length.
+// indexed by a zero the compiler cannot see through, so that they stay at the
+// start and are not hoisted out of the trajectory loop, where they would hold
+// registers for its whole length.  (A volatile read would do the same but
+// loses the LDS address space: serialized flat loads, each waited for.)
 struct StartCache {
-    double c[NCOL];
-    double R, h;
+    double v[NCOL + 2];   // c[0..NCOL), then R, then the first step h
 };
 
 template <class CF>
@@ -176,19 +177,21 @@ __device__ __forceinline__ void start_cache_fill(StartCache &sc, const CF &cf, d
     if (threadIdx.x == 0) {
         double c[NCOL], R;
         cf.at(u_start, c, R);
-        for (int i = 0; i < NCOL; ++i) sc.c[i] = c[i];
-        sc.R = R;
-        sc.h = dp5_first_step(h0, u_start, u_end);
+        for (int i = 0; i < NCOL; ++i) sc.v[i] = c[i];
+        sc.v[NCOL] = R;
+        sc.v[NCOL + 1] = dp5_first_step(h0, u_start, u_end);
     }
 }
 
 __device__ __forceinline__ void dp5_start_cached(Lane64 &L, const StartCache &sc, double x0, double vx0,
                                                  double vy0, double u_start)
 {
-    const volatile StartCache &v = sc;
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    const double *v = sc.v + z;
     double c[NCOL];
-    for (int i = 0; i < NCOL; ++i) c[i] = v.c[i];
-    dp5_start_at(L, c, v.R, x0, vx0, vy0, v.h, u_start);
+    for (int i = 0; i < NCOL; ++i) c[i] = v[i];
+    dp5_start_at(L, c, v[NCOL], x0, vx0, vy0, v[NCOL + 1], u_start);
 }
 
 // One attempted step.  Returns -1 while the trajectory continues, else its
