@@ -254,21 +254,24 @@ enum {
                                   default [0]: 3073, or for the batched and serving forms as many
                                   as their LDS slots hold (a larger value is NH_EINVAL there) */
     NH_OPT_BLOCK_THREADS = 5,  /* Dormand-Prince threads per workgroup, a multiple of 64 in
-                                  [64, 1024] (FP32C kernels use at most 768), or 0 for the
-                                  defaults [0]: what nh_autotune chose for that form and
-                                  precision, else 768 for FP64 nh_solve (three waves per SIMD;
-                                  more lanes per profile lengthen its tail), 512 for FP32C
-                                  nh_solve, 768 for FP32C batches and serving (three waves per
-                                  SIMD, their limit), 1024 for FP64 batches and serving (four
-                                  waves per SIMD).  Plain solves run side by side under
+                                  [64, 1024] (FP32C plain solves and FP32C batches with two
+                                  table slots use at most 768), or 0 for the defaults [0]: what
+                                  nh_autotune chose for that form and precision, else 768 for
+                                  FP64 nh_solve (three waves per SIMD; more lanes per profile
+                                  lengthen its tail), 512 for FP32C nh_solve, 1024 for batches
+                                  and serving (four waves per SIMD; 768 for FP32C with two
+                                  slots).  Plain solves run side by side under
                                   NH_OPT_WORKGROUPS do best at 1024 (FP64) and 768 (FP32C). */
     NH_OPT_BATCH_SLOTS   = 6,  /* batched and serving forms: request tables per workgroup in
                                   LDS, 1 or 2, or 0 for the default [0]: what nh_autotune chose
-                                  for FP32C, else 2 for FP32C, and 1 for FP64 (3073
-                                  nodes, the plain form's table; a workgroup drains before it
-                                  changes request), 2 for FP32C (3073 FP32 nodes each; lanes
-                                  keep integrating while the next table loads).  Two FP64
-                                  tables hold at most 2044 (constant R) or 1703 nodes. */
+                                  for FP32C, else 1 (3073 nodes; a workgroup drains before it
+                                  changes request, and every running lane serves one request,
+                                  so its parameters are scalars).  With 2 the lanes keep
+                                  integrating while the next table loads, but carry their
+                                  request's parameters in registers: FP32C batches at 768
+                                  threads with two slots ran 21 % slower than at 1024 with
+                                  one.  Two FP64 tables hold at most 2044 (constant R) or
+                                  1703 nodes. */
     NH_OPT_SLICE_US      = 7,  /* serving: length of a time slice in microseconds, 200..1e6 [4000];
                                   requests are admitted and retired between slices.  While
                                   the admitted, unclaimed work would take more than four

@@ -23,11 +23,12 @@ int request_columns(const nh_request *q)
     return (q->halo.compensated && q->halo.geometry == NH_GEOM_DELTA200) ? NCOL : NCOL - 1;
 }
 
-int batch_block(const nh_context *ctx, bool f32c)
+int batch_block(const nh_context *ctx, bool f32c, int slots)
 {
-    // FP64 slices fit four waves per SIMD (1024 threads, 128 VGPRs); the FP32C
-    // lane state three (768 threads, 170 VGPRs)
-    const int cap = f32c ? 768 : 1024;
+    // FP64 slices fit four waves per SIMD (1024 threads, 128 VGPRs); FP32C
+    // slices with two table slots three (768 threads, 170 VGPRs), with one
+    // slot four (the request parameters sit in scalar registers)
+    const int cap = (!f32c || slots == 1) ? 1024 : 768;
     if (ctx->block_threads > 0) return std::min(ctx->block_threads, cap);
     return ctx->tuned_batch_block[f32c] > 0 ? std::min(ctx->tuned_batch_block[f32c], cap) : cap;
 }
@@ -35,7 +36,7 @@ int batch_block(const nh_context *ctx, bool f32c)
 int batch_slots(const nh_context *ctx, bool f32c)
 {
     if (ctx->batch_slots > 0) return ctx->batch_slots;
-    return ctx->tuned_batch_slots[f32c] > 0 ? ctx->tuned_batch_slots[f32c] : (f32c ? 2 : 1);
+    return ctx->tuned_batch_slots[f32c] > 0 ? ctx->tuned_batch_slots[f32c] : 1;
 }
 
 int batch_table_nodes(nh_context *ctx, bool f32c, int nc, int slots, int *n_tab)
@@ -137,7 +138,6 @@ int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d
     const int slots = batch_slots(ctx, f32c);
     int n_tab = 0;
     if ((rc = batch_table_nodes(ctx, f32c, nc, slots, &n_tab)) != NH_OK) return rc;
-    const int block = batch_block(ctx, f32c);
     hipStream_t s = (hipStream_t)stream;
 
     HIPCHK(hipSetDevice(ctx->device));
@@ -218,6 +218,7 @@ int nh_solve_batch(nh_context *ctx, int n_req, const nh_request *reqs, double *d
     A.resume = 0;
     bool pow = false;
     for (int i = 0; i < n_req; ++i) pow = pow || hdesc[i].P.hist;
+    const int block = batch_block(ctx, f32c, slots);
     int grid = 0;
     HIPCHK(slice_capacity(f32c, nc, slots, pow, n_tab, block, ctx->n_cu, &grid));
     const long long need = (ntot + block - 1) / block;

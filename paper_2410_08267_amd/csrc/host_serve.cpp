@@ -194,7 +194,7 @@ int alloc_device_state(nh_context *ctx, ServeState &S)
 int start_session(nh_context *ctx, ServeState &S, bool f32c)
 {
     S.slots = batch_slots(ctx, f32c);
-    S.block = batch_block(ctx, f32c);
+    S.block = batch_block(ctx, f32c, S.slots);
     int rc = batch_table_nodes(ctx, f32c, NCOL, S.slots, &S.n_tab);
     if (rc != NH_OK) return rc;
     HIPCHK(hipSetDevice(ctx->device));

@@ -33,10 +33,11 @@ std::vector<Cand> candidates(int form, bool f32c)
         else
             for (int b : fp64) c.push_back({b, 0});
     } else if (f32c) {
-        // two FP32 tables of 3073 nodes fit one workgroup's LDS; the results do
-        // not depend on the slot count
+        // two FP32 tables of 3073 nodes fit one workgroup's LDS, and one slot
+        // allows 1024 threads; the results do not depend on either
         for (int s : {1, 2})
-            for (int b : {256, 384, 512, 768}) c.push_back({b, s});
+            for (int b : {256, 384, 512, 768, 1024})
+                if (s == 1 || b <= 768) c.push_back({b, s});
     } else {
         // FP64 batches keep one 3073-node table per workgroup: the plain
         // form's table, so that a batched profile equals the plain one

@@ -262,21 +262,44 @@ __device__ __forceinline__ void setup_split_uniform(const BatchReq *reqs, int ru
     p.ctl.max_steps = (int)q->P.max_steps;
 }
 
-template <int NC, bool HIST>
+// A request descriptor read with a wave-uniform index through the constant
+// address space, word by word into a local copy (only the words used are
+// loaded): scalar loads into scalar registers.  Descriptors do not change
+// while a kernel runs; through a generic pointer the compiler cannot rule out
+// the kernel's own stores and loads them per lane.
+__device__ __forceinline__ BatchReq load_uniform(const BatchReq *p)
+{
+    static_assert(sizeof(BatchReq) % 4 == 0, "descriptor words");
+    constexpr int N = (int)(sizeof(BatchReq) / 4);
+    using W = const __attribute__((address_space(4))) unsigned;
+    W *w = (W *)p;
+    unsigned buf[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) buf[i] = w[i];
+    BatchReq q;
+    __builtin_memcpy(&q, buf, sizeof(BatchReq));
+    return q;
+}
+
+// SPLIT: the table slot holds the split FP32C layout (K, Kc in FP64; A from
+// the request's staged copy in device memory), with the shared window of
+// stages 2 and 3.
+template <int NC, bool HIST, bool SPLIT = false>
 struct Lane32Params {
-    TabCoef32<NC, HIST> cf;
+    TabCoef32<NC, HIST, SPLIT> cf;
     TabCoefB<NC, NCOL, HIST> cf64;    // the promoted FP64 attempts read the FP64 table from HBM
     DpCtl32 ctl;
     DpCtl ctl64;
     double h_fp64;
 };
-template <int NC, bool HIST>
-__device__ __forceinline__ void setup32(const BatchReq &q, const char *slot, Lane32Params<NC, HIST> &p)
+template <int NC, bool HIST, bool SPLIT>
+__device__ __forceinline__ void setup32(const BatchReq &q, const char *slot, Lane32Params<NC, HIST, SPLIT> &p)
 {
     const TrajParams &P = q.P;
     const double *t64 = (const double *)slot;
-    p.cf = TabCoef32<NC, HIST>{t64, (const float *)(t64 + (size_t)P.n_tab * F32C_T64), q.nc, P.n_tab,
-                              P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30), P.pw, P.kn};
+    p.cf = TabCoef32<NC, HIST, SPLIT>{t64, (const float *)(t64 + (size_t)P.n_tab * f32c_t64<SPLIT>), q.nc,
+                                     P.n_tab, P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30), P.pw,
+                                     P.kn, q.g.tabA};
     p.cf64 = TabCoefB<NC, NCOL, HIST>{q.g.tab, q.nc, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     f32c_controls(P, p.ctl, p.ctl64);
     p.h_fp64 = P.h_fp64;
@@ -424,32 +447,43 @@ __global__ __launch_bounds__(1024) void k_slice_f64(SliceArgs A)
 // FP32-compensated slice kernel
 // ---------------------------------------------------------------------------
 
+// Two slots: at most 768 threads (three waves per SIMD: the lane state with
+// per-lane request parameters needs ~160 VGPRs).  One slot: 1024 (four waves;
+// with smooth histories the request parameters sit in scalar registers, and
+// the sampled-history variant spills a few values).
 template <int NC, int SLOTS, bool HIST>
-__global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
+constexpr int f32c_slice_max_block = SLOTS == 1 ? 1024 : 768;
+template <int NC, int SLOTS, bool HIST>
+__global__ __launch_bounds__((f32c_slice_max_block<NC, SLOTS, HIST>)) void k_slice_f32c(SliceArgs A)
 {
     extern __shared__ double lds32b[];
     __shared__ WgSched S;
     char *const slots = (char *)lds32b;
     const size_t slot_n = f32c_slot_bytes<NC>(A.n_tab);
+    // one slot, smooth histories: every lane running a trajectory serves the
+    // slot's one request (a new one is loaded only once none runs), so its
+    // parameters are wave-uniform scalars, which leaves registers for the
+    // split table and the shared window of stages 2 and 3
+    constexpr bool UNI = SLOTS == 1 && !HIST;
     if (threadIdx.x == 0) sched_init(S, A);
     __syncthreads();
     for (int s = 0; s < SLOTS; ++s)
         if (S.slot_req[s] >= 0)
-            stage_f32c_table<NC>(slots + s * slot_n, A.reqs[S.slot_req[s]].g.tab, A.reqs[S.slot_req[s]].P.n_tab,
-                                 threadIdx.x, blockDim.x);
+            stage_f32c_table<NC, UNI>(slots + s * slot_n, A.reqs[S.slot_req[s]].g.tab,
+                                      A.reqs[S.slot_req[s]].P.n_tab, threadIdx.x, blockDim.x);
 
     long long t = -1;
     int rq = 0, sl = 0;
     double v0n = 1.0;
     Lane32 L{};
     Lane32Params<NC, HIST> lp{};
-    LaneSave *const my = A.lane_save ? A.lane_save + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) : nullptr;
-    if (A.resume && my) {
-        const LaneSave sv = *my;
+    const auto my_save = [&]() { return A.lane_save + ((size_t)blockIdx.x * blockDim.x + threadIdx.x); };
+    if (A.resume && A.lane_save) {
+        const LaneSave sv = *my_save();
         if (sv.t >= 0 && !A.reqs[sv.req].retired) {
             t = sv.t;
             rq = sv.req;
-            sl = sv.slot;
+            sl = SLOTS == 1 ? 0 : sv.slot;
             unpack32(sv, L, v0n);
             setup32(A.reqs[rq], slots + sl * slot_n, lp);
             __hip_atomic_fetch_add(&S.active[sl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -466,28 +500,34 @@ __global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
             int r, s;
             long long p;
             wave_acquire<SLOTS>(S, A, mask, r, p, s, [&](int slot, int req) {
-                stage_f32c_table<NC>(slots + slot * slot_n, A.reqs[req].g.tab, A.reqs[req].P.n_tab, (int)__lane_id(),
-                                     64);
+                stage_f32c_table<NC, UNI>(slots + slot * slot_n, A.reqs[req].g.tab, A.reqs[req].P.n_tab,
+                                          (int)__lane_id(), 64);
             });
             if (r >= 0) {
-                const BatchReq &q = A.reqs[r];
-                rq = r;
-                sl = s;
+                // the lanes that got a trajectory share one request and slot
+                const int ru = __builtin_amdgcn_readfirstlane(r);
+                const BatchReq &q = A.reqs[ru];
+                rq = ru;
+                sl = SLOTS == 1 ? 0 : s;
                 t = traj_of(p, q.P);
                 if (q.free_all) {
                     finish_free(q, t);
-                    slot_release(S, s);
+                    slot_release(S, sl);
                     t = -1;
                 } else {
-                    setup32(q, slots + s * slot_n, lp);
                     double x0, vx0, vy0;
                     initial_state(q, t, x0, vx0, vy0);
                     v0n = sqrt(norm2(vx0, vy0));
                     if (q.P.cull_D > 0.0 && never_enters(x0, vx0, vy0, q.P.cull_D, cull_radius2(q.P.r_exit))) {
                         finish_free(q, t);
-                        slot_release(S, s);
+                        slot_release(S, sl);
                         t = -1;
+                    } else if constexpr (UNI) {
+                        Lane32Params<NC, false, true> up;
+                        setup32(load_uniform(A.reqs + ru), slots, up);
+                        f32c_start(L, up.cf, x0, vx0, vy0, q.P.h0, q.P.u_start, q.P.u_end);
                     } else {
+                        setup32(q, slots + sl * slot_n, lp);
                         f32c_start(L, lp.cf, x0, vx0, vy0, q.P.h0, q.P.u_start, q.P.u_end);
                     }
                 }
@@ -500,7 +540,14 @@ __global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
         }
         if (expired) break;
         if (t >= 0) {
-            const int st = f32c_attempt(L, lp.cf, lp.cf64, lp.ctl, lp.ctl64, lp.h_fp64);
+            int st;
+            if constexpr (UNI) {
+                Lane32Params<NC, false, true> up;
+                setup32(load_uniform(A.reqs + __builtin_amdgcn_readfirstlane(rq)), slots, up);
+                st = f32c_attempt(L, up.cf, up.cf64, up.ctl, up.ctl64, up.h_fp64);
+            } else {
+                st = f32c_attempt(L, lp.cf, lp.cf64, lp.ctl, lp.ctl64, lp.h_fp64);
+            }
             if (st >= 0) {
                 const TrajOut o = A.reqs[rq].o;
                 const double fx = L.vx, fy = L.vy;
@@ -511,7 +558,7 @@ __global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
             }
         }
     }
-    if (my) {
+    if (A.lane_save) {
         LaneSave sv;
         sv.t = t;
         sv.req = rq;
@@ -520,7 +567,7 @@ __global__ __launch_bounds__(768) void k_slice_f32c(SliceArgs A)
             pack32(L, v0n, sv);
             atomicAdd(&A.inflight[rq], 1u);
         }
-        *my = sv;
+        *my_save() = sv;
     }
     __syncthreads();
     if (threadIdx.x == 0 && A.wg_save) A.wg_save[blockIdx.x] = WgSave{{S.slot_req[0], S.slot_req[1]}, S.cur, 0};

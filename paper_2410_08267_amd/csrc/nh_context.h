@@ -99,7 +99,7 @@ int solve_enqueue(nh_context *ctx, const nh_request *q, double *d_out, double *d
 int collect_stats(nh_context *ctx, nh_stats *out);
 int request_columns(const nh_request *q);
 int batch_slots(const nh_context *ctx, bool f32c);
-int batch_block(const nh_context *ctx, bool f32c);
+int batch_block(const nh_context *ctx, bool f32c, int slots);
 int batch_table_nodes(nh_context *ctx, bool f32c, int nc, int slots, int *n_tab);
 
 #define HIPCHK(call)                                                                     \

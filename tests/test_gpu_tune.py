@@ -58,8 +58,10 @@ def test_batch_autotune_changes_no_result(ctx, prec):
     res = ctx.autotune(reqs, "batch")
     print(res, flush=True)
     if prec == "fp32c":
-        assert res["block_threads"] in {256, 384, 512, 768} and res["batch_slots"] in {1, 2}
-        assert res["n_tried"] == 8
+        assert res["batch_slots"] in {1, 2}
+        # one slot: up to 1024 threads; two slots: up to 768
+        assert res["block_threads"] in ({256, 384, 512, 768, 1024} if res["batch_slots"] == 1 else {256, 384, 512, 768})
+        assert res["n_tried"] == 9
     else:
         assert res["block_threads"] in {512, 768, 1024} and res["batch_slots"] == 1
         assert res["n_tried"] == 3
