@@ -242,7 +242,7 @@ def tune(ctx, form: str, reqs):
 # share queues and serialise.
 PIPE_DEPTH = 4
 PLAIN_FP64_BLOCK = 1024   # four waves per SIMD pay once tails no longer idle the device
-PLAIN_FP32C_BLOCK = 768   # three waves per SIMD, the FP32C kernel's limit
+PLAIN_FP32C_BLOCK = 1024  # four waves per SIMD (the FP32C kernel built for them)
 CU_SHARE = 1.0            # workgroups per launch: this many CUs' worth over the profiles in flight
 
 

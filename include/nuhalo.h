@@ -254,14 +254,14 @@ enum {
                                   default [0]: 3073, or for the batched and serving forms as many
                                   as their LDS slots hold (a larger value is NH_EINVAL there) */
     NH_OPT_BLOCK_THREADS = 5,  /* Dormand-Prince threads per workgroup, a multiple of 64 in
-                                  [64, 1024] (FP32C plain solves and FP32C batches with two
-                                  table slots use at most 768), or 0 for the defaults [0]: what
+                                  [64, 1024] (FP32C batches with two table slots use at most
+                                  768), or 0 for the defaults [0]: what
                                   nh_autotune chose for that form and precision, else 768 for
                                   FP64 nh_solve (three waves per SIMD; more lanes per profile
                                   lengthen its tail), 512 for FP32C nh_solve, 1024 for batches
                                   and serving (four waves per SIMD; 768 for FP32C with two
                                   slots).  Plain solves run side by side under
-                                  NH_OPT_WORKGROUPS do best at 1024 (FP64) and 768 (FP32C). */
+                                  NH_OPT_WORKGROUPS do best at 1024. */
     NH_OPT_BATCH_SLOTS   = 6,  /* batched and serving forms: request tables per workgroup in
                                   LDS, 1 or 2, or 0 for the default [0]: what nh_autotune chose
                                   for FP32C, else 1 (3073 nodes; a workgroup drains before it

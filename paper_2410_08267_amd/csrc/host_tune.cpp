@@ -27,7 +27,7 @@ std::vector<Cand> candidates(int form, bool f32c)
 {
     std::vector<Cand> c;
     if (form == NH_FORM_PLAIN) {
-        const int fp64[] = {256, 384, 512, 640, 768, 1024}, fp32[] = {256, 384, 512, 640, 768};
+        const int fp64[] = {256, 384, 512, 640, 768, 1024}, fp32[] = {256, 384, 512, 640, 768, 1024};
         if (f32c)
             for (int b : fp32) c.push_back({b, 0});
         else

@@ -24,9 +24,10 @@ namespace nh {
 // and the test is left out of the trajectory loop)
 // FUSED: each finished trajectory adds its quadrature term and statistics
 // directly (QuadAcc); nothing is written per trajectory.
-template <int NC, bool CULL, bool HIST, bool FUSED>
-__global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, TrajOut o,
-                                                   unsigned long long *counter, QuadAcc qa)
+// WIDE: up to 1024 threads (four waves per SIMD) instead of 768.
+template <int NC, bool CULL, bool HIST, bool FUSED, bool WIDE>
+__global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, GridPtrs g, TrajOut o,
+                                                                unsigned long long *counter, QuadAcc qa)
 {
     extern __shared__ double lds_mix[];
     __shared__ BlockStats bst;
@@ -40,15 +41,30 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
     stage_f32c_table<NC, true>(lds_mix, g.tab, P.n_tab, threadIdx.x, blockDim.x);
     __syncthreads();
 
-    // K and Kc (FP64) and 1/s, c (FP32) from LDS, A from device memory
-    const TabCoef32<NC, HIST, true> cf{lds_mix, (const float *)(lds_mix + (size_t)P.n_tab * f32c_t64<true>), NC,
-                                      P.n_tab, P.tab_u0, P.tab_inv_du, (float)fmin(P.R_const, 1.0e30), P.pw, P.kn,
-                                      g.tabA};
-    // the promoted FP64 steps read the FP64 table from global memory (rows of NCOL)
-    const TabCoef<NC, NCOL, HIST> cf64{g.tab, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
-    DpCtl32 ctl;
-    DpCtl ctl64;
-    f32c_controls(P, ctl, ctl64);
+    // The request's coefficient sources and step controls.  WIDE: re-read
+    // from the kernel arguments where they are used (scalar loads, kept in
+    // place by an index the compiler cannot see through), since held for the
+    // whole launch they overflow the scalar registers at four waves per SIMD;
+    // otherwise read once (the index is a constant zero and the compiler
+    // hoists the reads).
+    struct Src {
+        TabCoef32<NC, HIST, true> cf;    // K, Kc (FP64) and 1/s, c (FP32) from LDS, A from device memory
+        TabCoef<NC, NCOL, HIST> cf64;    // the promoted FP64 steps: the FP64 table in device memory
+        DpCtl32 ctl;
+        DpCtl ctl64;
+        double h_fp64;
+    };
+    const auto src = [&]() {
+        int z = 0;
+        if constexpr (WIDE) asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        const TrajParams &Pa = (&P)[z];
+        const GridPtrs &ga = (&g)[z];
+        Src r{{lds_mix, (const float *)(lds_mix + (size_t)Pa.n_tab * f32c_t64<true>), NC, Pa.n_tab, Pa.tab_u0,
+               Pa.tab_inv_du, (float)fmin(Pa.R_const, 1.0e30), Pa.pw, Pa.kn, ga.tabA},
+              {ga.tab, Pa.n_tab, Pa.tab_u0, Pa.tab_inv_du, Pa.R_const, Pa.pw, Pa.kn}, {}, {}, Pa.h_fp64};
+        f32c_controls(Pa, r.ctl, r.ctl64);
+        return r;
+    };
 
     long long t = -1;
     double v0n = 1.0;
@@ -76,7 +92,7 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
                     }
                     t = -1;
                 } else {
-                    f32c_start(L, cf, g.r[k], vx0, vy0, P.h0, P.u_start, P.u_end);
+                    f32c_start(L, src().cf, g.r[k], vx0, vy0, P.h0, P.u_start, P.u_end);
                 }
             } else {
                 t = -2;
@@ -86,7 +102,8 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
         // trajectory was culled (t == -1) claim again on the next pass
         if (__ballot(t != -2) == 0ull) break;
         if (t >= 0) {
-            const int st = f32c_attempt(L, cf, cf64, ctl, ctl64, P.h_fp64);
+            const Src a = src();
+            const int st = f32c_attempt(L, a.cf, a.cf64, a.ctl, a.ctl64, a.h_fp64);
             if (st >= 0) {
                 const double fx = L.vx, fy = L.vy;
                 const double ratio = sqrt(norm2(fx, fy)) / v0n;
@@ -108,21 +125,18 @@ __global__ __launch_bounds__(768) void k_dp5_f32c(TrajParams P, GridPtrs g, Traj
     }
 }
 
-template <int NC, bool CULL, bool HIST, bool FUSED>
-static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
-                                 unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
+template <int NC, bool CULL, bool HIST, bool FUSED, bool WIDE>
+static hipError_t launch_f32c_w(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                                unsigned long long *counter, const QuadAcc &qa, int n_cu, int B, hipStream_t s)
 {
-    // default 512 (a single profile's tail grows with more lanes); at most the
-    // launch bound, 768 (the lane state fits 170 VGPRs: three waves per SIMD)
-    const int B = P.block > 0 ? (P.block < 768 ? P.block : 768) : 512;
     size_t lds = f32c_table_bytes<NC, true>(P.n_tab);
     int per_cu = 0;
-    hipError_t e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED>, B, lds, &per_cu);
+    hipError_t e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED, WIDE>, B, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     QuadAcc q = qa;
     if (FUSED) {
-        e = quad_lds_plan((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED>, B, per_cu, P.n_r, lds, q);
+        e = quad_lds_plan((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED, WIDE>, B, per_cu, P.n_r, lds, q);
         if (e != hipSuccess) return e;
     }
     long long grid = (long long)n_cu * per_cu;
@@ -132,9 +146,22 @@ static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const T
     if (grid < 1) grid = 1;
     TrajParams Pk = P;
     Pk.r_exit2 = exit_radius2(P);
-    auto *kern = k_dp5_f32c<NC, CULL, HIST, FUSED>;
+    auto *kern = k_dp5_f32c<NC, CULL, HIST, FUSED, WIDE>;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, s, Pk, g, o, counter, q);
     return hipGetLastError();
+}
+
+template <int NC, bool CULL, bool HIST, bool FUSED>
+static hipError_t launch_f32c_nc(const TrajParams &P, const GridPtrs &g, const TrajOut &o,
+                                 unsigned long long *counter, const QuadAcc &qa, int n_cu, hipStream_t s)
+{
+    // default 512 (a single profile's tail grows with more lanes), at most 1024;
+    // above 768 the kernel built for four waves per SIMD, which re-reads the
+    // request's parameters at each use (a few values spill at that bound, so
+    // it is slower at 768 and below than the one that holds them)
+    const int B = P.block > 0 ? (P.block < 1024 ? P.block : 1024) : 512;
+    return B > 768 ? launch_f32c_w<NC, CULL, HIST, FUSED, true>(P, g, o, counter, qa, n_cu, B, s)
+                   : launch_f32c_w<NC, CULL, HIST, FUSED, false>(P, g, o, counter, qa, n_cu, B, s);
 }
 
 template <bool HIST, bool FUSED>

@@ -87,18 +87,23 @@ def test_fp32c_within_1e4_of_oracle(ctx, O, name, h_fp64):
 
 def test_fp32c_full_size_launch_shapes_agree(ctx):
     """Full 1.28 M-trajectory profile of a heavy halo (seed 4) in the benchmark's
-    launch shape (768-thread workgroups, at most 64 of them) and in the default
-    launch: the same bits.  (The whole profile against the oracle's reference
-    integration: test_gpu_full_size.py.)"""
+    launch shape (1024-thread workgroups, at most 64 of them: the kernel built
+    for four waves per SIMD), at 768 threads and in the default launch: the
+    same bits.  (The whole profile against the oracle's reference integration:
+    test_gpu_full_size.py.)"""
     req = W.precision(4)
-    say(f"fp32c full size seed 4 n_traj={req.n_traj}, 768 threads x 64 workgroups vs default")
-    ctx.set_option("block_threads", 768)
-    ctx.set_option("workgroups", 64)
-    try:
-        got, stats, _ = ctx.solve(req)
-    finally:
-        ctx.set_option("block_threads", 0)
-        ctx.set_option("workgroups", 0)
+    got = {}
+    for block in (1024, 768):
+        say(f"fp32c full size seed 4 n_traj={req.n_traj}, {block} threads x 64 workgroups")
+        ctx.set_option("block_threads", block)
+        ctx.set_option("workgroups", 64)
+        try:
+            got[block], stats, _ = ctx.solve(req)
+        finally:
+            ctx.set_option("block_threads", 0)
+            ctx.set_option("workgroups", 0)
+        assert stats["n_failed"] == 0
+    say("fp32c full size seed 4, default launch")
     got0, _, _ = ctx.solve(req)
-    assert np.array_equal(got0, got)
-    assert stats["n_failed"] == 0
+    assert np.array_equal(got0, got[1024])
+    assert np.array_equal(got0, got[768])

@@ -38,7 +38,7 @@ def test_plain_autotune_changes_no_result(ctx, prec):
     before = plain(ctx, req)
     res = ctx.autotune(sample, "plain")
     print(res, flush=True)
-    allowed = {256, 384, 512, 640, 768} if prec == "fp32c" else {256, 384, 512, 640, 768, 1024}
+    allowed = {256, 384, 512, 640, 768, 1024}
     assert res["block_threads"] in allowed
     assert res["n_tried"] == len(allowed)
     assert res["batch_slots"] == 0
