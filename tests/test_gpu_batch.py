@@ -89,8 +89,10 @@ def rel(a, b):
     return np.abs(np.asarray(a) / np.asarray(b) - 1.0)
 
 
+# slots 0: the default (one table slot per workgroup, request parameters as
+# scalars); 2: two slots with per-lane parameters (FP32C at 768 threads)
 @pytest.mark.parametrize("prec,slots,nodes", [("fp64", 0, 0), ("fp64", 2, 1537), ("fp32c", 0, 0),
-                                               ("fp32c", 1, 0)])
+                                               ("fp32c", 2, 0)])
 def test_batch_equals_plain_bitwise(ctx, prec, slots, nodes):
     reqs = small_mix(21, 12, prec)
     say(f"batch {prec} of {len(reqs)} vs plain, slots {slots} nodes {nodes}, n_traj {sum(r.n_traj for r in reqs)}")
@@ -186,6 +188,27 @@ def test_sec4_variants_in_a_batch(ctx, O):
         e = rel(profs[i], O.solve(r)["n_over_nbar"]).max()
         print(f"request {i}: max rel {e:.2e}", flush=True)
         assert e <= 1e-9, i
+
+
+@pytest.mark.parametrize("slots", [0, 2])
+def test_sec4_variants_fp32c_in_a_batch(ctx, O, slots):
+    """The Sec. IV variants (power-law factors: the kernels' HIST variant) in the
+    FP32C form, one slot (the default, 1024 threads) and two (768): each
+    request equals the plain FP32C path bit for bit, and the oracle's reference
+    integration within 1e-4."""
+    reqs = [r.with_(precision="fp32c") for r in sec4_variants()]
+    say(f"batch fp32c of the Sec. IV variants, slots {slots}, n_traj {sum(r.n_traj for r in reqs)}")
+    with options(ctx, batch_slots=slots):
+        profs, stats, rc = run_batch(ctx, reqs)
+    assert rc == 0
+    for i, r in enumerate(reqs):
+        p, st = run_plain(ctx, r)
+        assert np.array_equal(p, profs[i]), (i, rel(p, profs[i]).max())
+        assert st["accepted_steps"] == stats[i]["accepted_steps"]
+        ref = O.solve(r.with_(precision="fp64", rtol=1e-10))["n_over_nbar"]
+        e = rel(profs[i], ref).max()
+        print(f"request {i}: max rel {e:.2e}", flush=True)
+        assert e <= 1e-4, i
 
 
 def test_batch_fp32c_vs_oracle(ctx, O):
