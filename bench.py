@@ -456,14 +456,114 @@ def fp32c_leg(ctx, stream, reqs, prof64=None, tuned=None):
     }
 
 
+def next_leg(ctx, stream):
+    """The rows beyond the headline path, timed on full-size requests of the
+    headline's shape (100 r x 200 y x 64 mu, rtol 1e-8, FP64), one profile at a
+    time on the whole device:
+      masses    - several relic masses from one integration (Sec. II.D), against
+                  plain solves at the same velocities (y scaled by m_k/m);
+      cull_exit - the App. B cull with the exact free-streaming exit, on and off,
+                  on the lightest halo of the headline's seeds (its outer radii
+                  lie beyond the compensation radius); the profiles must be the
+                  same bits;
+      variants  - the Sec. IV halo variants (growth xi^alpha, early onset, the
+                  G modulations kappa_1 and kappa_2) and observation at z0 > 0;
+      integrand - the profile plus the relic distribution behind it (Fig. 3),
+                  against the plain solve of the same request.
+    Their parity with the oracle is covered by the GPU tests at reduced sizes."""
+    import numpy as np
+    import torch
+    from paper_2410_08267_amd import workloads as W
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def rate(st):
+        att = st["accepted_steps"] + st["rejected_steps"]
+        tf = FLOP_PER_DP5_ATTEMPT * att / (st["kernel_ms"] / 1e3) / 1e12
+        return {"kernel_ms": st["kernel_ms"], "attempted_steps": att, "achieved_tflops": tf,
+                "frac": tf / FP64_VECTOR_PEAK_TFLOPS}
+
+    def one(req):
+        out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+        dt = timed(lambda: ctx.solve_async(req, out, stream=stream))
+        st, _ = ctx.last_stats()
+        return out.cpu().numpy(), st, dt
+
+    def rel(a, b):
+        return float(np.max(np.abs(np.asarray(a) / np.asarray(b) - 1.0)))
+
+    one(W.plain_scale(1000))
+    res = {}
+
+    req = W.plain_scale(0)
+    masses = [float(m) for m in np.geomspace(0.02, 0.3, 8)]
+    out = torch.empty(len(masses) * req.n_r, dtype=torch.float64, device="cuda")
+    ctx.solve_masses(req, masses, out, stream=stream)
+    ctx.last_stats()
+    dt_m = timed(lambda: ctx.solve_masses(req, masses, out, stream=stream))
+    st_m, _ = ctx.last_stats()
+    pm = out.cpu().numpy().reshape(len(masses), req.n_r)
+    dt_p, err = 0.0, 0.0
+    for i, mk in enumerate(masses):
+        p, _, dt = one(req.with_(m_eV=mk, y=req.y * (mk / req.m_eV)))
+        dt_p += dt
+        err = max(err, rel(pm[i], p))
+    res["masses"] = {"request": f"plain_scale seed 0 (m = {req.m_eV} eV), masses {masses[0]:.3g}-{masses[-1]:.3g} eV",
+                     "masses": len(masses), "seconds": dt_m, "profiles_per_s": len(masses) / dt_m,
+                     "plain_seconds": dt_p, "speedup_vs_plain": dt_p / dt_m,
+                     "max_rel_diff_vs_plain": err, **rate(st_m)}
+
+    seeds = {s: W.plain_scale(s) for s in range(16)}
+    s_light = min(seeds, key=lambda s: seeds[s].M0)
+    light = seeds[s_light]
+    p_on, st_on, dt_on = one(light)
+    ctx.set_option("free_exit", 0)
+    try:
+        p_off, st_off, dt_off = one(light)
+    finally:
+        ctx.set_option("free_exit", 1)
+    res["cull_exit"] = {"request": f"plain_scale seed {s_light} (M0 = {light.M0:.3g} Msun)",
+                        "seconds_on": dt_on, "seconds_off": dt_off, "speedup": dt_off / dt_on,
+                        "same_bits": bool(np.array_equal(p_on, p_off)),
+                        "free_exits": st_on["free_exits"],
+                        "attempted_steps_on": st_on["accepted_steps"] + st_on["rejected_steps"],
+                        "attempted_steps_off": st_off["accepted_steps"] + st_off["rejected_steps"]}
+
+    base = W.plain_scale(0).with_(mass_kind="paper", M0=1.0e14, conc_kind="constant", c0=7.0)
+    variants = {"paper_halo": base, "xi_alpha_0.5": base.with_(mass_alpha=0.5),
+                "xi_alpha_2": base.with_(mass_alpha=2.0), "early_onset_z9": base.with_(z_form=9.0),
+                "kappa_1": base.with_(kappa_kind="paper", kappa_a=0.2, kappa_b=1.5),
+                "kappa_2": base.with_(kappa_kind="paper", kappa_a=0.1, kappa_b=0.8),
+                "z_obs_0.5": base.with_(z_obs=0.5)}
+    res["variants"] = {"request": "plain_scale seed 0 grids, the paper's halo with M_h = 1e14 Msun, c = 7"}
+    for name, r in variants.items():
+        _, st, dt = one(r)
+        res["variants"][name] = {"seconds": dt, **rate(st)}
+
+    p, st_p, dt_p = one(req)
+    out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+    integ = torch.empty(req.n_r * req.n_y, dtype=torch.float64, device="cuda")
+    dt_i = timed(lambda: ctx.solve_integrand(req, out, integ, stream=stream))
+    st_i, _ = ctx.last_stats()
+    res["integrand"] = {"request": "plain_scale seed 0", "seconds": dt_i, "plain_seconds": dt_p,
+                        "same_profile_bits": bool(np.array_equal(out.cpu().numpy(), p)), **rate(st_i)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="plain,fp32c,batched,serving",
-                    help="comma list of legs: plain (the headline value), fp32c, batched, serving")
+    ap.add_argument("--legs", default="plain,fp32c,batched,serving,next",
+                    help="comma list of legs: plain (the headline value), fp32c, batched, serving, "
+                         "next (multi-mass reuse, cull, halo variants, integrand output)")
     ap.add_argument("--no-fp32c", dest="fp32c", action="store_false",
                     help="skip the FP32-compensated leg")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
@@ -557,6 +657,8 @@ def main():
         prof32, line["fp32c"] = fp32c_leg(ctx, stream, reqs, prof64, tuned)
     if args.batched:
         line["batched"] = batched_leg(ctx, args.batch_requests, tuned)
+    if "next" in legs:
+        line["next_rows"] = next_leg(ctx, stream)
     if args.serving and args.batched:
         serving = {}
         for pr in ("fp32c", "fp64"):

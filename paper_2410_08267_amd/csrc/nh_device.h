@@ -284,19 +284,93 @@ __device__ __forceinline__ void coef_interp2_split(const double *__restrict__ ld
     }
 }
 
+// Elementary functions of the power-law factors below, written for the
+// bounded arguments they take there (|x| of a few units).
+//
+// ln 2 as the Cody-Waite pair of fdlibm (high part exact in products with
+// small integers, and the remainder).
+constexpr double LN2_HI = 6.93147180369123816490e-01, LN2_LO = 1.90821492927058770002e-10;
+
+// x = k ln2 + r with k = rint(x / ln2), |r| <= ln2/2 (Cody-Waite reduction).
+__device__ __forceinline__ double reduce_ln2(double x, double &k)
+{
+    k = __builtin_rint(x * 1.4426950408889634);
+    return fma(-k, LN2_LO, fma(-k, LN2_HI, x));
+}
+
+// (e^r - 1)/r for |r| <= ln2/2 by its Taylor series to r^12 (the first
+// omitted term is below 2^-58 of the sum there), Horner in r.
+__device__ __forceinline__ double expm1_over_r(double r)
+{
+    double p = 1.0 / 6227020800.0;                                   // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    return fma(p, r, 1.0);
+}
+
+// e^x = 2^k e^r, an ulp or two.
+__device__ __forceinline__ double exp_small(double x)
+{
+    double k;
+    const double r = reduce_ln2(x, k);
+    return __builtin_amdgcn_ldexp(fma(r, expm1_over_r(r), 1.0), (int)k);
+}
+
+// e^x - 1 = 2^k (e^r - 1) + (2^k - 1): with k = 0 (|x| <= ln2/2) the series
+// value itself, so small results keep their relative accuracy.
+__device__ __forceinline__ double expm1_small(double x)
+{
+    double k;
+    const double r = reduce_ln2(x, k);
+    const double t = __builtin_amdgcn_ldexp(1.0, (int)k);
+    return fma(t, r * expm1_over_r(r), t - 1.0);
+}
+
+// ln x for x > 0: x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln x = e ln2 +
+// 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, the atanh series to s^21 as in
+// nfw_I.  An ulp or two.
+__device__ __forceinline__ double log_pos(double x)
+{
+    const int e = __builtin_amdgcn_frexp_exp(x * 1.4142135623730951) - 1;
+    const double m = __builtin_amdgcn_ldexp(x, -e);
+    const double s = (m - 1.0) * rcp64(m + 1.0);
+    const double s2 = s * s, z2 = s2 * s2;
+    double pe = fma(z2, 2.0 / 19.0, 2.0 / 15.0), po = fma(z2, 2.0 / 21.0, 2.0 / 17.0);
+    pe = fma(z2, pe, 2.0 / 11.0);
+    po = fma(z2, po, 2.0 / 13.0);
+    pe = fma(z2, pe, 2.0 / 7.0);
+    po = fma(z2, po, 2.0 / 9.0);
+    pe = fma(z2, pe, 2.0 / 3.0);
+    po = fma(z2, po, 2.0 / 5.0);
+    const double t3 = s * s2 * fma(s2, po, pe);                        // 2 (atanh(s) - s)
+    const double de = (double)e;
+    return fma(de, LN2_HI, fma(de, LN2_LO, fma(s, 2.0, t3)));
+}
+
 // The power-law factor of K and Kc at u (PowFactor): xi^alpha of the paper's
-// growth model and kappa = 1 + a [z/(1+z)]^b, from the library's FP64 exp,
-// expm1 and log (a few ulp); 0^alpha = 0 (alpha > 0 wherever it applies).
+// growth model and kappa = 1 + a [z/(1+z)]^b (Sec. IV.A, IV.B), from the
+// functions above (an ulp or two each; fewer instructions than the
+// library's routines); 0^alpha = 0 (alpha > 0 wherever it applies).  Not
+// inlined: in the trajectory loops its temporaries would spill.
 __device__ __noinline__ double pow_factor(const PowFactor &f, double u)
 {
     double s = 1.0;
     if (f.on_mass) {
-        const double xi = fmin(fmax((f.zf1 - exp(-u)) * f.inv_dz, 0.0), 1.0);
-        s = xi > 0.0 ? exp(f.alpha * log(xi)) : 0.0;
+        const double xi = fmin(fmax((f.zf1 - exp_small(-u)) * f.inv_dz, 0.0), 1.0);
+        s = xi > 0.0 ? exp_small(f.alpha * log_pos(xi)) : 0.0;
     }
     if (f.on_kappa) {
-        const double zr = -expm1(u);   // z / (1+z)
-        s *= 1.0 + (zr > 0.0 ? f.ka * exp(f.kb * log(zr)) : 0.0);
+        const double zr = -expm1_small(u);   // z / (1+z)
+        s *= 1.0 + (zr > 0.0 ? f.ka * exp_small(f.kb * log_pos(zr)) : 0.0);
     }
     return s;
 }
