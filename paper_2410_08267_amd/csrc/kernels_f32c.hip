@@ -54,9 +54,13 @@ __global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, Gr
         DpCtl ctl64;
         double h_fp64;
     };
-    const auto src = [&]() {
+    const auto opaque_zero = [&]() {
         int z = 0;
         if constexpr (WIDE) asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        return z;
+    };
+    const auto src = [&]() {
+        const int z = opaque_zero();
         const TrajParams &Pa = (&P)[z];
         const GridPtrs &ga = (&g)[z];
         Src r{{lds_mix, (const float *)(lds_mix + (size_t)Pa.n_tab * f32c_t64<true>), NC, Pa.n_tab, Pa.tab_u0,
@@ -74,25 +78,29 @@ __global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, Gr
         const bool need = (t == -1);
         const long long p = wave_claim(need, counter, wq);
         if (need) {
-            if (p < P.n_traj) {
-                t = traj_of(p, P);
-                const TrajIdx ix = traj_idx(t, P);
+            // WIDE: the claim reads the arguments in place too (see src)
+            const int zc = opaque_zero();
+            const TrajParams &Pc = (&P)[zc];
+            const GridPtrs &gc = (&g)[zc];
+            if (p < Pc.n_traj) {
+                t = traj_of(p, Pc);
+                const TrajIdx ix = traj_idx(t, Pc);
                 const int l = ix.l, j = ix.j, k = ix.k;
-                const double V = g.y[j] * P.vfac;
-                const double vx0 = V * g.mu[l], vy0 = V * g.smu[l];
+                const double V = gc.y[j] * Pc.vfac;
+                const double vx0 = V * gc.mu[l], vy0 = V * gc.smu[l];
                 v0n = sqrt(norm2(vx0, vy0));
-                if (CULL && never_enters(g.r[k], vx0, vy0, P.cull_D, cull_radius2(P.r_exit))) {
+                if (CULL && never_enters(gc.r[k], vx0, vy0, Pc.cull_D, cull_radius2(Pc.r_exit))) {
                     // App. B cull: the path never reaches R, the momentum is final
                     const TrajStat ts{0, 0, ST_OK | ST_FREE_EXIT, 0};
                     if constexpr (FUSED) {
-                        fused_finish(P, g, qa, lacc, bst, t, 1.0, ts);
+                        fused_finish(Pc, gc, qa, lacc, bst, t, 1.0, ts);
                     } else {
                         o.ratio[t] = 1.0;
                         o.stat[t] = ts;
                     }
                     t = -1;
                 } else {
-                    f32c_start(L, src().cf, g.r[k], vx0, vy0, P.h0, P.u_start, P.u_end);
+                    f32c_start(L, src().cf, gc.r[k], vx0, vy0, Pc.h0, Pc.u_start, Pc.u_end);
                 }
             } else {
                 t = -2;
@@ -109,7 +117,8 @@ __global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, Gr
                 const double ratio = sqrt(norm2(fx, fy)) / v0n;
                 const TrajStat ts{L.nacc, L.nrej, st, L.n64};
                 if constexpr (FUSED) {
-                    fused_finish(P, g, qa, lacc, bst, t, ratio, ts);
+                    const int zf = opaque_zero();
+                    fused_finish((&P)[zf], (&g)[zf], qa, lacc, bst, t, ratio, ts);
                 } else {
                     o.ratio[t] = ratio;
                     o.stat[t] = ts;
