@@ -45,10 +45,10 @@ TRAFFIC_BYTES_PER_LAUNCH = 2200335
 TRAFFIC_SOURCES = {
     "kernels_f64.hip": "e214d1ffa13fe116ab16acbe9eee6a3f1f5ddf236b14a8c85070702f8b68a01c",
     "nh_dp5.h": "f8703b33b3cbb420f2cf254cdc48ae63e2cab7bb151c0ae319bca1e780e8eb07",
-    "nh_device.h": "569d3dc210e7fa3ffb63b0cb896c86ff85c4cf3cd3229f0c4a68aa3091667246",
+    "nh_device.h": "bd5a84adbae45440719a1675cba78bf387164f8ede851c77e95b71ae0d5c08d0",
     "nh_internal.h": "7ae9c8a38332d355885dedcd99ead21490360a72aef49c868341dc134f74e86d",
     "nh_reduce.h": "4a7614c397af55b2edd74db041836b4390af4c5f8f53aab960413dbe1eede52e",
-    "../build.py": "a2f74296fa1f0cf61f1cac1b26c9c8152bfd7190acc99c5f531c13443aadf33d",
+    "../build.py": "460fa76e681efeee43268db77e28bb7db2f63ba999f4b207719e81dac423d265",
 }
 METRIC = ("trajectory-steps/s + n/n̄ profiles/s (FP32-comp vs FP64) at ≤1e-4 rel err; p50/p99")
 

@@ -498,6 +498,20 @@ const char *nh_version(void);
  * this is the ceiling the trajectory kernels are measured against as well. */
 int nh_fp64_fma_peak(nh_context *ctx, double *tflops);
 
+/* The device's own values of two elementary functions of the right-hand side,
+ * computed by the same inline code the trajectory kernels run, for tests of
+ * their accuracy against references of higher precision:
+ *   NH_FN_NFW_I       y = I(x) = ln(1+x) - x/(1+x), the NFW mass integral
+ *                     (Eq. nfw, App. A), x >= 0; req is ignored (may be NULL);
+ *   NH_FN_POW_FACTOR  y = the factor of K and Kc at u = x that req's tables
+ *                     leave out: xi^alpha of the paper's growth model times
+ *                     kappa = 1 + a [z/(1+z)]^b (Sec. IV.A, IV.B); 1 where req
+ *                     has neither.  Validates req.
+ * x, y: host, n doubles each (0 <= n <= 2^26).  Synchronous on the context's
+ * stream.  NH_EINVAL for an unknown fn, bad sizes or pointers. */
+enum { NH_FN_NFW_I = 1, NH_FN_POW_FACTOR = 2 };
+int nh_device_function(nh_context *ctx, int fn, const nh_request *req, long long n, const double *x, double *y);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ SOURCES = [
     "kernels_f32c.hip",
     "kernels_batch.hip",
     "noalloc.hip",
+    "device_fn.hip",
 ]
 
 ARCH = "gfx950"

@@ -394,6 +394,32 @@ int nh_fp64_fma_peak(nh_context *ctx, double *tflops)
     return NH_OK;
 }
 
+int nh_device_function(nh_context *ctx, int fn, const nh_request *req, long long n, const double *x, double *y)
+{
+    if (!ctx) return set_err(ctx, NH_EINVAL, "context is required");
+    if (fn != NH_FN_NFW_I && fn != NH_FN_POW_FACTOR) return set_err(ctx, NH_EINVAL, "unknown function %d", fn);
+    if (n < 0 || n > (1ll << 26) || (n > 0 && (!x || !y))) return set_err(ctx, NH_EINVAL, "bad n/x/y");
+    PowFactor pw{};
+    if (fn == NH_FN_POW_FACTOR) {
+        if (!req) return set_err(ctx, NH_EINVAL, "req is required for NH_FN_POW_FACTOR");
+        int rc = validate(req, ctx->err, sizeof(ctx->err));
+        if (rc != NH_OK) return rc;
+        pw = Physics(*req).pw;
+    }
+    if (n == 0) return NH_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc;
+    if ((rc = wait_pending(ctx)) != NH_OK) return rc;
+    const size_t bytes = (size_t)n * sizeof(double);
+    if ((rc = ensure_dev(ctx, ctx->out, 2 * bytes)) != NH_OK) return rc;
+    double *dx = (double *)ctx->out.p, *dy = dx + n;
+    HIPCHK(hipMemcpyAsync(dx, x, bytes, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(launch_device_fn(fn == NH_FN_NFW_I ? FN_NFW_I : FN_POW_FACTOR, pw, n, dx, dy, ctx->stream));
+    HIPCHK(hipMemcpyAsync(y, dy, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return NH_OK;
+}
+
 const char *nh_strerror(int code)
 {
     switch (code) {

@@ -46,7 +46,8 @@ __device__ __forceinline__ double sqrt_pos(double a) { return a * rsq64(a); }
 //   I = e ln2 + 2s - q/(1+q) + 2 (atanh(s) - s),
 // with atanh(s) - s = s^3/3 + s^5/5 + ... + s^21/21 (|s| <= 0.1716).  One
 // reciprocal serves both divisions: 1/((m+1)(1+q)).  Relative error a few ulp
-// (up to ~20 near q = 0.5, where ln(1+q) and q/(1+q) cancel); the two forms
+// (up to ~30 just above q = sqrt(2) - 1, where the reduction switches and
+// e ln2, 2s and q/(1+q) cancel to a twenty-fifth of their size); the two forms
 // differ only through selects, so a wavefront whose lanes straddle the switch
 // does not diverge.
 __device__ __forceinline__ double nfw_I(double q)

@@ -33,6 +33,9 @@ hipError_t launch_reduce_masses(const TrajParams &P, const GridPtrs &g, const do
                                 const double *wm, int n_mass, double *out, hipStream_t s);
 // FP64 FMA throughput probe: `blocks` workgroups of 1024 threads; *flop = work of one launch
 hipError_t launch_fma_probe(double *out, int blocks, hipStream_t s, double *flop);
+// y[i] = f(x[i]) on the device for f = nfw_I (FN_NFW_I) or pow_factor(pw, .) (FN_POW_FACTOR)
+enum { FN_NFW_I = 1, FN_POW_FACTOR = 2 };
+hipError_t launch_device_fn(int fn, const PowFactor &pw, long long n, const double *x, double *y, hipStream_t s);
 
 // slice kernels (batched and serving forms)
 // nc: table columns of the launch (NCOL when any request has a moving R);

@@ -133,6 +133,8 @@ _SIGNATURES = {
     "nh_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "nh_version": (ctypes.c_char_p, []),
     "nh_fp64_fma_peak": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "nh_device_function": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(nh_request), ctypes.c_longlong,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "nh_solve_integrand": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(nh_request), ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nh_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nh_request),
@@ -416,6 +418,18 @@ class Context:
         t = ctypes.c_double()
         self._check(self._lib.nh_fp64_fma_peak(self.h, ctypes.byref(t)))
         return t.value
+
+    def device_function(self, fn: str, x, req: Optional[Request] = None) -> np.ndarray:
+        """The device's own values of an elementary function of the right-hand side
+        (nh_device_function): fn "nfw_I" (x = q) or "pow_factor" (x = u, for req)."""
+        code = {"nfw_I": 1, "pow_factor": 2}[fn]
+        xs = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        ys = np.empty_like(xs)
+        m = marshal(req) if req is not None else None
+        rc = self._lib.nh_device_function(self.h, code, ctypes.byref(m.q) if m is not None else None, int(xs.size),
+                                          xs.ctypes.data_as(_dp), ys.ctypes.data_as(_dp))
+        self._check(rc)
+        return ys
 
     def autotune(self, reqs, form: str = "plain") -> dict:
         """Time the launch configurations of one form on a sample of requests and
