@@ -211,6 +211,13 @@ def serving_leg(ctx, capacity: float, prec: str, n_req: int, loads=(0.5, 0.9), w
             time.sleep(0.0005)
         m = lat[warm:]
         span = np.nanmax(done_t[warm:]) - arrivals[warm]
+        # where the tail comes from: latency by quartile of request size
+        # (trajectories), smallest first
+        size = np.array([r.n_traj for r in reqs[warm:]], dtype=np.float64)
+        quart = np.digitize(size, np.quantile(size, [0.25, 0.5, 0.75]))
+        by_size = [{"max_trajectories": int(size[quart == b].max()),
+                    "p50_ms": float(np.percentile(m[quart == b], 50) * 1e3),
+                    "p99_ms": float(np.percentile(m[quart == b], 99) * 1e3)} for b in range(4)]
         out[f"load_{frac:g}"] = {
             "offered_qps": qps,
             "requests": n_req,
@@ -218,6 +225,7 @@ def serving_leg(ctx, capacity: float, prec: str, n_req: int, loads=(0.5, 0.9), w
             "p99_ms": float(np.percentile(m, 99) * 1e3),
             "mean_ms": float(np.mean(m) * 1e3),
             "profiles_per_s": n_req / span,
+            "by_size_quartile": by_size,
         }
         print(f"[bench] serving {prec} at {frac:g} C: p50 {out[f'load_{frac:g}']['p50_ms']:.1f} ms "
               f"p99 {out[f'load_{frac:g}']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)

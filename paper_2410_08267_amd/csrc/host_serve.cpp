@@ -31,6 +31,7 @@ namespace nh {
 namespace {
 
 constexpr int SERVE_CAP = 1024;   // requests admitted at once (descriptor slots)
+constexpr int SERVE_SHARE_TPL = 16;   // POLICY_SHARE: trajectories per lane to justify one more workgroup
 constexpr size_t GRANULE = 256;
 
 size_t round_up(size_t x) { return (x + GRANULE - 1) & ~(GRANULE - 1); }
@@ -136,6 +137,7 @@ struct ServeState {
     BatchReq *d_desc = nullptr;
     unsigned long long *d_next = nullptr;
     unsigned int *d_inflight = nullptr;
+    int *d_helpers = nullptr;           // per request id: workgroups drawing from it (POLICY_SHARE)
     unsigned long long *d_stats = nullptr;
     int *d_order = nullptr, *d_list = nullptr, *d_rstart = nullptr;
     LaneSave *d_lanes = nullptr;
@@ -152,6 +154,7 @@ struct ServeState {
     int *h_order = nullptr, *h_list = nullptr, *h_rstart = nullptr;
     unsigned long long *h_next = nullptr, *h_stats = nullptr;
     unsigned int *h_inflight = nullptr;
+    int *h_zero = nullptr;              // SERVE_CAP zeros: the source that resets d_helpers
 };
 
 namespace {
@@ -171,6 +174,7 @@ int alloc_device_state(nh_context *ctx, ServeState &S)
     HIPCHK(hipMalloc((void **)&S.d_desc, SERVE_CAP * sizeof(BatchReq)));
     HIPCHK(hipMalloc((void **)&S.d_next, SERVE_CAP * sizeof(unsigned long long)));
     HIPCHK(hipMalloc((void **)&S.d_inflight, SERVE_CAP * sizeof(unsigned int)));
+    HIPCHK(hipMalloc((void **)&S.d_helpers, SERVE_CAP * sizeof(int)));
     HIPCHK(hipMalloc((void **)&S.d_stats, 8 * SERVE_CAP * sizeof(unsigned long long)));
     HIPCHK(hipMalloc((void **)&S.d_order, SERVE_CAP * sizeof(int)));
     HIPCHK(hipMalloc((void **)&S.d_list, SERVE_CAP * sizeof(int)));
@@ -182,6 +186,9 @@ int alloc_device_state(nh_context *ctx, ServeState &S)
     HIPCHK(hipHostMalloc((void **)&S.h_rstart, (SERVE_CAP + 1) * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&S.h_next, SERVE_CAP * sizeof(unsigned long long), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&S.h_inflight, SERVE_CAP * sizeof(unsigned int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&S.h_zero, SERVE_CAP * sizeof(int), hipHostMallocDefault));
+    std::memset(S.h_zero, 0, SERVE_CAP * sizeof(int));
+    HIPCHK(hipMemcpy(S.d_helpers, S.h_zero, SERVE_CAP * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipHostMalloc((void **)&S.h_stats, 8 * SERVE_CAP * sizeof(unsigned long long), hipHostMallocDefault));
     std::memset(S.h_desc, 0, SERVE_CAP * sizeof(BatchReq));
     for (int i = 0; i < SERVE_CAP; ++i) S.h_desc[i].retired = 1;   // unused slots are never claimed
@@ -302,6 +309,7 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
         S.h_next[t->slot] = 0;
         WCHK(hipMemcpyAsync(S.d_next + t->slot, S.h_next + t->slot, sizeof(unsigned long long),
                             hipMemcpyHostToDevice, s));
+        WCHK(hipMemcpyAsync(S.d_helpers + t->slot, S.h_zero + t->slot, sizeof(int), hipMemcpyHostToDevice, s));
     }
     int nc = NCOL - 1;
     bool pow = false;
@@ -316,8 +324,15 @@ bool run_slice(nh_context *ctx, ServeState &S, char (&fail)[256])
     A.inflight = S.d_inflight;
     A.order = S.d_order;
     A.n_order = (int)run.size();
-    A.policy = POLICY_UNOPENED_FIRST;
+    // Oldest first, each request spread over as many workgroups as its
+    // unclaimed work keeps busy for SERVE_SHARE_TPL trajectories per lane
+    // (a workgroup drains before it changes request, so fewer would be
+    // idle): under load a request no longer runs on the one workgroup that
+    // opened it while fresh requests keep arriving.
+    A.policy = POLICY_SHARE;
     A.cursor = nullptr;
+    A.helpers = S.d_helpers;
+    A.share = (long long)S.block * SERVE_SHARE_TPL;
     A.n_tab = S.n_tab;
     // Slice length: NH_OPT_SLICE_US, stretched up to 8x while the admitted
     // backlog would take more than four such slices to claim.  Every slice
@@ -511,12 +526,12 @@ void serve_shutdown(nh_context *ctx)
     if (S->worker.joinable()) S->worker.join();
     if (S->stream) (void)hipStreamSynchronize(S->stream);
     for (SliceGraph &G : S->graph) slice_graph_destroy(G);
-    for (void *p : {(void *)S->d_desc, (void *)S->d_next, (void *)S->d_inflight, (void *)S->d_stats,
+    for (void *p : {(void *)S->d_desc, (void *)S->d_next, (void *)S->d_inflight, (void *)S->d_helpers, (void *)S->d_stats,
                     (void *)S->d_order, (void *)S->d_list, (void *)S->d_rstart, (void *)S->d_lanes,
                     (void *)S->d_wg, (void *)S->arena_base})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)S->h_desc, (void *)S->h_desc_up, (void *)S->h_order, (void *)S->h_list, (void *)S->h_rstart,
-                    (void *)S->h_next, (void *)S->h_inflight, (void *)S->h_stats})
+                    (void *)S->h_next, (void *)S->h_inflight, (void *)S->h_zero, (void *)S->h_stats})
         if (p) (void)hipHostFree(p);
     if (S->ev0) (void)hipEventDestroy(S->ev0);
     if (S->ev1) (void)hipEventDestroy(S->ev1);

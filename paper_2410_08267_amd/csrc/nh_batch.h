@@ -57,6 +57,19 @@ __device__ __forceinline__ int pick_request(const SliceArgs &A)
             const int r = A.order[c];
             if (remaining_of(A, r) > 0) return r;
         }
+    } else if (A.policy == POLICY_SHARE) {
+        for (int b = 0; b < A.n_order; b += 64) {
+            const int i = b + lane;
+            bool ok = false;
+            if (i < A.n_order) {
+                const int r = A.order[i];
+                const long long rem = remaining_of(A, r);
+                const int h = max(__hip_atomic_load(&A.helpers[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), 0);
+                ok = rem > 0 && (h == 0 || rem >= (long long)(h + 1) * A.share);
+            }
+            const unsigned long long m = __ballot(ok);
+            if (m) return A.order[b + __ffsll((unsigned long long)m) - 1];
+        }
     } else {
         for (int b = 0; b < A.n_order; b += 64) {
             const int i = b + lane;
@@ -118,6 +131,7 @@ __device__ __forceinline__ void wave_acquire(WgSched &S, const SliceArgs &A, uns
     if ((r < 0 || dry) && !done) {
         const int other = SLOTS == 2 ? cur ^ 1 : cur;
         const int busy = __hip_atomic_load(&S.active[other], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int leaving = r;   // the request this workgroup has drawn from (or -1)
         r = -1;
         if (__shfl(busy, 0) == 0) {
             const int nr = pick_request(A);
@@ -125,6 +139,12 @@ __device__ __forceinline__ void wave_acquire(WgSched &S, const SliceArgs &A, uns
                 if (lane == 0) S.done = 1;
             } else {
                 if (__shfl(S.slot_req[other], 0) != nr) load(other, nr);
+                if (lane == 0 && A.helpers) {
+                    // this workgroup now draws from nr instead of the request it leaves
+                    if (leaving >= 0)
+                        __hip_atomic_fetch_add(&A.helpers[leaving], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&A.helpers[nr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
                 if (lane == 0) {
                     S.slot_req[other] = nr;
                     S.cur = other;

@@ -166,6 +166,10 @@ enum : int {
     POLICY_UNOPENED_FIRST = 1,  // the oldest request nobody has drawn from yet, else help the
                                 // one with the most work left (no cursor: the request list
                                 // changes between slices)
+    POLICY_SHARE = 2,           // the oldest request whose unclaimed work still gives every
+                                // workgroup drawing from it, one more included, `share`
+                                // trajectories (one nobody draws from: any work), else help
+                                // the one with the most work left
 };
 
 // One request as the slice kernels see it (device array).
@@ -200,6 +204,8 @@ struct SliceArgs {
     int n_order;
     int policy;               // POLICY_*
     unsigned long long *cursor;   // POLICY_OPEN_FIRST: next position of `order` to open
+    int *helpers;             // POLICY_SHARE: per request id, workgroups drawing from it (a hint)
+    long long share;          // POLICY_SHARE: unclaimed trajectories per workgroup to join
     int n_tab;                // table nodes of every request (slot capacity)
     long long budget_ticks;   // wall-clock ticks (100 MHz) until lanes save and exit; < 0: none
     LaneSave *lane_save;      // per thread of the grid, or null
