@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void k_rk4_f64(TrajParams P, GridPtrs g, TrajO
 // long trajectories run alone.  The autotuner picks per workload.
 constexpr int DP5_MAX_BLOCK = 1024;
 constexpr int DP5_DEFAULT_BLOCK = 768;
+constexpr int START_RADII = 256;   // radii whose start force a workgroup keeps in LDS
 
 // CULL: some start radius lies beyond R_exit.  Without one no relic can be
 // culled, and the kernel leaves the test out: its branch alone costs the
@@ -179,6 +180,13 @@ __global__ __launch_bounds__(DP5_MAX_BLOCK) void k_dp5_f64(TrajParams P, GridPtr
     const TabCoefSplit<HIST> cf{lds_tab, g.tabA, P.n_tab, P.tab_u0, P.tab_inv_du, P.R_const, P.pw, P.kn};
     __shared__ StartCache sc;
     start_cache_fill(sc, cf, P.h0, P.u_start, P.u_end);
+    __syncthreads();
+    // the first stage's force at the common start depends on the radius
+    // alone: once per radius here (the first START_RADII radii), instead of a
+    // right-hand side with one or two lanes active at every trajectory start
+    __shared__ double g0s[START_RADII];
+    const int n_g0 = min(P.n_r, START_RADII);
+    for (int k = threadIdx.x; k < n_g0; k += blockDim.x) g0s[k] = start_g(sc, g.r[k]);
     __syncthreads();
     DpCtl ctl;
     ctl.u_end = P.u_end;
@@ -214,7 +222,8 @@ __global__ __launch_bounds__(DP5_MAX_BLOCK) void k_dp5_f64(TrajParams P, GridPtr
                     }
                     t = -1;
                 } else {
-                    dp5_start_cached(L, sc, g.r[k], vx0, vy0, P.u_start);
+                    if (k < START_RADII) dp5_start_g(L, sc, g0s[k], g.r[k], vx0, vy0, P.u_start);
+                    else dp5_start_cached(L, sc, g.r[k], vx0, vy0, P.u_start);
                 }
             } else {
                 t = -2;

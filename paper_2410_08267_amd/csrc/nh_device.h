@@ -387,16 +387,21 @@ __device__ __noinline__ double pow_factor(const PowFactor &f, double u)
 // and r^3 >= R^3, where the enclosed perturbation is zero.  max(g, 0) thus
 // gives both cases without a compare (R is not needed).  At r = 0 the
 // reciprocal square root makes g NaN, and max(NaN, 0) = 0: no force there.
-__device__ __forceinline__ void rhs(const double c[NCOL], double R, double x, double y, double vx,
-                                    double vy, double &dx, double &dy, double &dvx, double &dvy)
+__device__ __forceinline__ double rhs_g(const double c[NCOL], double x, double y)
 {
-    (void)R;
     const double r2 = x * x + y * y;
     const double ri = rsq64(r2);
     const double r = r2 * ri;
     const double q = fmin(r * c[COL_INVS], c[COL_C]);
     const double I = nfw_I(q);
-    const double g = fmax(fma(c[COL_K] * I, ri * ri * ri, -c[COL_KC]), 0.0);
+    return fmax(fma(c[COL_K] * I, ri * ri * ri, -c[COL_KC]), 0.0);
+}
+
+__device__ __forceinline__ void rhs(const double c[NCOL], double R, double x, double y, double vx,
+                                    double vy, double &dx, double &dy, double &dvx, double &dvy)
+{
+    (void)R;
+    const double g = rhs_g(c, x, y);
     dx = c[COL_A] * vx;
     dy = c[COL_A] * vy;
     dvx = -g * x;

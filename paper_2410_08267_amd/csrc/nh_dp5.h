@@ -183,6 +183,38 @@ __device__ __forceinline__ void start_cache_fill(StartCache &sc, const CF &cf, d
     }
 }
 
+// The force term g of the first stage at the common start, x0 = (r, 0): it
+// depends on the radius alone (the same arithmetic as rhs).
+__device__ __forceinline__ double start_g(const StartCache &sc, double r)
+{
+    double c[NCOL];
+    for (int i = 0; i < NCOL; ++i) c[i] = sc.v[i];
+    return rhs_g(c, r, 0.0);
+}
+
+// Start a trajectory at x0 = (r, 0) from its radius's start force g0
+// (start_g): the first stage without evaluating the right-hand side, the
+// same bits as dp5_start_cached.
+__device__ __forceinline__ void dp5_start_g(Lane64 &L, const StartCache &sc, double g0, double x0, double vx0,
+                                            double vy0, double u_start)
+{
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    const double *v = sc.v + z;
+    L.x = x0;
+    L.y = 0.0;
+    L.vx = vx0;
+    L.vy = vy0;
+    L.u = u_start;
+    L.h = v[NCOL + 1];
+    L.nacc = L.nrej = L.natt = 0;
+    L.rej_prev = false;
+    L.k1x = v[COL_A] * vx0;
+    L.k1y = v[COL_A] * vy0;
+    L.k1u = -g0 * L.x;
+    L.k1v = -g0 * L.y;
+}
+
 __device__ __forceinline__ void dp5_start_cached(Lane64 &L, const StartCache &sc, double x0, double vx0,
                                                  double vy0, double u_start)
 {
