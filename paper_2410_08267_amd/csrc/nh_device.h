@@ -39,27 +39,27 @@ __device__ __forceinline__ double sqrt_pos(double a) { return a * rsq64(a); }
 // NFW mass integral I(q) = ln(1+q) - q/(1+q) (Eq. nfw), branch-free for q >= 0.
 // 1+q = m 2^e with e = round(log2(1+q)) (the exponent of (1+q) sqrt(2), so m
 // lies in [sqrt(1/2), sqrt(2)) up to rounding), ln(1+q) = e ln2 + 2 atanh(s),
-// s = (m-1)/(m+1).  m - 1 is corrected by the exact rounding error of 1+q, so
-// that s = q/(2+q) when e = 0.  Then q/(1+q) = 2s/(1+s) and
-//   I = 2 s^2/(1+s) + 2 (atanh(s) - s)                  (e = 0, all terms positive)
-// otherwise
-//   I = e ln2 + 2s - q/(1+q) + 2 (atanh(s) - s),
-// with atanh(s) - s = s^3/3 + s^5/5 + ... + s^19/19 (|s| <= 0.1716).  One
-// reciprocal serves both divisions: 1/((m+1)(1+q)).  Relative error a few ulp
-// (up to ~30 just above q = sqrt(2) - 1, where the reduction switches and
-// e ln2, 2s and q/(1+q) cancel to a twenty-fifth of their size); the two forms
-// differ only through selects, so a wavefront whose lanes straddle the switch
-// does not diverge.
+// s = (m-1)/(m+1) = N/D with N = q - (2^e - 1) (2^e - 1 is an exact integer,
+// so N is the correctly rounded value of 1 + q - 2^e, and s = q/(2+q) when
+// e = 0) and D = (1+q) + 2^e.  With 1/m = 2^e/(1+q), the identity
+//   2s - q/(1+q) = s^2 (1 + 1/m) + (1 - 2^e)/(1+q)
+// gives one form for every e:
+//   I = e ln2 + (1 - 2^e)/(1+q) + s^2 (1 + 1/m) + 2 (atanh(s) - s),
+// with atanh(s) - s = s^3/3 + s^5/5 + ... + s^19/19 (|s| <= 0.1716).  At e = 0
+// the first two terms are exactly zero and the others positive (relative error
+// a few ulp for any q); above, the error is a few ulp of the largest term (up
+// to ~30 ulp of I just above q = sqrt(2) - 1, where e ln2 and (1 - 2^e)/(1+q)
+// cancel to a twenty-fifth of their size).  One reciprocal serves both
+// divisions: 1/(D (1+q)).
 __device__ __forceinline__ double nfw_I(double q)
 {
     const double w0 = 1.0 + q;
     const int e = __builtin_amdgcn_frexp_exp(w0 * 1.4142135623730951) - 1;
-    const double m = __builtin_amdgcn_ldexp(w0, -e);
-    const double num = (m - 1.0) + __builtin_amdgcn_ldexp(q - (w0 - 1.0), -e);
-    const double den = m + 1.0;
-    const double rp = rcp64(den * w0);
-    const double s = num * (w0 * rp);                    // (m-1)/(m+1)
-    const double iw = den * rp;                          // 1/(1+q)
+    const double p2 = __builtin_amdgcn_ldexp(1.0, e);        // 2^e
+    const double N = q - (p2 - 1.0), D = w0 + p2;
+    const double rp = rcp64(D * w0);
+    const double s = N * (w0 * rp);                          // (m-1)/(m+1)
+    const double iw = D * rp;                                // 1/(1+q)
     const double s2 = s * s;
     // 2 s^-3 (atanh(s) - s) = sum_{k=0..8} 2 s2^k / (2k+3) (the next term adds
     // less than 1e-17 to I for |s| <= 0.1716), one Horner chain in s2: the
@@ -72,15 +72,12 @@ __device__ __forceinline__ double nfw_I(double q)
     p = fma(s2, p, 2.0 / 7.0);
     p = fma(s2, p, 2.0 / 5.0);
     p = fma(s2, p, 2.0 / 3.0);
-    const double t3 = s * s2 * p;                        // 2 (atanh(s) - s)
-    // e = 0: m = 1+q, so 2 s^2/(1+s) = s^2 (m+1)/m = s^2 (1 + 1/(1+q))
-    const double sm = fma(s2, iw, s2);
+    const double t3 = s * s2 * p;                            // 2 (atanh(s) - s)
+    const double small = fma(s2, fma(p2, iw, 1.0), t3);      // s^2 (1 + 1/m) + t3
     // ln 2 as the Cody-Waite pair of fdlibm's log: a high part whose products
     // with small integers are exact, and the remainder
     const double de = (double)e;
-    const double big = fma(de, 6.93147180369123816490e-01,
-                           fma(de, 1.90821492927058770002e-10, fma(-q, iw, s + s)));
-    return ((e == 0) ? sm : big) + t3;
+    return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, fma(-p2, iw, iw))) + small;
 }
 
 // |v|^2 with a fixed operation order (the final and initial speeds must round
@@ -95,7 +92,7 @@ __device__ __forceinline__ double norm2(double a, double b) { return fma(a, a, b
 // (nodes i..i+1) uses nodes i-1..i+2, the stencil shifted inward in the first
 // and last interval.
 struct Stencil4 {
-    int row;
+    int i1;   // the node at the interval's start: the rows are i1-1 .. i1+2
     double wa, wb, wc, wd;
 };
 
@@ -138,7 +135,7 @@ __device__ __forceinline__ Stencil4 stencil_at(int n_tab, double u0, double inv_
     const double s = fma(u, inv_du, -(u0 * inv_du));
     const int i = table_interval(n_tab, s);
     Stencil4 w;
-    w.row = i - 1;
+    w.i1 = i;
     stencil_weights(s - (double)i, w);
     return w;
 }
@@ -155,7 +152,7 @@ __device__ __forceinline__ Stencil4 stencil_at_knots(int n_tab, double u0, doubl
     const int hi = min(lo + kn.m - 3, n_tab - 4);
     const int row = min(max(i - 1, lo), hi);
     Stencil4 w;
-    w.row = row;
+    w.i1 = row + 1;
     stencil_weights(s - (double)(row + 1), w);
     return w;
 }
@@ -175,6 +172,14 @@ __device__ __forceinline__ const double *tab_row(const double *tab, int row, int
     return (const double *)((const char *)tab + __umul24((unsigned)row, (unsigned)stride * 8u));
 }
 
+// The first row of a stencil, addressed from its interval's node i1 and the
+// table base moved back one row (a constant offset), so that no i1 - 1 is
+// formed per lookup.
+__device__ __forceinline__ const double *stencil_rows(const double *tab, const Stencil4 &w, int stride)
+{
+    return tab_row(tab - stride, w.i1, stride);
+}
+
 // Column k of the interpolated coefficients from rows of `stride` doubles.
 // The sum runs node by node as one FMA chain, so that the five-node form
 // below reproduces it bit for bit.
@@ -191,7 +196,7 @@ __device__ __forceinline__ void coef_interp(const double *__restrict__ tab, int 
                                             double inv_du, const Knots &kn, double u, double c[NCOL])
 {
     const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
-    const double *row = tab_row(tab, w.row, STRIDE);
+    const double *row = stencil_rows(tab, w, STRIDE);
 #pragma unroll
     for (int k = 0; k < NC; ++k) c[k] = stencil_col(w, row, STRIDE, k);
 }
@@ -210,9 +215,9 @@ __device__ __forceinline__ void coef_interp2(const double *__restrict__ tab, int
 {
     const Stencil4 wQ = table_stencil<HIST>(n_tab, u0, inv_du, kn, uQ);
     const Stencil4 wP = table_stencil<HIST>(n_tab, u0, inv_du, kn, uP);
-    const double *row = tab_row(tab, wQ.row, STRIDE);
-    const double *row4 = tab_row(tab, min(wQ.row + 4, n_tab - 1), STRIDE);
-    const int d = wP.row - wQ.row;
+    const double *row = stencil_rows(tab, wQ, STRIDE);
+    const double *row4 = tab_row(tab, min(wQ.i1 + 3, n_tab - 1), STRIDE);
+    const int d = wP.i1 - wQ.i1;
     const bool s = d == 1;
     const double v0 = s ? 0.0 : wP.wa, v1 = s ? wP.wa : wP.wb, v2 = s ? wP.wb : wP.wc;
     const double v3 = s ? wP.wc : wP.wd, v4 = s ? wP.wd : 0.0;
@@ -223,7 +228,7 @@ __device__ __forceinline__ void coef_interp2(const double *__restrict__ tab, int
         cP[k] = fma(v4, row4[k], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
     }
     if ((unsigned)d > 1u) {
-        const double *rp = tab_row(tab, wP.row, STRIDE);
+        const double *rp = stencil_rows(tab, wP, STRIDE);
 #pragma unroll
         for (int k = 0; k < NC; ++k) cP[k] = stencil_col(wP, rp, STRIDE, k);
     }
@@ -245,8 +250,8 @@ __device__ __forceinline__ void coef_interp_split(const double *__restrict__ lds
                                                   double c[NCOL])
 {
     const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
-    c[COL_A] = stencil_a(w, a + (unsigned)w.row);
-    const double *row = tab_row(lds, w.row, STRIDE);
+    c[COL_A] = stencil_a(w, (a - 1) + (unsigned)w.i1);
+    const double *row = stencil_rows(lds, w, STRIDE);
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[COL_K + k] = stencil_col(w, row, STRIDE, k);
 }
@@ -258,11 +263,11 @@ __device__ __forceinline__ void coef_interp2_split(const double *__restrict__ ld
 {
     const Stencil4 wQ = table_stencil<HIST>(n_tab, u0, inv_du, kn, uQ);
     const Stencil4 wP = table_stencil<HIST>(n_tab, u0, inv_du, kn, uP);
-    const int row4i = min(wQ.row + 4, n_tab - 1);
-    const double *row = tab_row(lds, wQ.row, STRIDE);
+    const int row4i = min(wQ.i1 + 3, n_tab - 1);
+    const double *row = stencil_rows(lds, wQ, STRIDE);
     const double *row4 = tab_row(lds, row4i, STRIDE);
-    const double *aq = a + (unsigned)wQ.row;
-    const int d = wP.row - wQ.row;
+    const double *aq = (a - 1) + (unsigned)wQ.i1;
+    const int d = wP.i1 - wQ.i1;
     const bool s = d == 1;
     const double v0 = s ? 0.0 : wP.wa, v1 = s ? wP.wa : wP.wb, v2 = s ? wP.wb : wP.wc;
     const double v3 = s ? wP.wc : wP.wd, v4 = s ? wP.wd : 0.0;
@@ -278,8 +283,8 @@ __device__ __forceinline__ void coef_interp2_split(const double *__restrict__ ld
         cP[COL_K + k] = fma(v4, row4[k], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
     }
     if ((unsigned)d > 1u) {
-        cP[COL_A] = stencil_a(wP, a + (unsigned)wP.row);
-        const double *rp = tab_row(lds, wP.row, STRIDE);
+        cP[COL_A] = stencil_a(wP, (a - 1) + (unsigned)wP.i1);
+        const double *rp = stencil_rows(lds, wP, STRIDE);
 #pragma unroll
         for (int k = 0; k < 4; ++k) cP[COL_K + k] = stencil_col(wP, rp, STRIDE, k);
     }

@@ -97,10 +97,10 @@ struct TabCoef32 {
         constexpr int N32 = NC - F32C_T64;
         constexpr int T64 = f32c_t64<SPLIT>;
         const Stencil4 w = table_stencil<HIST>(n_tab, u0, inv_du, kn, u);
-        const double *r64 = tab_row(t64, w.row, T64);
+        const double *r64 = stencil_rows(t64, w, T64);
         double A, K, Kc;
         if constexpr (SPLIT) {
-            A = stencil_a(w, a + (unsigned)w.row);
+            A = stencil_a(w, (a - 1) + (unsigned)w.i1);
             K = stencil_col(w, r64, T64, 0);
             Kc = stencil_col(w, r64, T64, 1);
         } else {
@@ -117,7 +117,7 @@ struct TabCoef32 {
         c[COL_K] = (float)K;
         c[COL_KC] = (float)Kc;
         const float wa = (float)w.wa, wb = (float)w.wb, wc = (float)w.wc, wd = (float)w.wd;
-        const float *r32 = t32 + __umul24((unsigned)w.row, (unsigned)N32);
+        const float *r32 = (t32 - N32) + __umul24((unsigned)w.i1, (unsigned)N32);
 #pragma unroll
         for (int k = 0; k < N32; ++k)
             c[F32C_T64 + k] = fmaf(wd, r32[3 * N32 + k], fmaf(wc, r32[2 * N32 + k], fmaf(wb, r32[N32 + k], wa * r32[k])));
@@ -138,19 +138,19 @@ struct TabCoef32 {
         constexpr int T64 = f32c_t64<SPLIT>;
         const Stencil4 wQ = table_stencil<HIST>(n_tab, u0, inv_du, kn, uQ);
         const Stencil4 wP = table_stencil<HIST>(n_tab, u0, inv_du, kn, uP);
-        const int d = wP.row - wQ.row;
+        const int d = wP.i1 - wQ.i1;
         const bool sh = d == 1;
         const double v0 = sh ? 0.0 : wP.wa, v1 = sh ? wP.wa : wP.wb, v2 = sh ? wP.wb : wP.wc;
         const double v3 = sh ? wP.wc : wP.wd, v4 = sh ? wP.wd : 0.0;
-        const int row4i = min(wQ.row + 4, n_tab - 1);
+        const int row4i = min(wQ.i1 + 3, n_tab - 1);
         double q64[F32C_T64], p64[F32C_T64];   // A, K, Kc
         {
-            const double *aq = a + (unsigned)wQ.row;
+            const double *aq = (a - 1) + (unsigned)wQ.i1;
             const double r0 = aq[0], r1 = aq[1], r2 = aq[2], r3 = aq[3];
             q64[0] = fma(wQ.wd, r3, fma(wQ.wc, r2, fma(wQ.wb, r1, wQ.wa * r0)));
             p64[0] = fma(v4, a[(unsigned)row4i], fma(v3, r3, fma(v2, r2, fma(v1, r1, v0 * r0))));
         }
-        const double *row = tab_row(t64, wQ.row, T64);
+        const double *row = stencil_rows(t64, wQ, T64);
         const double *row4 = tab_row(t64, row4i, T64);
 #pragma unroll
         for (int k = 0; k < T64; ++k) {
@@ -160,7 +160,7 @@ struct TabCoef32 {
         }
         const float qa = (float)wQ.wa, qb = (float)wQ.wb, qc = (float)wQ.wc, qd = (float)wQ.wd;
         const float f0 = (float)v0, f1 = (float)v1, f2 = (float)v2, f3 = (float)v3, f4 = (float)v4;
-        const float *r32 = t32 + __umul24((unsigned)wQ.row, (unsigned)N32);
+        const float *r32 = (t32 - N32) + __umul24((unsigned)wQ.i1, (unsigned)N32);
         const float *r32e = t32 + __umul24((unsigned)row4i, (unsigned)N32);
 #pragma unroll
         for (int k = 0; k < N32; ++k) {
@@ -169,12 +169,12 @@ struct TabCoef32 {
             cP[F32C_T64 + k] = fmaf(f4, r32e[k], fmaf(f3, r3, fmaf(f2, r2, fmaf(f1, r1, f0 * r0))));
         }
         if ((unsigned)d > 1u) {
-            p64[0] = stencil_a(wP, a + (unsigned)wP.row);
-            const double *rp = tab_row(t64, wP.row, T64);
+            p64[0] = stencil_a(wP, (a - 1) + (unsigned)wP.i1);
+            const double *rp = stencil_rows(t64, wP, T64);
 #pragma unroll
             for (int k = 0; k < T64; ++k) p64[1 + k] = stencil_col(wP, rp, T64, k);
             const float pa = (float)wP.wa, pb = (float)wP.wb, pc = (float)wP.wc, pd = (float)wP.wd;
-            const float *rp32 = t32 + __umul24((unsigned)wP.row, (unsigned)N32);
+            const float *rp32 = (t32 - N32) + __umul24((unsigned)wP.i1, (unsigned)N32);
 #pragma unroll
             for (int k = 0; k < N32; ++k)
                 cP[F32C_T64 + k] =

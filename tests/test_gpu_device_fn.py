@@ -2,15 +2,16 @@
 ABI (nh_device_function), against 50-digit references (mpmath):
 
   * the NFW mass integral I(q) = ln(1+q) - q/(1+q) (Eq. nfw, App. A), over q
-    from 1e-10 to 1e4: the kernels' branch-free form sums e ln2, 2s,
-    -q/(1+q) and 2(atanh s - s) with 1+q = m 2^e, s = (m-1)/(m+1), so its error
-    is a few ulp of the largest of those terms, not of I: the bound is 12 ulp
-    of the sum of their magnitudes (s carries up to ~3 ulp from the reciprocal
-    of (m+1)(1+q) and two products, and the form below squares it; where the
-    terms cancel, just above q = sqrt(2) - 1, I is a twenty-fifth of their sum
-    and the relative error reaches ~40 ulp); below q = sqrt(2) - 1 the form
-    2 s^2/(1+s) + 2 (atanh s - s) has only positive terms and the bound is 12
-    ulp of I itself.  The median error is within 4 ulp of I;
+    from 1e-10 to 1e4: the kernels' branch-free form sums e ln2,
+    (1 - 2^e)/(1+q), s^2 (1 + 1/m) and 2(atanh s - s) with 1+q = m 2^e,
+    s = (m-1)/(m+1), so its error is a few ulp of the largest of those terms,
+    not of I: the bound is 12 ulp of the sum of their magnitudes (s carries up
+    to ~3 ulp from the reciprocal of (m+1)(1+q) and two products, and s^2
+    doubles it; where the terms cancel, just above q = sqrt(2) - 1, I is a
+    twenty-fifth of their sum and the relative error reaches ~30 ulp); below
+    q = sqrt(2) - 1 (e = 0) the first two terms are exactly zero, the others
+    positive, and the bound is 12 ulp of I itself.  The median error is within
+    4 ulp of I;
   * the power-law factor of K and Kc (Sec. IV.A, IV.B): xi^alpha of the paper's
     growth model and kappa = 1 + a [z/(1+z)]^b, from the kernels' own exp, expm1
     and log.  Bound per point: 8 ulp, plus for xi^alpha the error that 4 ulp of
@@ -54,10 +55,12 @@ def test_nfw_integral_on_the_device(ctx):
     ref = np.array([float(mp.log1p(mp.mpf(x)) - mp.mpf(x) / (1 + mp.mpf(x))) for x in q])
     e = np.frexp((1.0 + q) * math.sqrt(2.0))[1] - 1.0
     m = (1.0 + q) / 2.0 ** e
-    # e = 0: the form 2 s^2/(1+s) + 2 (atanh s - s), every term positive and
-    # their sum I; otherwise e ln2 + 2s - q/(1+q) + 2 (atanh s - s)
-    terms = np.where(e == 0.0, ref, np.abs(e) * math.log(2.0) + 2.0 * np.abs((m - 1.0) / (m + 1.0))
-                     + q / (1.0 + q) + ref)
+    # the magnitudes of e ln2, (1 - 2^e)/(1+q), s^2 (1 + 1/m) and
+    # 2 (atanh s - s); at e = 0 the first two vanish and the others sum to I
+    s = (m - 1.0) / (m + 1.0)
+    t3 = np.abs(2.0 * (np.arctanh(s) - s))
+    terms = np.where(e == 0.0, ref, e * math.log(2.0) + (2.0 ** e - 1.0) / (1.0 + q)
+                     + s * s * (1.0 + 1.0 / m) + t3)
     err = np.abs(got / ref - 1.0) / EPS
     over = np.abs(got - ref) / (12.0 * EPS * terms)
     print(f"ulp max {err.max():.1f} median {np.median(err):.2f} at q = {q[np.argmax(err)]:.3g}; "
