@@ -334,6 +334,7 @@ QuadAcc quad_acc(void *base, int n_r, unsigned long long *stats)
     qa.scale = (double *)(qa.den + 2);
     qa.stats = stats;
     qa.lds_n = 0;   // set per launch by the trajectory kernels' launchers
+    qa.ring = 0;    // likewise
     return qa;
 }
 

@@ -156,6 +156,8 @@ struct QuadAcc {
     double *scale;
     unsigned long long *stats;
     int lds_n;    // radii 0 .. lds_n-1 summed per workgroup in LDS first (0: straight to num)
+    int ring;     // FP64 trajectory kernel: finished trajectories wait in per-wavefront LDS
+                  // rings and are summed 64 at a time (0: each when it finishes)
 };
 
 // ---- batched and serving forms (scheduling: nh_batch.h) ----

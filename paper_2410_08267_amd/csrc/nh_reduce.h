@@ -239,14 +239,12 @@ __device__ __forceinline__ void quad_lds_flush(const QuadAcc &q, const unsigned 
     }
 }
 
-// A finished trajectory t: its quadrature term into radius k's sum (the
-// workgroup's LDS partial when there is one), its statistics into the
-// workgroup's.
-__device__ __forceinline__ void fused_finish(const TrajParams &P, const GridPtrs &g, const QuadAcc &q,
-                                             unsigned long long *lacc, BlockStats &b, long long t, double ratio,
-                                             const TrajStat &ts)
+// A finished trajectory (radius k, momentum j, angle l): its quadrature term
+// into radius k's sum (the workgroup's LDS partial when there is one), its
+// statistics into the workgroup's.
+__device__ __forceinline__ void fused_finish_ix(const GridPtrs &g, const QuadAcc &q, unsigned long long *lacc,
+                                                BlockStats &b, const TrajIdx &ix, double ratio, const TrajStat &ts)
 {
-    const TrajIdx ix = traj_idx(t, P);
     const int l = ix.l, j = ix.j, k = ix.k;
     const Fix128 v = to_fix(quad_term(g, j, l, ratio, *q.scale));
     if (k < q.lds_n) fix_lds_add(lacc + 2 * k, v);
@@ -258,6 +256,14 @@ __device__ __forceinline__ void fused_finish(const TrajParams &P, const GridPtrs
     if ((ts.status & 0xff) != ST_OK) __hip_atomic_fetch_add(&b.fail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (ts.fp64) __hip_atomic_fetch_add(&b.f64, (unsigned long long)(unsigned)ts.fp64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (ts.status & ST_FREE_EXIT) __hip_atomic_fetch_add(&b.fre, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The same for trajectory t = (k n_y + j) n_mu + l.
+__device__ __forceinline__ void fused_finish(const TrajParams &P, const GridPtrs &g, const QuadAcc &q,
+                                             unsigned long long *lacc, BlockStats &b, long long t, double ratio,
+                                             const TrajStat &ts)
+{
+    fused_finish_ix(g, q, lacc, b, traj_idx(t, P), ratio, ts);
 }
 
 // After the workgroup's last trajectory (all threads, after a barrier).
