@@ -333,6 +333,29 @@ def test_queue_order_does_not_change_results(ctx, block):
         ctx.set_option("block_threads", 0)
 
 
+@pytest.mark.parametrize("block", [512, 1024])
+def test_fused_quadrature_from_finish_rings(ctx, block):
+    """The fused quadrature (finished trajectories wait in per-wavefront LDS
+    rings of 64 and are summed a ring at a time) against the reduction of
+    stored ratios: the same bits and the same step statistics.  100650
+    trajectories on 8 or 16 wavefronts a workgroup: many full rings, and a
+    partial one per wavefront at the end."""
+    req = W.shrink(W.plain_scale(4), 25, 66, 61)
+    say(f"fused vs stored ratios, block {block}, n_traj={req.n_traj}")
+    ctx.set_option("block_threads", block)
+    try:
+        prof, _, st = gpu_ratios(ctx, req)
+        out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+        ctx.solve_async(req, out)
+        fst, _ = ctx.last_stats()
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option("block_threads", 0)
+    assert np.array_equal(out.cpu().numpy(), prof)
+    for key in ("accepted_steps", "rejected_steps", "n_failed", "free_exits", "max_steps_one_traj"):
+        assert fst[key] == st[key], key
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_workgroup_cap_does_not_change_results(ctx, prec):
     """Capping a launch's workgroups (so that solves on several streams run side
