@@ -31,9 +31,13 @@ __global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, Gr
 {
     extern __shared__ double lds_mix[];
     __shared__ BlockStats bst;
-    // the workgroup's partial sums follow the table
+    // the wavefronts' rings of finished trajectories (when on) and the
+    // workgroup's partial sums follow the table
+    char *const ring_base = (char *)lds_mix + quad_lds_offset(f32c_table_bytes<NC, true>(P.n_tab));
     unsigned long long *const lacc =
-        (unsigned long long *)((char *)lds_mix + quad_lds_offset(f32c_table_bytes<NC, true>(P.n_tab)));
+        (unsigned long long *)(ring_base + (FUSED && qa.ring ? blockDim.x * FinishRing<true>::ENTRY : 0));
+    const FinishRing<true> R = FinishRing<true>::of(ring_base);
+    const bool ring = FUSED && qa.ring;
     if constexpr (FUSED) {
         block_stats_init(bst);
         quad_lds_init(lacc, qa.lds_n);
@@ -74,6 +78,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, Gr
     double v0n = 1.0;
     Lane32 L{};
     WaveQueue wq{0ull, 0ull};
+    unsigned nfin = 0;   // records in the wavefront's ring
     for (;;) {
         const bool need = (t == -1);
         const long long p = wave_claim(need, counter, wq);
@@ -88,7 +93,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, Gr
                 const int l = ix.l, j = ix.j, k = ix.k;
                 const double V = gc.y[j] * Pc.vfac;
                 const double vx0 = V * gc.mu[l], vy0 = V * gc.smu[l];
-                v0n = sqrt(norm2(vx0, vy0));
+                if (!ring) v0n = sqrt(norm2(vx0, vy0));
                 if (CULL && never_enters(gc.r[k], vx0, vy0, Pc.cull_D, cull_radius2(Pc.r_exit))) {
                     // App. B cull: the path never reaches R, the momentum is final
                     const TrajStat ts{0, 0, ST_OK | ST_FREE_EXIT, 0};
@@ -109,10 +114,11 @@ __global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, Gr
         // leave once every lane found the queue drained; lanes whose new
         // trajectory was culled (t == -1) claim again on the next pass
         if (__ballot(t != -2) == 0ull) break;
+        int st = -1;
         if (t >= 0) {
             const Src a = src();
-            const int st = f32c_attempt(L, a.cf, a.cf64, a.ctl, a.ctl64, a.h_fp64);
-            if (st >= 0) {
+            st = f32c_attempt(L, a.cf, a.cf64, a.ctl, a.ctl64, a.h_fp64);
+            if (st >= 0 && !ring) {
                 const double fx = L.vx, fy = L.vy;
                 const double ratio = sqrt(norm2(fx, fy)) / v0n;
                 const TrajStat ts{L.nacc, L.nrej, st, L.n64};
@@ -126,8 +132,15 @@ __global__ __launch_bounds__(WIDE ? 1024 : 768) void k_dp5_f32c(TrajParams P, Gr
                 t = -1;
             }
         }
+        if (ring) {
+            const int zf = opaque_zero();
+            if (R.put(t >= 0 && st >= 0, nfin, t, st, L.nacc, L.nrej, L.n64, norm2((double)L.vx, (double)L.vy),
+                      (&P)[zf], (&g)[zf], qa, lacc, bst))
+                t = -1;
+        }
     }
     if constexpr (FUSED) {
+        if (ring && nfin) R.flush(nfin, P, g, qa, lacc, bst);
         __syncthreads();
         block_stats_flush(bst, qa.stats);
         quad_lds_flush(qa, lacc);
@@ -144,7 +157,19 @@ static hipError_t launch_f32c_w(const TrajParams &P, const GridPtrs &g, const Tr
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     QuadAcc q = qa;
+    q.ring = 0;
     if (FUSED) {
+        // the wavefronts' rings of finished trajectories, when they keep the occupancy
+        const size_t with = quad_lds_offset(lds) + (size_t)B * FinishRing<true>::ENTRY;
+        int per_cu2 = 0;
+        if (with <= QUAD_LDS_LIMIT && P.n_traj < (1ll << 48)) {
+            e = occupancy_cached((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED, WIDE>, B, with, &per_cu2);
+            if (e != hipSuccess) return e;
+            if (per_cu2 == per_cu) {
+                q.ring = 1;
+                lds = with;
+            }
+        }
         e = quad_lds_plan((const void *)k_dp5_f32c<NC, CULL, HIST, FUSED, WIDE>, B, per_cu, P.n_r, lds, q);
         if (e != hipSuccess) return e;
     }

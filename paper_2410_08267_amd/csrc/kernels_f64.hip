@@ -150,45 +150,6 @@ constexpr int DP5_MAX_BLOCK = 1024;
 constexpr int DP5_DEFAULT_BLOCK = 768;
 constexpr int START_RADII = 256;   // radii whose start force a workgroup keeps in LDS
 
-// Finished trajectories of a fused launch wait in their wavefront's ring in
-// LDS, 64 records of RING_ENTRY bytes in three arrays: the final speed
-// squared, the trajectory index with the status word from bit 48, and the
-// accepted and rejected step counts.  When the next finishers would overflow
-// it, the whole wavefront sums the ring at once, one record a lane (the
-// quadrature term, the fixed-point add and the statistics), instead of running
-// that code with the one or two lanes that finish in a pass.  The sums are
-// exact, so the order changes no result.
-constexpr int RING_ENTRY = 24;
-constexpr int RING_SLOTS = 64;
-struct Ring {
-    double *n2;
-    long long *tw;
-    uint2 *st;
-};
-
-__device__ __forceinline__ Ring ring_of(char *base)
-{
-    char *b = base + (threadIdx.x >> 6) * (RING_SLOTS * RING_ENTRY);
-    return Ring{(double *)b, (long long *)(b + RING_SLOTS * 8), (uint2 *)(b + RING_SLOTS * 16)};
-}
-
-// Record i < n of the ring, for lane i: its speed ratio (the same arithmetic
-// as at the trajectory's start and end) and its quadrature term.
-__device__ __forceinline__ void ring_flush(const Ring &R, unsigned n, const TrajParams &P, const GridPtrs &g,
-                                           const QuadAcc &qa, unsigned long long *lacc, BlockStats &bst)
-{
-    const unsigned i = __lane_id();
-    if (i < n) {
-        const long long tw = R.tw[i];
-        const uint2 c = R.st[i];
-        const TrajIdx ix = traj_idx(tw & ((1ll << 48) - 1), P);
-        const double V = g.y[ix.j] * P.vfac;
-        const double v0n = sqrt(norm2(V * g.mu[ix.l], V * g.smu[ix.l]));
-        const double ratio = sqrt(R.n2[i]) / v0n;
-        fused_finish_ix(g, qa, lacc, bst, ix, ratio, TrajStat{(int)c.x, (int)c.y, (int)(tw >> 48), 0});
-    }
-}
-
 // CULL: some start radius lies beyond R_exit.  Without one no relic can be
 // culled, and the kernel leaves the test out: its branch alone costs the
 // trajectory loop a few percent in register moves.
@@ -205,8 +166,8 @@ __global__ __launch_bounds__(DP5_MAX_BLOCK) void k_dp5_f64(TrajParams P, GridPtr
     // the wavefronts' rings (when on) and the workgroup's partial sums follow the table
     char *const ring_base = (char *)lds_tab + quad_lds_offset((size_t)P.n_tab * SPLIT_ROW * sizeof(double));
     unsigned long long *const lacc =
-        (unsigned long long *)(ring_base + (FUSED && qa.ring ? blockDim.x * RING_ENTRY : 0));
-    const Ring R = ring_of(ring_base);
+        (unsigned long long *)(ring_base + (FUSED && qa.ring ? blockDim.x * FinishRing<false>::ENTRY : 0));
+    const FinishRing<false> R = FinishRing<false>::of(ring_base);
     const bool ring = FUSED && qa.ring;
     if constexpr (FUSED) {
         block_stats_init(bst);
@@ -290,29 +251,11 @@ __global__ __launch_bounds__(DP5_MAX_BLOCK) void k_dp5_f64(TrajParams P, GridPtr
                 t = -1;
             }
         }
-        if (ring) {
-            const bool fin = t >= 0 && st >= 0;
-            const unsigned long long fm = __ballot(fin);
-            if (fm) {
-                const unsigned nf = (unsigned)__popcll(fm);
-                if (nfin + nf > (unsigned)RING_SLOTS) {
-                    ring_flush(R, nfin, P, g, qa, lacc, bst);
-                    nfin = 0;
-                }
-                if (fin) {
-                    const unsigned slot =
-                        nfin + __builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
-                    R.n2[slot] = norm2(L.vx, L.vy);
-                    R.tw[slot] = t | ((long long)st << 48);
-                    R.st[slot] = make_uint2((unsigned)L.nacc, (unsigned)L.nrej);
-                    t = -1;
-                }
-                nfin += nf;
-            }
-        }
+        if (ring && R.put(t >= 0 && st >= 0, nfin, t, st, L.nacc, L.nrej, 0, norm2(L.vx, L.vy), P, g, qa, lacc, bst))
+            t = -1;
     }
     if constexpr (FUSED) {
-        if (ring && nfin) ring_flush(R, nfin, P, g, qa, lacc, bst);
+        if (ring && nfin) R.flush(nfin, P, g, qa, lacc, bst);
         __syncthreads();
         block_stats_flush(bst, qa.stats);
         quad_lds_flush(qa, lacc);
@@ -510,7 +453,7 @@ static hipError_t launch_dp5_k(const TrajParams &P, const GridPtrs &g, const Tra
     if (FUSED) {
         // the wavefronts' rings of finished trajectories, when they keep the occupancy
         // (trajectory indices below 2^48: the status word shares their record)
-        const size_t with = quad_lds_offset(lds) + (size_t)B * RING_ENTRY;
+        const size_t with = quad_lds_offset(lds) + (size_t)B * FinishRing<false>::ENTRY;
         int per_cu2 = 0;
         if (with <= QUAD_LDS_LIMIT && P.n_traj < (1ll << 48)) {
             e = occupancy_cached((const void *)k_dp5_f64<CULL, HIST, FUSED>, B, with, &per_cu2);

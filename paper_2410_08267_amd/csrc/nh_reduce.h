@@ -266,6 +266,78 @@ __device__ __forceinline__ void fused_finish(const TrajParams &P, const GridPtrs
     fused_finish_ix(g, q, lacc, b, traj_idx(t, P), ratio, ts);
 }
 
+// Finished trajectories of a fused launch wait in their wavefront's ring in
+// LDS: 64 records in parallel arrays, the final speed squared, the trajectory
+// index with the status word from bit 48, the accepted and rejected step
+// counts and (N64, the FP32C form) the FP64 attempt count.  When the next
+// finishers would overflow it, the whole wavefront sums the ring at once, one
+// record a lane (the speed ratio, the quadrature term, the fixed-point add and
+// the statistics), instead of running that code with the one or two lanes
+// that finish in a pass.  The sums are exact, so the order changes no result.
+// A launch of 2^48 or more trajectories sums each finisher at once.
+template <bool N64>
+struct FinishRing {
+    static constexpr int SLOTS = 64;
+    static constexpr int ENTRY = N64 ? 28 : 24;   // bytes a record
+    double *n2;
+    long long *tw;
+    uint2 *st;
+    unsigned *n64;
+
+    __device__ __forceinline__ static FinishRing of(char *base)
+    {
+        char *b = base + (threadIdx.x >> 6) * (SLOTS * ENTRY);
+        return FinishRing{(double *)b, (long long *)(b + SLOTS * 8), (uint2 *)(b + SLOTS * 16),
+                          (unsigned *)(b + SLOTS * 24)};
+    }
+
+    // Records i < n, record i by lane i.  The speed ratio repeats the
+    // arithmetic of the trajectory's start (the initial speed from the grid)
+    // and of its end, so it is the value an immediate finish would compute.
+    __device__ __forceinline__ void flush(unsigned n, const TrajParams &P, const GridPtrs &g, const QuadAcc &qa,
+                                          unsigned long long *lacc, BlockStats &bst) const
+    {
+        const unsigned i = __lane_id();
+        if (i < n) {
+            const long long w = tw[i];
+            const uint2 c = st[i];
+            const TrajIdx ix = traj_idx(w & ((1ll << 48) - 1), P);
+            const double V = g.y[ix.j] * P.vfac;
+            const double v0n = sqrt(norm2(V * g.mu[ix.l], V * g.smu[ix.l]));
+            const double ratio = sqrt(n2[i]) / v0n;
+            fused_finish_ix(g, qa, lacc, bst, ix, ratio,
+                            TrajStat{(int)c.x, (int)c.y, (int)(w >> 48), N64 ? (int)n64[i] : 0});
+        }
+    }
+
+    // Called by every lane of the wavefront: the lanes with `fin` set put
+    // their trajectory t in the ring (after a flush if it would overflow);
+    // nfin, the ring's fill, is wave-uniform.  Returns whether this lane's
+    // trajectory went in.
+    __device__ __forceinline__ bool put(bool fin, unsigned &nfin, long long t, int status, int acc, int rej, int f64,
+                                        double speed2, const TrajParams &P, const GridPtrs &g, const QuadAcc &qa,
+                                        unsigned long long *lacc, BlockStats &bst) const
+    {
+        const unsigned long long fm = __ballot(fin);
+        if (fm == 0ull) return false;
+        const unsigned nf = (unsigned)__popcll(fm);
+        if (nfin + nf > (unsigned)SLOTS) {
+            flush(nfin, P, g, qa, lacc, bst);
+            nfin = 0;
+        }
+        if (fin) {
+            const unsigned slot =
+                nfin + __builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
+            n2[slot] = speed2;
+            tw[slot] = t | ((long long)status << 48);
+            st[slot] = make_uint2((unsigned)acc, (unsigned)rej);
+            if constexpr (N64) n64[slot] = (unsigned)f64;
+        }
+        nfin += nf;
+        return fin;
+    }
+};
+
 // After the workgroup's last trajectory (all threads, after a barrier).
 __device__ __forceinline__ void block_stats_flush(const BlockStats &b, unsigned long long *stats)
 {

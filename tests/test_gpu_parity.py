@@ -333,15 +333,17 @@ def test_queue_order_does_not_change_results(ctx, block):
         ctx.set_option("block_threads", 0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 @pytest.mark.parametrize("block", [512, 1024])
-def test_fused_quadrature_from_finish_rings(ctx, block):
+def test_fused_quadrature_from_finish_rings(ctx, block, prec):
     """The fused quadrature (finished trajectories wait in per-wavefront LDS
     rings of 64 and are summed a ring at a time) against the reduction of
     stored ratios: the same bits and the same step statistics.  100650
     trajectories on 8 or 16 wavefronts a workgroup: many full rings, and a
-    partial one per wavefront at the end."""
-    req = W.shrink(W.plain_scale(4), 25, 66, 61)
-    say(f"fused vs stored ratios, block {block}, n_traj={req.n_traj}")
+    partial one per wavefront at the end.  FP32C at 1024 threads is the build
+    that re-reads the request's parameters at each use."""
+    req = W.shrink(W.plain_scale(4), 25, 66, 61).with_(precision=prec)
+    say(f"{prec} fused vs stored ratios, block {block}, n_traj={req.n_traj}")
     ctx.set_option("block_threads", block)
     try:
         prof, _, st = gpu_ratios(ctx, req)
@@ -352,7 +354,7 @@ def test_fused_quadrature_from_finish_rings(ctx, block):
     finally:
         ctx.set_option("block_threads", 0)
     assert np.array_equal(out.cpu().numpy(), prof)
-    for key in ("accepted_steps", "rejected_steps", "n_failed", "free_exits", "max_steps_one_traj"):
+    for key in ("accepted_steps", "rejected_steps", "n_failed", "free_exits", "max_steps_one_traj", "fp64_steps"):
         assert fst[key] == st[key], key
 
 
