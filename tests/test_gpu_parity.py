@@ -359,6 +359,34 @@ def test_fused_quadrature_from_finish_rings(ctx, block, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_fused_quadrature_with_culled_relics(ctx, O, prec):
+    """As above with App. B culls: radii from 0.3 to 12 compensation radii, so
+    that many relics never reach the halo and are summed at their claim without
+    a step (ratio exactly 1), beside the ring's finishers.  Fused and
+    stored-ratio profiles and statistics are the same bits."""
+    base = W.shrink(W.plain_scale(0), 25, 66, 61)
+    R, _ = O.halo_radii(base, 0.0)
+    req = base.with_(r_kpc=R * np.geomspace(0.3, 12.0, 25), precision=prec)
+    say(f"{prec} fused vs stored ratios with culls, n_traj={req.n_traj}")
+    ctx.set_option("block_threads", 1024)
+    try:
+        prof, ratio, st = gpu_ratios(ctx, req)
+        acc, rej, _ = ctx.trajectory_stats(req.n_traj)
+        out = torch.empty(req.n_r, dtype=torch.float64, device="cuda")
+        ctx.solve_async(req, out)
+        fst, _ = ctx.last_stats()
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option("block_threads", 0)
+    culled = (acc + rej) == 0
+    print(f"culled {culled.sum()} of {req.n_traj}", flush=True)
+    assert culled.sum() > req.n_traj // 10 and np.all(ratio[culled] == 1.0)
+    assert np.array_equal(out.cpu().numpy(), prof)
+    for key in ("accepted_steps", "rejected_steps", "n_failed", "free_exits", "max_steps_one_traj", "fp64_steps"):
+        assert fst[key] == st[key], key
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_workgroup_cap_does_not_change_results(ctx, prec):
     """Capping a launch's workgroups (so that solves on several streams run side
     by side) changes only which lanes take which trajectories: identical ratios.
