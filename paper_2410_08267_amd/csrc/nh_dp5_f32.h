@@ -31,20 +31,28 @@ constexpr float e6 = (float)(11.0 / 84.0 - 187.0 / 2100.0);
 constexpr float e7 = (float)(-1.0 / 40.0);
 }  // namespace dp32
 
-// I(q) in FP32, branch-free: for q < sqrt(2) - 1 the positive-term form
-// 2 s^2/(1+s) + 2 (s^3/3 + ... + s^9/9), s = q/(2+q); above it
-// ln(1+q) - q/(1+q) with the hardware log2 (mild cancellation there).
+// I(q) in FP32, branch-free, in the FP64 kernels' form (nfw_I): 1+q = m 2^e
+// with e the exponent of (1+q) sqrt(2), s = (m-1)/(m+1) from q - (2^e - 1)
+// and (1+q) + 2^e, and
+//   I = e ln2 + (1 - 2^e)/(1+q) + s^2 (1 + 1/m) + 2 (s^3/3 + ... + s^9/9),
+// one reciprocal for both divisions.  At e = 0 the first two terms vanish
+// (a few ulp of I for any small q); just above q = sqrt(2) - 1 e ln2 and
+// (1 - 2^e)/(1+q) cancel to a twenty-fifth of their size (~1e-6 of I).
 __device__ __forceinline__ float nfw_I32(float q)
 {
-    const float s = q * __builtin_amdgcn_rcpf(2.0f + q);
+    const float w0 = 1.0f + q;
+    const int e = __builtin_amdgcn_frexp_expf(w0 * 1.41421356f) - 1;
+    const float p2 = __builtin_amdgcn_ldexpf(1.0f, e);
+    const float N = q - (p2 - 1.0f), D = w0 + p2;
+    const float rp = __builtin_amdgcn_rcpf(D * w0);
+    const float s = N * (w0 * rp);
+    const float iw = D * rp;
     const float s2 = s * s;
-    float p = fmaf(1.0f / 9.0f, s2, 1.0f / 7.0f);
-    p = fmaf(p, s2, 1.0f / 5.0f);
-    p = fmaf(p, s2, 1.0f / 3.0f);
-    const float small = 2.0f * s2 * __builtin_amdgcn_rcpf(1.0f + s) + 2.0f * s * s2 * p;
-    const float opq = 1.0f + q;
-    const float big = fmaf(__builtin_amdgcn_logf(opq), 0.69314718056f, -q * __builtin_amdgcn_rcpf(opq));
-    return q < 0.41421356f ? small : big;
+    float p = fmaf(s2, 2.0f / 9.0f, 2.0f / 7.0f);
+    p = fmaf(s2, p, 2.0f / 5.0f);
+    p = fmaf(s2, p, 2.0f / 3.0f);
+    const float small = fmaf(s2, fmaf(p2, iw, 1.0f), s * s2 * p);
+    return fmaf((float)e, 0.693147182f, fmaf(-p2, iw, iw)) + small;
 }
 
 __device__ __forceinline__ void rhs32(const float c[NCOL], float R, float x, float y, float vx,
